@@ -1,0 +1,160 @@
+/*
+ * spect.h - C ABI of the MI355X (gfx950) SPECT projector library.
+ *
+ * The library computes the parallel-hole SPECT system matrix of the paper
+ * (Section 2.1.1, Eq. 1)
+ *
+ *     H = sum_n v_n (x) ( T_fov P_x T_cdr T_att T_trans T_rot )
+ *
+ * its transpose H^T (forward projection FP and back projection BP, same
+ * section), the subset normalisation H_m^T 1 ("compute_normalization_factor",
+ * Section 2.2) and one OSEM subiteration: the preconditioned gradient ascent
+ * step of Eq. 5 with the Poisson log-likelihood gradient and the OSEM
+ * preconditioner of Table 1.
+ *
+ * Discretisation (the paper names the operations but not their sampling):
+ *   T_rot   bilinear interpolation in each axial slice about the grid centre
+ *           c = (N-1)/2; rotated sample (i', j') sits at
+ *           X = c + cos(t)(i'-c) - sin(t)(j'-c), Y = c + sin(t)(i'-c) + cos(t)(j'-c);
+ *           zero outside the grid.  cos/sin are evaluated in double precision
+ *           and magnitudes below 1e-15 are set to 0.
+ *   T_trans identity (rotation axis on the grid centre).
+ *   T_att   exp(-tau), tau(i') = dx (mu(i')/2 + sum over i'' > i' of mu(i''))
+ *           along the rotated depth axis i'; the detector lies beyond i' = N-1.
+ *   T_cdr   at depth i': Gaussian of sigma = psf_a d + psf_b (cm), with
+ *           d = max(0, R_n - (i'-c) dx), sampled at integer pixel offsets,
+ *           truncated at K = ceil(psf_nsigma sigma/dx - 1e-9), normalised to unit
+ *           sum, applied along the detector bin axis and the axial axis with
+ *           zero padding.
+ *   P_x     plain sum over i'.   T_fov  all ones.
+ *
+ * Layouts (all device arrays are float32, C order, last index fastest):
+ *   object       f[i][j][k]  shape (N, N, Nz): i = x, j = y, k = z (axial)
+ *   projections  p[n][r][k]  shape (A, N, Nz): n = angle, r = detector bin
+ * z is the fastest axis because the rotation acts in the x-y plane: every
+ * bilinear corner is then a contiguous run of axial voxels.
+ *
+ * Conventions for every call:
+ *   - Device pointers are caller-owned, must be 4-byte aligned and must not
+ *     alias one another unless stated; 16-byte alignment with Nz % 4 == 0
+ *     enables vector loads.  The library never frees caller memory.
+ *   - Host-side validation runs before any launch; on error nothing is
+ *     launched and the call returns a negative status with a message for
+ *     spect_last_error().
+ *   - Calls are asynchronous on the given stream (a hipStream_t; NULL is the
+ *     null stream).  Results are valid once the stream reaches them.
+ *   - angle_idx is a host array of angle indices in [0, n_angles); NULL means
+ *     all angles in order (n_idx is then ignored).
+ *   - The workspace is device memory of at least spect_workspace_size() bytes
+ *     for the same op and angle count, 256-byte aligned; it holds nothing
+ *     between calls.  Two calls in flight at once need separate workspaces.
+ */
+#ifndef SPECT_H
+#define SPECT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define SPECT_OK 0
+#define SPECT_EINVAL (-1)      /* invalid argument (nothing launched) */
+#define SPECT_ENOMEM (-2)      /* device allocation failed */
+#define SPECT_EHIP (-3)        /* HIP runtime or launch error */
+#define SPECT_EUNSUPPORTED (-4) /* valid but outside this build's limits */
+
+/* Workspace queries. */
+#define SPECT_OP_FWD 0
+#define SPECT_OP_BACK 1
+#define SPECT_OP_SENS 2
+#define SPECT_OP_OSEM 3
+
+/* Limits of this build. */
+#define SPECT_MAX_N 256        /* transverse size N */
+#define SPECT_MAX_K 32         /* collimator blur radius in pixels */
+
+typedef struct spect_plan spect_plan;
+
+/* Acquisition geometry (Section 2.1.1: projection space V of 2D images, one
+ * per angle; object space U of voxelised activity). */
+typedef struct {
+    int32_t n;                /* transverse grid size N (object N x N x nz, N bins) */
+    int32_t nz;               /* axial size Nz (object slices = detector rows) */
+    int32_t n_angles;         /* A */
+    int32_t flags;            /* reserved, must be 0 */
+    double voxel_cm;          /* isotropic voxel and detector pixel size dx > 0 */
+    const double *angles_deg; /* host [n_angles]; NULL = n * 360 / A */
+    const double *radius_cm;  /* host [n_angles] detector distance R_n >= 0;
+                                 NULL = N dx / 2 (detector touching the grid) */
+    double psf_a;             /* sigma(d) = psf_a d + psf_b in cm; both >= 0; */
+    double psf_b;             /*   psf_a = psf_b = 0 disables T_cdr */
+    double psf_nsigma;        /* truncation in sigmas; <= 0 means 4 */
+} spect_geometry;
+
+/* Validate the geometry and precompute per-angle trigonometry and per-depth
+ * blur kernels (Eq. 1) on the current HIP device.  *out receives a plan that
+ * owns a small device table; the plan is immutable and may be used from
+ * several streams at once.  The angle and radius arrays are copied.
+ * Errors: SPECT_EINVAL (NULL pointers, sizes < 1, flags != 0, non-finite or
+ * out-of-range values), SPECT_EUNSUPPORTED (N > SPECT_MAX_N, blur radius >
+ * SPECT_MAX_K, index range beyond 32 bits), SPECT_ENOMEM, SPECT_EHIP. */
+int spect_plan_create(const spect_geometry *geom, spect_plan **out);
+
+/* Free a plan (NULL is accepted).  The caller must make sure no work that
+ * uses the plan is still queued. */
+int spect_plan_destroy(spect_plan *plan);
+
+/* Workspace bytes needed by op (SPECT_OP_*) over n_idx angles; for
+ * SPECT_OP_OSEM n_idx is the number of subsets M.  with_mu != 0 when an
+ * attenuation map will be passed. */
+int spect_workspace_size(const spect_plan *plan, int op, int32_t n_idx, int with_mu,
+                         size_t *bytes);
+
+/* Forward projection (FP, Section 2.1.1; Eq. 1): for each listed angle n,
+ * proj[n] = P_x T_cdr T_att T_rot f.  f: device (N, N, Nz); mu: device
+ * (N, N, Nz) attenuation map in cm^-1, or NULL for no attenuation; proj:
+ * device (A, N, Nz), only the listed rows are written.  f and proj must not
+ * overlap. */
+int spect_fwd(const spect_plan *plan, const float *f, const float *mu, float *proj,
+              const int32_t *angle_idx, int32_t n_idx, void *ws, size_t ws_bytes,
+              void *stream);
+
+/* Back projection (BP, Section 2.1.1): f_out = sum over listed n of
+ * H_n^T proj[n] (accumulate == 0), or f_out += that sum (accumulate != 0).
+ * proj: device (A, N, Nz), only listed rows are read; f_out: device
+ * (N, N, Nz). */
+int spect_back(const spect_plan *plan, const float *proj, const float *mu, float *f_out,
+               const int32_t *angle_idx, int32_t n_idx, int accumulate, void *ws,
+               size_t ws_bytes, void *stream);
+
+/* Subset normalisation H_S^T 1 (Section 2.2 "compute_normalization_factor";
+ * the OSEM denominator of Table 1) for the listed angles S; sens: device
+ * (N, N, Nz), overwritten. */
+int spect_sensitivity(const spect_plan *plan, const float *mu, float *sens,
+                      const int32_t *angle_idx, int32_t n_idx, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/* One OSEM subiteration (Eq. 5 with Table 1: PoissonLogLikelihood gradient
+ * H^T(g/(Hf+s)) - H^T 1, OSEM preconditioner f / (H_m^T 1), no prior) on the
+ * interleaved subset S_m = { n : n mod n_subsets == m }:
+ *     gbar = H_m f + s_m;  q = g / gbar where gbar > 0, else 0;
+ *     f <- f * (H_m^T q) / sens_m where sens_m > 0, else f unchanged.
+ * f: device (N, N, Nz), updated in place; g: device (A, N, Nz) measured data;
+ * s_add: device (A, N, Nz) additive term or NULL (zero); sens_m: device
+ * (N, N, Nz) = H_m^T 1 from spect_sensitivity with the same subset; mu as in
+ * spect_fwd.  0 <= m < n_subsets <= n_angles. */
+int osem_subset_step(const spect_plan *plan, float *f, const float *mu, const float *g,
+                     const float *s_add, const float *sens_m, int32_t m, int32_t n_subsets,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char *spect_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPECT_H */

@@ -1,0 +1,13 @@
+"""MI355X-native SPECT OSEM hot path (paper: arXiv 2309.01977, Section 2.1).
+
+The parallel-hole SPECT system matrix pair (Eq. 1 and its transpose) and the
+OSEM subset update (Eq. 5, Table 1) run as hand-written gfx950 HIP kernels
+behind the C ABI in include/spect.h; this package is the thin Python binding
+(torch supplies device memory and streams) plus the OSEM driver loop.
+"""
+from ._binding import (EXPORTS, LIB_PATH, OP_BACK, OP_FWD, OP_OSEM, OP_SENS, Plan, SpectError,
+                       load_library, subset_angles)
+from .recon import osem, sensitivities
+
+__all__ = ["Plan", "SpectError", "load_library", "osem", "sensitivities", "subset_angles",
+           "EXPORTS", "LIB_PATH", "OP_FWD", "OP_BACK", "OP_SENS", "OP_OSEM"]

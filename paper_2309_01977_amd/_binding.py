@@ -1,0 +1,218 @@
+"""ctypes binding of the HIP C ABI (include/spect.h).
+
+Argument marshalling only: torch tensors supply device memory and the
+current HIP stream; every step of the projector and of the OSEM update runs
+in the library's kernels.  There is no CPU fallback: without the built
+library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libspect_hip.so")
+
+SPECT_OK = 0
+SPECT_EINVAL = -1
+SPECT_ENOMEM = -2
+SPECT_EHIP = -3
+SPECT_EUNSUPPORTED = -4
+OP_FWD, OP_BACK, OP_SENS, OP_OSEM = 0, 1, 2, 3
+
+EXPORTS = ("spect_plan_create", "spect_plan_destroy", "spect_workspace_size", "spect_fwd",
+           "spect_back", "spect_sensitivity", "osem_subset_step", "spect_last_error")
+
+
+class SpectError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"spect error {code}: {msg}")
+        self.code = code
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nz", ctypes.c_int32), ("n_angles", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("voxel_cm", ctypes.c_double),
+                ("angles_deg", ctypes.POINTER(ctypes.c_double)),
+                ("radius_cm", ctypes.POINTER(ctypes.c_double)),
+                ("psf_a", ctypes.c_double), ("psf_b", ctypes.c_double),
+                ("psf_nsigma", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None):
+    """Load the built library (no fallback: raises if it is missing)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"HIP library not built: {p} (run python -m paper_2309_01977_amd.build)")
+    lib = ctypes.CDLL(p)
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.spect_plan_create.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(vp)]
+    lib.spect_plan_destroy.argtypes = [vp]
+    lib.spect_workspace_size.argtypes = [vp, ctypes.c_int, i32, ctypes.c_int, ctypes.POINTER(sz)]
+    lib.spect_fwd.argtypes = [vp, vp, vp, vp, i32p, i32, vp, sz, vp]
+    lib.spect_back.argtypes = [vp, vp, vp, vp, i32p, i32, ctypes.c_int, vp, sz, vp]
+    lib.spect_sensitivity.argtypes = [vp, vp, vp, i32p, i32, vp, sz, vp]
+    lib.osem_subset_step.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, vp, sz, vp]
+    lib.spect_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS[:-1]:
+        getattr(lib, name).restype = ctypes.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != SPECT_OK:
+        raise SpectError(code, load_library().spect_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor], shape: Tuple[int, ...], name: str):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must be a contiguous float32 tensor of shape {shape}, "
+                         f"got {tuple(t.shape)} {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """Immutable projector plan for one acquisition geometry (spect_plan)."""
+
+    def __init__(self, n: int, nz: int, n_angles: int, voxel_cm: float, psf_a: float = 0.0,
+                 psf_b: float = 0.0, psf_nsigma: float = 4.0,
+                 angles_deg: Optional[Sequence[float]] = None,
+                 radius_cm: Optional[Sequence[float]] = None):
+        lib = load_library()
+        self.n, self.nz, self.n_angles = int(n), int(nz), int(n_angles)
+        self.voxel_cm = float(voxel_cm)
+        self._ang = None if angles_deg is None else (ctypes.c_double * n_angles)(*angles_deg)
+        self._rad = None if radius_cm is None else (ctypes.c_double * n_angles)(*radius_cm)
+        g = Geometry(self.n, self.nz, self.n_angles, 0, self.voxel_cm,
+                     ctypes.cast(self._ang, ctypes.POINTER(ctypes.c_double)) if self._ang else None,
+                     ctypes.cast(self._rad, ctypes.POINTER(ctypes.c_double)) if self._rad else None,
+                     float(psf_a), float(psf_b), float(psf_nsigma))
+        h = ctypes.c_void_p()
+        _check(lib.spect_plan_create(ctypes.byref(g), ctypes.byref(h)))
+        self._h = h
+        self._ws: Dict[Tuple[int, int, int], torch.Tensor] = {}
+
+    @classmethod
+    def for_workload(cls, w) -> "Plan":
+        return cls(w.n, w.nz, w.n_angles, w.voxel_cm, w.psf_a, w.psf_b, w.psf_nsigma)
+
+    @property
+    def object_shape(self):
+        return (self.n, self.n, self.nz)
+
+    @property
+    def proj_shape(self):
+        return (self.n_angles, self.n, self.nz)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            torch.cuda.synchronize()
+            load_library().spect_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                load_library().spect_plan_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def workspace_size(self, op: int, n_idx: int, with_mu: bool) -> int:
+        b = ctypes.c_size_t()
+        _check(load_library().spect_workspace_size(self._h, op, int(n_idx), int(bool(with_mu)),
+                                                   ctypes.byref(b)))
+        return b.value
+
+    def workspace(self, op: int, n_idx: int, with_mu: bool) -> torch.Tensor:
+        key = (op, int(n_idx), int(bool(with_mu)))
+        ws = self._ws.get(key)
+        if ws is None:
+            nbytes = max(self.workspace_size(op, n_idx, with_mu), 256)
+            ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            self._ws[key] = ws
+        return ws
+
+    def _idx(self, idx):
+        if idx is None:
+            return None, self.n_angles
+        arr = (ctypes.c_int32 * len(idx))(*[int(i) for i in idx])
+        return arr, len(idx)
+
+    def forward(self, f: torch.Tensor, mu: Optional[torch.Tensor] = None, idx=None,
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Rows idx of H f (spect_fwd); other rows of ``out`` are untouched."""
+        if out is None:
+            out = torch.zeros(self.proj_shape, dtype=torch.float32, device=f.device)
+        arr, n = self._idx(idx)
+        ws = self.workspace(OP_FWD, max(n, 1), mu is not None)
+        _check(load_library().spect_fwd(self._h, _ptr(f, self.object_shape, "f"),
+                                         _ptr(mu, self.object_shape, "mu"),
+                                         _ptr(out, self.proj_shape, "proj"), arr, n,
+                                         ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+        return out
+
+    def back(self, proj: torch.Tensor, mu: Optional[torch.Tensor] = None, idx=None,
+             out: Optional[torch.Tensor] = None, accumulate: bool = False) -> torch.Tensor:
+        """sum over n in idx of H_n^T proj[n] (spect_back)."""
+        if out is None:
+            out = torch.empty(self.object_shape, dtype=torch.float32, device=proj.device)
+            accumulate = False
+        arr, n = self._idx(idx)
+        ws = self.workspace(OP_BACK, max(n, 1), mu is not None)
+        _check(load_library().spect_back(self._h, _ptr(proj, self.proj_shape, "proj"),
+                                          _ptr(mu, self.object_shape, "mu"),
+                                          _ptr(out, self.object_shape, "f_out"), arr, n,
+                                          int(bool(accumulate)), ctypes.c_void_p(ws.data_ptr()),
+                                          ws.numel(), _stream()))
+        return out
+
+    def sensitivity(self, mu: Optional[torch.Tensor] = None, idx=None,
+                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """H_idx^T 1 (spect_sensitivity)."""
+        if out is None:
+            out = torch.empty(self.object_shape, dtype=torch.float32, device="cuda")
+        arr, n = self._idx(idx)
+        ws = self.workspace(OP_SENS, max(n, 1), mu is not None)
+        _check(load_library().spect_sensitivity(self._h, _ptr(mu, self.object_shape, "mu"),
+                                                 _ptr(out, self.object_shape, "sens"), arr, n,
+                                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                                 _stream()))
+        return out
+
+    def osem_subset_step(self, f: torch.Tensor, g: torch.Tensor, sens_m: torch.Tensor, m: int,
+                         n_subsets: int, mu: Optional[torch.Tensor] = None,
+                         s_add: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """One OSEM subiteration on subset m, f updated in place."""
+        ws = self.workspace(OP_OSEM, n_subsets, mu is not None)
+        _check(load_library().osem_subset_step(
+            self._h, _ptr(f, self.object_shape, "f"), _ptr(mu, self.object_shape, "mu"),
+            _ptr(g, self.proj_shape, "g"), _ptr(s_add, self.proj_shape, "s_add"),
+            _ptr(sens_m, self.object_shape, "sens_m"), int(m), int(n_subsets),
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+        return f
+
+
+def subset_angles(n_angles: int, n_subsets: int, m: int):
+    """Interleaved subset m = {n : n mod M = m}."""
+    return list(range(m, n_angles, n_subsets))

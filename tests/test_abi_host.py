@@ -1,0 +1,90 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+that include/spect.h declares, and rejects invalid arguments on the host
+before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2309_01977_amd as S
+from paper_2309_01977_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "spect.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_header_declares_the_abi():
+    assert header_functions() == sorted(S.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = S.load_library()
+    for name in header_functions():
+        assert hasattr(lib, name), name
+    out = os.popen("nm -D --defined-only %s" % S.LIB_PATH).read()
+    for name in header_functions():
+        assert re.search(r" T %s$" % name, out, flags=re.M), name
+
+
+def _geom(**kw):
+    d = dict(n=16, nz=8, n_angles=6, flags=0, voxel_cm=0.5, angles_deg=None, radius_cm=None,
+             psf_a=0.03, psf_b=0.1, psf_nsigma=4.0)
+    d.update(kw)
+    return B.Geometry(**d)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=0), B.SPECT_EINVAL), (dict(nz=0), B.SPECT_EINVAL), (dict(n_angles=0), B.SPECT_EINVAL),
+    (dict(flags=1), B.SPECT_EINVAL), (dict(voxel_cm=0.0), B.SPECT_EINVAL),
+    (dict(voxel_cm=float("nan")), B.SPECT_EINVAL), (dict(psf_a=-1.0), B.SPECT_EINVAL),
+    (dict(psf_b=float("inf")), B.SPECT_EINVAL), (dict(n=257), B.SPECT_EUNSUPPORTED),
+    (dict(psf_a=1.0), B.SPECT_EUNSUPPORTED),
+])
+def test_plan_create_rejects_invalid_geometry(kw, code):
+    lib = S.load_library()
+    h = ctypes.c_void_p(123)
+    g = _geom(**kw)
+    assert lib.spect_plan_create(ctypes.byref(g), ctypes.byref(h)) == code
+    assert h.value is None
+    assert lib.spect_last_error().decode() != ""
+
+
+def test_plan_create_rejects_bad_angle_and_radius_arrays():
+    lib = S.load_library()
+    h = ctypes.c_void_p()
+    ang = (ctypes.c_double * 6)(0, 1, 2, float("nan"), 4, 5)
+    g = _geom(angles_deg=ctypes.cast(ang, ctypes.POINTER(ctypes.c_double)))
+    assert lib.spect_plan_create(ctypes.byref(g), ctypes.byref(h)) == B.SPECT_EINVAL
+    assert "angles_deg[3]" in lib.spect_last_error().decode()
+    rad = (ctypes.c_double * 6)(5, 5, -1, 5, 5, 5)
+    g = _geom(radius_cm=ctypes.cast(rad, ctypes.POINTER(ctypes.c_double)))
+    assert lib.spect_plan_create(ctypes.byref(g), ctypes.byref(h)) == B.SPECT_EINVAL
+    assert "radius_cm[2]" in lib.spect_last_error().decode()
+
+
+def test_null_arguments_are_rejected_before_any_device_call():
+    lib = S.load_library()
+    h = ctypes.c_void_p()
+    assert lib.spect_plan_create(None, ctypes.byref(h)) == B.SPECT_EINVAL
+    g = _geom()
+    assert lib.spect_plan_create(ctypes.byref(g), None) == B.SPECT_EINVAL
+    sz = ctypes.c_size_t()
+    assert lib.spect_workspace_size(None, 0, 1, 0, ctypes.byref(sz)) == B.SPECT_EINVAL
+    assert lib.spect_fwd(None, None, None, None, None, 0, None, 0, None) == B.SPECT_EINVAL
+    assert lib.spect_back(None, None, None, None, None, 0, 0, None, 0, None) == B.SPECT_EINVAL
+    assert lib.spect_sensitivity(None, None, None, None, 0, None, 0, None) == B.SPECT_EINVAL
+    assert lib.osem_subset_step(None, None, None, None, None, None, 0, 1, None, 0, None) == B.SPECT_EINVAL
+    assert "plan is NULL" in lib.spect_last_error().decode()
+    assert lib.spect_plan_destroy(None) == B.SPECT_OK
+    assert lib.spect_last_error().decode() == ""
+
+
+def test_binding_has_no_cpu_fallback(tmp_path):
+    with pytest.raises(RuntimeError, match="not built"):
+        B.load_library(str(tmp_path / "missing.so"))

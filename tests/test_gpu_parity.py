@@ -1,0 +1,266 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bar (from the workload statement): forward projections within 1e-5 relative
+L2 per projection, back projections within 1e-5 relative L2 over the volume,
+the FP32 adjoint identity within 1e-5, OSEM within 1e-4 relative L2 after the
+full run.  Both sides read the same FP32 inputs; the oracle promotes them to
+FP64.  Data for the OSEM cases (Poisson counts of the phantom's expected
+projection) are made by the oracle.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+import paper_2309_01977_amd as S
+from paper_2309_01977_amd import phantoms as P
+
+pytestmark = pytest.mark.gpu
+
+FWD_TOL = 1e-5
+BACK_TOL = 1e-5
+OSEM_TOL = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    O.build(force=False)
+    S.load_library()
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a)
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def both(n, nz, A, voxel=0.48, psf=(0.03, 0.1), angles=None, radius=None):
+    og = O.Geometry(n, nz, A, voxel, psf[0], psf[1], 4.0, angles, radius)
+    plan = S.Plan(n, nz, A, voxel, psf[0], psf[1], 4.0, angles, radius)
+    return og, plan
+
+
+def check_forward(og, plan, f, mu, idx=None, tol=FWD_TOL, label=""):
+    ref = O.forward(og, f.astype(np.float64), None if mu is None else mu.astype(np.float64), idx)
+    out = plan.forward(dev(f), None if mu is None else dev(mu), idx)
+    got = host(out)
+    rows = range(og.n_angles) if idx is None else idx
+    worst = 0.0
+    for n in rows:
+        if np.linalg.norm(ref[n]) == 0:
+            assert np.abs(got[n]).max() <= 1e-30, (label, n)
+            continue
+        e = rel_l2(got[n], ref[n])
+        worst = max(worst, e)
+        assert e <= tol, (label, n, e)
+    say(f"  forward {label}: worst per-projection rel L2 {worst:.2e}")
+    return got, ref
+
+
+# ------------------------------------------------------- operator parity --
+
+SMALL = [
+    # n, nz, A, mu, psf, random angles
+    (16, 8, 6, True, (0.03, 0.1), True),
+    (37, 20, 5, True, (0.03, 0.1), True),     # ragged N, slab tail (Nz % 16 != 0)
+    (24, 6, 4, True, (0.03, 0.1), True),      # Nz % 4 != 0: scalar loads
+    (33, 17, 7, False, (0.03, 0.1), True),
+    (20, 12, 8, True, (0.0, 0.0), False),     # no blur
+    (1, 3, 2, False, (0.0, 0.0), False),      # one voxel column
+    (48, 40, 3, True, (0.06, 0.2), True),     # wider blur class
+    (64, 64, 10, True, (0.03, 0.1), False),
+]
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[f"n{c[0]}_nz{c[1]}_a{c[2]}_mu{int(c[3])}" for c in SMALL])
+def test_forward_and_back_parity_small(case):
+    n, nz, A, with_mu, psf, rand_ang = case
+    say(f"case n={n} nz={nz} A={A} mu={with_mu} psf={psf}")
+    r = np.random.default_rng(100 + n + nz + A)
+    ang = list(r.uniform(0, 360, A)) if rand_ang else None
+    og, plan = both(n, nz, A, psf=psf, angles=ang)
+    f = P.random_object(og.object_shape, r)
+    mu = P.random_mu(og.object_shape, r, 0.2) if with_mu else None
+    check_forward(og, plan, f, mu, label="all angles")
+    idx = [A - 1, 0] if A > 1 else [0]
+    check_forward(og, plan, f, mu, idx=idx, label="subset")
+    y = P.random_object(og.proj_shape, r)
+    ref = O.back(og, y.astype(np.float64), None if mu is None else mu.astype(np.float64))
+    got = host(plan.back(dev(y), None if mu is None else dev(mu)))
+    e = rel_l2(got, ref)
+    say(f"  back rel L2 {e:.2e}")
+    assert e <= BACK_TOL
+    ref_s = O.back(og, y.astype(np.float64), None if mu is None else mu.astype(np.float64), idx)
+    got_s = host(plan.back(dev(y), None if mu is None else dev(mu), idx))
+    assert rel_l2(got_s, ref_s) <= BACK_TOL
+
+
+def test_chunked_launch_matches_single_chunk():
+    """A one-angle launch splits depth into chunks with attenuation offsets
+    from the pre-pass; it must agree with the all-angle launch."""
+    w = P.C2
+    r = np.random.default_rng(5)
+    plan = S.Plan.for_workload(w)
+    f = dev(P.random_object(w.object_shape, r))
+    mu = dev(P.random_mu(w.object_shape, r, 0.2))
+    full = host(plan.forward(f, mu))
+    for n in (0, 37, 119):
+        one = host(plan.forward(f, mu, [n]))
+        e = rel_l2(one[n], full[n])
+        say(f"  angle {n}: chunked vs single-chunk rel L2 {e:.2e}")
+        assert e <= 2e-6
+    b_full = host(plan.back(dev(full), mu))
+    b_one = sum(host(plan.back(dev(full), mu, [n])) for n in range(0, 120, 40))
+    b_three = host(plan.back(dev(full), mu, list(range(0, 120, 40))))
+    assert rel_l2(b_one, b_three) <= 2e-6
+    assert np.isfinite(b_full).all()
+
+
+@pytest.mark.parametrize("which", ["C1", "C2"])
+def test_adjoint_identity_fp32(which):
+    """<H x, y> = <x, H^T y> for the GPU pair at the full workload grids."""
+    w = P.C1 if which == "C1" else P.C2
+    r = np.random.default_rng(11)
+    plan = S.Plan.for_workload(w)
+    mu = dev(P.random_mu(w.object_shape, r, 0.2)) if w.with_mu else None
+    for signed in (False, True):
+        x = P.random_object(w.object_shape, r, signed)
+        y = P.random_object(w.proj_shape, r, signed)
+        hx = host(plan.forward(dev(x), mu))
+        hty = host(plan.back(dev(y), mu))
+        lhs = float(np.vdot(hx, y.astype(np.float64)))
+        rhs = float(np.vdot(x.astype(np.float64), hty))
+        scale = float(np.abs(hx).ravel() @ np.abs(y).ravel().astype(np.float64))
+        e = abs(lhs - rhs) / scale
+        say(f"  {which} signed={signed}: |<Hx,y> - <x,H^T y>| / scale = {e:.2e}")
+        assert e <= 1e-5
+
+
+def test_sensitivity_parity():
+    w = P.C2
+    r = np.random.default_rng(12)
+    og, plan = both(w.n, w.nz, w.n_angles)
+    mu = P.random_mu(w.object_shape, r, 0.2)
+    idx = list(range(3, 120, 8))
+    ref = O.back(og, np.ones(og.proj_shape), mu.astype(np.float64), idx)
+    got = host(plan.sensitivity(dev(mu), idx))
+    e = rel_l2(got, ref)
+    say(f"  sensitivity rel L2 {e:.2e}")
+    assert e <= BACK_TOL
+
+
+def test_deterministic_results():
+    """The gather-form back projection and the chunk reduction use a fixed
+    summation order: repeated calls give identical bits."""
+    w = P.C2
+    r = np.random.default_rng(13)
+    plan = S.Plan.for_workload(w)
+    f = dev(P.random_object(w.object_shape, r))
+    mu = dev(P.random_mu(w.object_shape, r, 0.2))
+    idx = list(range(1, 120, 8))
+    a = host(plan.forward(f, mu, idx))
+    b = host(plan.forward(f, mu, idx))
+    assert np.array_equal(a, b)
+    y = dev(a)
+    c = host(plan.back(y, mu, idx))
+    d = host(plan.back(y, mu, idx))
+    assert np.array_equal(c, d)
+
+
+def test_empty_and_accumulating_calls():
+    og, plan = both(16, 8, 4)
+    r = np.random.default_rng(14)
+    f = dev(P.random_object(og.object_shape, r))
+    out = torch.full(og.proj_shape, 7.0, device="cuda")
+    plan.forward(f, None, [], out=out)
+    assert torch.all(out == 7.0)
+    y = dev(P.random_object(og.proj_shape, r))
+    b = torch.full(og.object_shape, 3.0, device="cuda")
+    plan.back(y, None, [], out=b)
+    assert torch.all(b == 0.0)
+    base = plan.back(y, None, [0, 1]).clone()
+    acc = base.clone()
+    plan.back(y, None, [2, 3], out=acc, accumulate=True)
+    full = plan.back(y, None)
+    assert rel_l2(host(acc), host(full)) <= 1e-6
+
+
+# --------------------------------------------------------- workload data --
+
+_DATA = {}
+
+
+def workload_data(w):
+    if w.name not in _DATA:
+        say(f"  building {w.name} phantom and oracle data")
+        f_true, mu = P.make_phantom(w)
+        og = O.Geometry(w.n, w.nz, w.n_angles, w.voxel_cm, w.psf_a, w.psf_b, w.psf_nsigma)
+        gbar = O.forward(og, f_true.astype(np.float64), None if mu is None else mu.astype(np.float64))
+        _, noise = P.rngs(w.seed_index)
+        g = P.poisson_counts(gbar, w.total_counts, noise)
+        _DATA[w.name] = (og, f_true, mu, g)
+    return _DATA[w.name]
+
+
+@pytest.mark.parametrize("which", ["C1", "C2"])
+def test_workload_forward_parity(which):
+    w = P.C1 if which == "C1" else P.C2
+    og, f_true, mu, _ = workload_data(w)
+    plan = S.Plan.for_workload(w)
+    check_forward(og, plan, f_true, mu, label=f"{which} all angles")
+    check_forward(og, plan, f_true, mu, idx=list(range(0, w.n_angles, w.n_subsets)),
+                  label=f"{which} subset 0")
+
+
+def test_osem_step_conserves_counts_on_gpu():
+    """P10 on the GPU: sum(sens_m f') = sum of g over the subset where Hf > 0."""
+    w = P.C1
+    og, f_true, mu, g = workload_data(w)
+    plan = S.Plan.for_workload(w)
+    M = w.n_subsets
+    sens = S.sensitivities(plan, M, None)
+    f = torch.ones(w.object_shape, device="cuda")
+    gd = dev(g)
+    for m in range(M):
+        plan.osem_subset_step(f, gd, sens[m], m, M)
+        idx = list(range(m, w.n_angles, M))
+        lhs = float((sens[m].double() * f.double()).sum())
+        rhs = float(g[idx].astype(np.float64).sum())
+        assert abs(lhs - rhs) / rhs <= 1e-5, (m, lhs, rhs)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("which", ["C1", "C2"])
+def test_osem_full_run_parity(which):
+    """The whole reconstruction (sensitivities + I x M subiterations) against
+    the FP64 oracle's OSEM on the same data: relative L2 <= 1e-4."""
+    w = P.C1 if which == "C1" else P.C2
+    og, f_true, mu, g = workload_data(w)
+    plan = S.Plan.for_workload(w)
+    got = host(S.osem(plan, dev(g), w.n_iters, w.n_subsets, None if mu is None else dev(mu)))
+    say(f"  {which}: GPU OSEM done; running the oracle OSEM")
+    ref = O.osem(og, g.astype(np.float64), None if mu is None else mu.astype(np.float64),
+                 w.n_iters, w.n_subsets)
+    e = rel_l2(got, ref)
+    say(f"  {which}: OSEM rel L2 {e:.2e}")
+    assert e <= OSEM_TOL
