@@ -46,7 +46,6 @@ namespace {
 constexpr int SLAB = 16;   // axial rows per workgroup
 constexpr int ROWS = 8;    // axial rows per thread
 constexpr int MAXL = 128;  // angles per launch
-constexpr int GATHER_TILE = 16;
 
 struct AngleList {
     int n;
@@ -93,37 +92,59 @@ __device__ __forceinline__ Corners corners(float X, float Y, int N, int Nz)
     return c;
 }
 
-// Bilinear sample of ROWS axial values starting at row kb (rows >= Nz give 0).
-__device__ __forceinline__ void sample_rows(const float *__restrict__ vol, const Corners &c, int kb,
-                                            int Nz, bool vec, float (&v)[ROWS])
+// Raw corner values of ROWS axial rows starting at kb: v[corner][row] for the
+// corners (x0,y0), (x0+1,y0), (x0,y0+1), (x0+1,y0+1).  Every load is issued
+// unconditionally (rows past Nz read a clamped, valid address and are zeroed
+// when combined), so all of them are in flight together.  Vector path:
+// Nz % 4 == 0 and a 16-byte aligned volume.
+struct Raw {
+    float v[4][ROWS];
+};
+
+template <bool VEC>
+__device__ __forceinline__ void load_raw(const float *__restrict__ vol, const Corners &c, int kb, int Nz, Raw &r)
 {
-    if (vec) {
+    const int o[4] = {c.o00, c.o10, c.o01, c.o11};
+    if constexpr (VEC) {
 #pragma unroll
         for (int q = 0; q < ROWS / 4; ++q) {
-            const int k = kb + 4 * q;
-            if (k < Nz) {
-                const float4 a = *reinterpret_cast<const float4 *>(vol + c.o00 + k);
-                const float4 b = *reinterpret_cast<const float4 *>(vol + c.o10 + k);
-                const float4 d = *reinterpret_cast<const float4 *>(vol + c.o01 + k);
-                const float4 e = *reinterpret_cast<const float4 *>(vol + c.o11 + k);
-                v[4 * q + 0] = fmaf(c.w11, e.x, fmaf(c.w01, d.x, fmaf(c.w10, b.x, c.w00 * a.x)));
-                v[4 * q + 1] = fmaf(c.w11, e.y, fmaf(c.w01, d.y, fmaf(c.w10, b.y, c.w00 * a.y)));
-                v[4 * q + 2] = fmaf(c.w11, e.z, fmaf(c.w01, d.z, fmaf(c.w10, b.z, c.w00 * a.z)));
-                v[4 * q + 3] = fmaf(c.w11, e.w, fmaf(c.w01, d.w, fmaf(c.w10, b.w, c.w00 * a.w)));
-            } else {
-                v[4 * q + 0] = v[4 * q + 1] = v[4 * q + 2] = v[4 * q + 3] = 0.f;
+            const int k = min(kb + 4 * q, Nz - 4);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float4 t = *reinterpret_cast<const float4 *>(vol + o[j] + k);
+                r.v[j][4 * q + 0] = t.x;
+                r.v[j][4 * q + 1] = t.y;
+                r.v[j][4 * q + 2] = t.z;
+                r.v[j][4 * q + 3] = t.w;
             }
         }
     } else {
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-            const int k = kb + r;
-            v[r] = 0.f;
-            if (k < Nz)
-                v[r] = fmaf(c.w11, vol[c.o11 + k],
-                            fmaf(c.w01, vol[c.o01 + k], fmaf(c.w10, vol[c.o10 + k], c.w00 * vol[c.o00 + k])));
+        for (int rr = 0; rr < ROWS; ++rr) {
+            const int k = min(kb + rr, Nz - 1);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) r.v[j][rr] = vol[o[j] + k];
         }
     }
+}
+
+// Bilinear combination of raw corner values; rows >= Nz give 0.
+__device__ __forceinline__ void combine(const Raw &r, const Corners &c, int kb, int Nz, float (&v)[ROWS])
+{
+#pragma unroll
+    for (int rr = 0; rr < ROWS; ++rr) {
+        const float z = (kb + rr < Nz) ? 1.f : 0.f;
+        v[rr] = z * fmaf(c.w11, r.v[3][rr], fmaf(c.w01, r.v[2][rr], fmaf(c.w10, r.v[1][rr], c.w00 * r.v[0][rr])));
+    }
+}
+
+template <bool VEC>
+__device__ __forceinline__ void sample_rows(const float *__restrict__ vol, const Corners &c, int kb, int Nz,
+                                            float (&v)[ROWS])
+{
+    Raw r;
+    load_raw<VEC>(vol, c, kb, Nz, r);
+    combine(r, c, kb, Nz, v);
 }
 
 // Attenuation factors for one depth: exp(-dx (mu/2 + sum beyond)), then add
@@ -133,7 +154,7 @@ __device__ __forceinline__ void attenuate(const float (&m)[ROWS], float (&S)[ROW
 {
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
-        att[r] = exp2f(-scale * fmaf(0.5f, m[r], S[r]));
+        att[r] = __builtin_amdgcn_exp2f(-scale * fmaf(0.5f, m[r], S[r]));
         S[r] += m[r];
     }
 }
@@ -261,20 +282,24 @@ struct TauArgs {
     DevGeom g;
     AngleList L;
     const float *mu;
-    float *tau;      // [L][nchunk][N][Nz]: sum of mu samples at depths >= N - c*D
+    float *tau;      // [L][nchunk][N][Nz]: sum of mu samples over the depths of chunk c
     int nchunk, dchunk;
     int vec;
 };
 
-// One thread per (angle, bin, 8 axial rows): walk the ray from the detector
-// and record the running sum of attenuation samples at every chunk boundary.
+// One thread per (angle, chunk, bin, 8 axial rows): sum the attenuation
+// samples of the chunk's depths.  Chunk c covers depths
+// [N - (c+1) D, N - c D); chunk 0 touches the detector.  A chunk's starting
+// attenuation is the sum of the partial sums of the chunks nearer the
+// detector (the last chunk's own sum is never needed).
+template <bool VEC>
 __global__ __launch_bounds__(256) void tau_prepass(TauArgs a)
 {
     const int N = a.g.N, Nz = a.g.Nz;
     const int ngrp = (Nz + ROWS - 1) / ROWS;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N * ngrp) return;
-    const int al = blockIdx.y;
+    const int ch = blockIdx.y, al = blockIdx.z;
     const int ang = a.L.idx[al];
     const int jp = t / ngrp, kb = (t % ngrp) * ROWS;
     const float2 cs = a.g.cs[ang];
@@ -282,21 +307,33 @@ __global__ __launch_bounds__(256) void tau_prepass(TauArgs a)
     float S[ROWS];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) S[r] = 0.f;
-    const int ilo = N - (a.nchunk - 1) * a.dchunk;
-    for (int ip = N - 1; ip >= ilo; --ip) {
+    const int ihi = N - ch * a.dchunk - 1;
+    const int ilo = max(0, N - (ch + 1) * a.dchunk);
+#pragma unroll 2
+    for (int ip = ihi; ip >= ilo; --ip) {
         const Corners c = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, Nz);
         float m[ROWS];
-        sample_rows(a.mu, c, kb, Nz, a.vec, m);
+        sample_rows<VEC>(a.mu, c, kb, Nz, m);
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) S[r] += m[r];
-        const int done = N - ip;
-        if (done % a.dchunk == 0) {
-            const int ch = done / a.dchunk;
-            float *dst = a.tau + (((size_t)al * a.nchunk + ch) * N + jp) * Nz;
+    }
+    float *dst = a.tau + (((size_t)al * a.nchunk + ch) * N + jp) * Nz;
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r)
-                if (kb + r < Nz) dst[kb + r] = S[r];
-        }
+    for (int r = 0; r < ROWS; ++r)
+        if (kb + r < Nz) dst[kb + r] = S[r];
+}
+
+// Attenuation sum at the detector side of chunk `chunk`: the partial sums of
+// chunks 0 .. chunk-1.
+__device__ __forceinline__ void chunk_start(const float *__restrict__ tau, int al, int nchunk, int chunk, int N,
+                                            int Nz, int jp, int kb, float (&S)[ROWS])
+{
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) S[r] = 0.f;
+    for (int c = 0; c < chunk; ++c) {
+        const float *src = tau + (((size_t)al * nchunk + c) * N + jp) * Nz;
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) S[r] += (kb + r < Nz) ? src[kb + r] : 0.f;
     }
 }
 
@@ -313,7 +350,7 @@ struct FwdArgs {
     int vec;
 };
 
-template <bool MU, int KMC>
+template <bool MU, int KMC, bool VEC>
 __global__ __launch_bounds__(512) void fwd_main(FwdArgs a)
 {
     extern __shared__ float4 smem[];
@@ -332,11 +369,7 @@ __global__ __launch_bounds__(512) void fwd_main(FwdArgs a)
     float S[ROWS];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) S[r] = 0.f;
-    if (MU && chunk > 0 && active) {
-        const float *src = a.tau + (((size_t)al * a.nchunk + chunk) * N + jp) * Nz;
-#pragma unroll
-        for (int r = 0; r < ROWS; ++r) S[r] = (kb + r < Nz) ? src[kb + r] : 0.f;
-    }
+    if (MU && chunk > 0 && active) chunk_start(a.tau, al, a.nchunk, chunk, N, Nz, jp, kb, S);
     float acc[ROWS + 2 * KMC];
 #pragma unroll
     for (int t = 0; t < ROWS + 2 * KMC; ++t) acc[t] = 0.f;
@@ -351,11 +384,14 @@ __global__ __launch_bounds__(512) void fwd_main(FwdArgs a)
         const float *gt = a.g.taps + ((size_t)ang * N + ip) * a.g.TS;
         float w[ROWS];
         if (active) {
-            const Corners c = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, Nz);
-            sample_rows(a.f, c, kb, Nz, a.vec, w);
+            const Corners cn = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, Nz);
+            Raw rf, rm;
+            load_raw<VEC>(a.f, cn, kb, Nz, rf);
+            if (MU) load_raw<VEC>(a.mu, cn, kb, Nz, rm);
+            combine(rf, cn, kb, Nz, w);
             if (MU) {
                 float m[ROWS], att[ROWS];
-                sample_rows(a.mu, c, kb, Nz, a.vec, m);
+                combine(rm, cn, kb, Nz, m);
                 attenuate(m, S, a.g.tau_scale, att);
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r) w[r] *= att[r];
@@ -454,7 +490,7 @@ struct BackRotArgs {
     int vec;
 };
 
-template <bool MU, int KMC>
+template <bool MU, int KMC, bool VEC>
 __global__ __launch_bounds__(512) void back_rot(BackRotArgs a)
 {
     extern __shared__ float4 smem[];
@@ -487,11 +523,7 @@ __global__ __launch_bounds__(512) void back_rot(BackRotArgs a)
     float S[ROWS];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) S[r] = 0.f;
-    if (MU && chunk > 0 && active) {
-        const float *src = a.tau + (((size_t)al * a.nchunk + chunk) * N + jp) * Nz;
-#pragma unroll
-        for (int r = 0; r < ROWS; ++r) S[r] = (kb + r < Nz) ? src[kb + r] : 0.f;
-    }
+    if (MU && chunk > 0 && active) chunk_start(a.tau, al, a.nchunk, chunk, N, Nz, jp, kb, S);
     const int ihi = N - chunk * a.dchunk - 1;
     const int ilo = max(0, N - (chunk + 1) * a.dchunk);
     const int *kd = a.g.kdep + (size_t)ang * N;
@@ -501,7 +533,14 @@ __global__ __launch_bounds__(512) void back_rot(BackRotArgs a)
         const int K = kd[ip];
         const float *gt = a.g.taps + ((size_t)ang * N + ip) * a.g.TS;
         float v[ROWS];
+        Corners cn;
+        Raw rm;
         if (active) {
+            if (MU) {
+                // attenuation samples of this depth, in flight during the blur
+                cn = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, Nz);
+                load_raw<VEC>(a.mu, cn, kb, Nz, rm);
+            }
             ZGather<KMC>::run(K, ybuf + jp * YP, h * ROWS + KMC, gt, v);
             smem[wb_index(buf, 0, jp + KMC, h, nrows)] = make_float4(v[0], v[1], v[2], v[3]);
             smem[wb_index(buf, 1, jp + KMC, h, nrows)] = make_float4(v[4], v[5], v[6], v[7]);
@@ -511,9 +550,8 @@ __global__ __launch_bounds__(512) void back_rot(BackRotArgs a)
             float u[ROWS];
             blur_bins(smem, buf, jp + KMC, h, nrows, K, gt, v, u);
             if (MU) {
-                const Corners c = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, Nz);
                 float m[ROWS], att[ROWS];
-                sample_rows(a.mu, c, kb, Nz, a.vec, m);
+                combine(rm, cn, kb, Nz, m);
                 attenuate(m, S, a.g.tau_scale, att);
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r) u[r] *= att[r];
@@ -536,62 +574,67 @@ struct GatherArgs {
     const float *sens;
 };
 
-// Thread per (x, y, slab): transpose of the bilinear rotation, as a gather.
+// Transpose of the bilinear rotation, as a gather.  Workgroup = 8 x 8 object
+// columns x one slab; a wave covers 16 columns and four lanes share a column,
+// one per 16-byte quad of its 16 axial rows, so that every candidate brick
+// (64 bytes) is read by four adjacent lanes.  For each angle a column takes
+// the <= 3 x 3 rotated samples around its rotated position; the weight of
+// sample P is the bilinear hat max(0, 1 - |X_P - x|) max(0, 1 - |Y_P - y|),
+// with X_P, Y_P computed by the forward's own FP32 expression, so the weights
+// equal the forward's to within one rounding.
+constexpr int GT = 8;  // gather tile edge
+
 __global__ __launch_bounds__(256) void back_gather(GatherArgs a)
 {
     const int N = a.g.N, Nz = a.g.Nz;
-    const int tiles = (N + GATHER_TILE - 1) / GATHER_TILE;
-    const int x = (blockIdx.x / tiles) * GATHER_TILE + (threadIdx.x >> 4);
-    const int y = (blockIdx.x % tiles) * GATHER_TILE + (threadIdx.x & 15);
+    const int tiles = (N + GT - 1) / GT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane >> 2, q = lane & 3;
+    const int x = (blockIdx.x / tiles) * GT + wave * 2 + (col >> 3);
+    const int y = (blockIdx.x % tiles) * GT + (col & 7);
     const int slab = blockIdx.y;
     if (x >= N || y >= N) return;
     const float c = 0.5f * (float)(N - 1);
     const float xx = (float)x - c, yy = (float)y - c;
-    float acc[SLAB];
-#pragma unroll
-    for (int r = 0; r < SLAB; ++r) acc[r] = 0.f;
+    const float fxv = (float)x, fyv = (float)y;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    const size_t zstride = (size_t)a.nslab * N * N * SLAB;
+    const float *zq = a.z + (size_t)slab * N * N * SLAB + 4 * q;
     for (int al = 0; al < a.L.n; ++al) {
         const int ang = a.L.idx[al];
         const float2 cs = a.g.cs[ang];
         const float2 *xy0 = a.g.xy0 + (size_t)ang * N;
+        const float wdw = fabsf(cs.x) + fabsf(cs.y) + 1e-3f;
         const float ic = c + cs.x * xx + cs.y * yy;
         const float jc = c - cs.y * xx + cs.x * yy;
-        const float wdw = fabsf(cs.x) + fabsf(cs.y) + 1e-3f;
         const int ilo = (int)ceilf(ic - wdw), jlo = (int)ceilf(jc - wdw);
-        const float *zb = a.z + ((size_t)al * a.nslab + slab) * N * N * SLAB;
+        const float *zb = zq + (size_t)al * zstride;
+        float2 o[3];
+        float4 v[9];
 #pragma unroll
-        for (int di = 0; di < 3; ++di) {
-            const int ip = ilo + di;
-            if ((unsigned)ip >= (unsigned)N) continue;
+        for (int dj = 0; dj < 3; ++dj) o[dj] = xy0[min(max(jlo + dj, 0), N - 1)];
 #pragma unroll
-            for (int dj = 0; dj < 3; ++dj) {
-                const int jp = jlo + dj;
-                if ((unsigned)jp >= (unsigned)N) continue;
-                const float2 ob = xy0[jp];
-                const float X = fmaf((float)ip, cs.x, ob.x), Y = fmaf((float)ip, cs.y, ob.y);
-                const float xf = floorf(X), yf = floorf(Y);
-                const int x0 = (int)xf, y0 = (int)yf;
-                const float fx = X - xf, fy = Y - yf;
-                float wx, wy;
-                if (x0 == x) wx = 1.f - fx; else if (x0 + 1 == x) wx = fx; else continue;
-                if (y0 == y) wy = 1.f - fy; else if (y0 + 1 == y) wy = fy; else continue;
-                const float w = wx * wy;
-                const float4 *zp = reinterpret_cast<const float4 *>(zb + ((size_t)ip * N + jp) * SLAB);
+        for (int d = 0; d < 9; ++d) {
+            const int ipc = min(max(ilo + d / 3, 0), N - 1), jpc = min(max(jlo + d % 3, 0), N - 1);
+            v[d] = *reinterpret_cast<const float4 *>(zb + ((size_t)ipc * N + jpc) * SLAB);
+        }
 #pragma unroll
-                for (int q = 0; q < SLAB / 4; ++q) {
-                    const float4 v = zp[q];
-                    acc[4 * q + 0] = fmaf(w, v.x, acc[4 * q + 0]);
-                    acc[4 * q + 1] = fmaf(w, v.y, acc[4 * q + 1]);
-                    acc[4 * q + 2] = fmaf(w, v.z, acc[4 * q + 2]);
-                    acc[4 * q + 3] = fmaf(w, v.w, acc[4 * q + 3]);
-                }
-            }
+        for (int d = 0; d < 9; ++d) {
+            const int ip = ilo + d / 3, jp = jlo + d % 3;
+            const bool inr = (unsigned)ip < (unsigned)N && (unsigned)jp < (unsigned)N;
+            const float X = fmaf((float)ip, cs.x, o[d % 3].x), Y = fmaf((float)ip, cs.y, o[d % 3].y);
+            const float wx = fmaxf(0.f, 1.f - fabsf(X - fxv)), wy = fmaxf(0.f, 1.f - fabsf(Y - fyv));
+            const float w = inr ? wx * wy : 0.f;
+            acc[0] = fmaf(w, v[d].x, acc[0]);
+            acc[1] = fmaf(w, v[d].y, acc[1]);
+            acc[2] = fmaf(w, v[d].z, acc[2]);
+            acc[3] = fmaf(w, v[d].w, acc[3]);
         }
     }
     const size_t base = ((size_t)x * N + y) * Nz;
 #pragma unroll
-    for (int r = 0; r < SLAB; ++r) {
-        const int k = slab * SLAB + r;
+    for (int r = 0; r < 4; ++r) {
+        const int k = slab * SLAB + 4 * q + r;
         if (k >= Nz) break;
         float *p = a.out + base + k;
         if (a.mode == 0) {
@@ -599,8 +642,8 @@ __global__ __launch_bounds__(256) void back_gather(GatherArgs a)
         } else if (a.mode == 1) {
             *p += acc[r];
         } else {
-            const float s = a.sens[base + k];
-            if (s > 0.f) *p = *p * acc[r] / s;
+            const float sv = a.sens[base + k];
+            if (sv > 0.f) *p = *p * acc[r] / sv;
         }
     }
 }
@@ -619,9 +662,11 @@ struct spect_plan {
     int N, Nz, A;
     double voxel_cm;
     int kmax;   // largest blur radius
-    int kmc;    // compile-time radius class (0, 8, 16, 24, 32)
+    int kmc;    // compile-time radius class (multiple of 4, <= 32)
     int TS;     // tap row stride
     int device;
+    int fwd_slots[2];   // resident forward workgroups on the device, without / with attenuation
+    int back_slots[2];  // same for the rotated-frame back-projection kernel
     void *dmem;
     DevGeom g;
 };
@@ -694,16 +739,37 @@ struct Tuning {
     int nslab, nchunk, dchunk;
 };
 
-Tuning tune(const spect_plan *p, int n_list)
+enum { T_FWD = 1, T_BACK = 2, T_BOTH = 3 };
+
+// Depth chunking of a launch over n_list angles: pick the chunk count that
+// minimises (waves of resident workgroups) x (depths per workgroup + a fixed
+// per-workgroup cost), summed over the kernels that share the split (both
+// passes of an OSEM step share the attenuation offsets).  Splitting adds an
+// attenuation pre-pass when a map is given.
+Tuning tune(const spect_plan *p, int n_list, bool mu, int which)
 {
     Tuning t;
     t.nslab = (p->Nz + SLAB - 1) / SLAB;
     const long base = (long)std::max(1, n_list) * t.nslab;
-    long want = (1024 + base - 1) / base;             // aim at >= 1024 workgroups
-    const int cap = std::max(1, p->N / 8);            // at least 8 depths per chunk
-    int nc = (int)std::min<long>(std::max<long>(want, 1), cap);
-    t.dchunk = (p->N + nc - 1) / nc;
-    t.nchunk = (p->N + t.dchunk - 1) / t.dchunk;
+    const int cap = std::max(1, p->N / 8);  // at least 8 depths per chunk
+    double best = 1e300;
+    t.nchunk = 1;
+    t.dchunk = p->N;
+    for (int nc = 1; nc <= cap; ++nc) {
+        const int D = (p->N + nc - 1) / nc;
+        const int ncc = (p->N + D - 1) / D;
+        if (ncc != nc) continue;
+        const long wgs = base * ncc;
+        double cost = 0;
+        if (which & T_FWD) cost += (double)((wgs + p->fwd_slots[mu] - 1) / p->fwd_slots[mu]) * (D + 6);
+        if (which & T_BACK) cost += (double)((wgs + p->back_slots[mu] - 1) / p->back_slots[mu]) * (D + 6);
+        if (mu && ncc > 1) cost += 2 + D / 4.0;
+        if (cost < best - 1e-9) {
+            best = cost;
+            t.nchunk = ncc;
+            t.dchunk = D;
+        }
+    }
     return t;
 }
 
@@ -744,15 +810,15 @@ std::vector<int> batch_sizes(int n, int B)
     return v;
 }
 
-size_t fwd_need(const spect_plan *p, int nl, bool mu)
+size_t fwd_need(const spect_plan *p, int nl, bool mu, int which = T_FWD)
 {
-    const Tuning t = tune(p, nl);
+    const Tuning t = tune(p, nl, mu, which);
     return tau_bytes(p, t, nl, mu) + part_bytes(p, t, nl);
 }
 
-size_t back_need(const spect_plan *p, int nl, bool mu)
+size_t back_need(const spect_plan *p, int nl, bool mu, int which = T_BACK)
 {
-    const Tuning t = tune(p, nl);
+    const Tuning t = tune(p, nl, mu, which);
     return tau_bytes(p, t, nl, mu) + z_bytes(p, t, nl);
 }
 
@@ -785,7 +851,7 @@ size_t osem_ws(const spect_plan *p, int M, bool mu)
     size_t b = 0;
     for (int nl : {p->A / M, (p->A + M - 1) / M}) {
         if (nl < 1) continue;
-        const Tuning t = tune(p, nl);
+        const Tuning t = tune(p, nl, mu, T_BOTH);
         b = std::max(b, tau_bytes(p, t, nl, mu) + std::max(part_bytes(p, t, nl), z_bytes(p, t, nl)));
     }
     return osem_q_bytes(p, M) + b;
@@ -794,26 +860,48 @@ size_t osem_ws(const spect_plan *p, int M, bool mu)
 typedef void (*KernelFn)(FwdArgs);
 typedef void (*BackFn)(BackRotArgs);
 
-KernelFn fwd_kernel(bool mu, int kmc)
+template <bool MU, bool VEC>
+KernelFn fwd_kernel_k(int kmc)
 {
     switch (kmc) {
-    case 0: return mu ? fwd_main<true, 0> : fwd_main<false, 0>;
-    case 8: return mu ? fwd_main<true, 8> : fwd_main<false, 8>;
-    case 16: return mu ? fwd_main<true, 16> : fwd_main<false, 16>;
-    case 24: return mu ? fwd_main<true, 24> : fwd_main<false, 24>;
-    default: return mu ? fwd_main<true, 32> : fwd_main<false, 32>;
+    case 0: return fwd_main<MU, 0, VEC>;
+    case 4: return fwd_main<MU, 4, VEC>;
+    case 8: return fwd_main<MU, 8, VEC>;
+    case 12: return fwd_main<MU, 12, VEC>;
+    case 16: return fwd_main<MU, 16, VEC>;
+    case 20: return fwd_main<MU, 20, VEC>;
+    case 24: return fwd_main<MU, 24, VEC>;
+    case 28: return fwd_main<MU, 28, VEC>;
+    default: return fwd_main<MU, 32, VEC>;
     }
 }
 
-BackFn back_kernel(bool mu, int kmc)
+KernelFn fwd_kernel(bool mu, int kmc, bool vec)
+{
+    if (mu) return vec ? fwd_kernel_k<true, true>(kmc) : fwd_kernel_k<true, false>(kmc);
+    return vec ? fwd_kernel_k<false, true>(kmc) : fwd_kernel_k<false, false>(kmc);
+}
+
+template <bool MU, bool VEC>
+BackFn back_kernel_k(int kmc)
 {
     switch (kmc) {
-    case 0: return mu ? back_rot<true, 0> : back_rot<false, 0>;
-    case 8: return mu ? back_rot<true, 8> : back_rot<false, 8>;
-    case 16: return mu ? back_rot<true, 16> : back_rot<false, 16>;
-    case 24: return mu ? back_rot<true, 24> : back_rot<false, 24>;
-    default: return mu ? back_rot<true, 32> : back_rot<false, 32>;
+    case 0: return back_rot<MU, 0, VEC>;
+    case 4: return back_rot<MU, 4, VEC>;
+    case 8: return back_rot<MU, 8, VEC>;
+    case 12: return back_rot<MU, 12, VEC>;
+    case 16: return back_rot<MU, 16, VEC>;
+    case 20: return back_rot<MU, 20, VEC>;
+    case 24: return back_rot<MU, 24, VEC>;
+    case 28: return back_rot<MU, 28, VEC>;
+    default: return back_rot<MU, 32, VEC>;
     }
+}
+
+BackFn back_kernel(bool mu, int kmc, bool vec)
+{
+    if (mu) return vec ? back_kernel_k<true, true>(kmc) : back_kernel_k<true, false>(kmc);
+    return vec ? back_kernel_k<false, true>(kmc) : back_kernel_k<false, false>(kmc);
 }
 
 int block_threads(int N) { return std::min(512, ((2 * N + 63) / 64) * 64); }
@@ -902,8 +990,8 @@ void launch_tau(const spect_plan *p, const AngleList &L, const Tuning &t, const 
     a.dchunk = t.dchunk;
     a.vec = vec;
     const int ngrp = (p->Nz + ROWS - 1) / ROWS;
-    dim3 grid((p->N * ngrp + 255) / 256, L.n);
-    hipLaunchKernelGGL(tau_prepass, grid, dim3(256), 0, st, a);
+    dim3 grid((p->N * ngrp + 255) / 256, t.nchunk - 1, L.n);
+    hipLaunchKernelGGL(vec ? tau_prepass<true> : tau_prepass<false>, grid, dim3(256), 0, st, a);
 }
 
 // Forward projection of one list into partial rows, then the reduction.
@@ -911,10 +999,10 @@ void launch_tau(const spect_plan *p, const AngleList &L, const Tuning &t, const 
 // already computed for the same list (the tau region is then skipped).
 int run_forward(const spect_plan *p, const float *f, const float *mu, const AngleList &L, char *ws,
                 size_t ws_avail, const float *tau_given, int mode, float *proj, const float *g,
-                const float *s_add, float *q, bool vec, hipStream_t st)
+                const float *s_add, float *q, bool vec, int which, hipStream_t st)
 {
-    const Tuning t = tune(p, L.n);
-    if (fwd_need(p, L.n, mu != nullptr) > ws_avail)
+    const Tuning t = tune(p, L.n, mu != nullptr, which);
+    if (fwd_need(p, L.n, mu != nullptr, which) > ws_avail)
         return fail(SPECT_EINVAL, "workspace too small for a %d-angle forward launch", L.n);
     const float *tau = nullptr;
     size_t off = 0;
@@ -940,7 +1028,7 @@ int run_forward(const spect_plan *p, const float *f, const float *mu, const Angl
     a.nchunk = t.nchunk;
     a.dchunk = t.dchunk;
     a.vec = vec;
-    KernelFn fk = fwd_kernel(mu != nullptr, p->kmc);
+    KernelFn fk = fwd_kernel(mu != nullptr, p->kmc, vec);
     allow_smem(reinterpret_cast<const void *>(fk), fwd_smem(p));
     hipLaunchKernelGGL(fk, dim3(t.nslab, t.nchunk, L.n), dim3(block_threads(p->N)), fwd_smem(p), st, a);
     ReduceArgs r;
@@ -966,10 +1054,10 @@ int run_forward(const spect_plan *p, const float *f, const float *mu, const Angl
 // ws holds [tau][z]; tau_given as in run_forward.
 int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const float *mu,
              const AngleList &L, char *ws, size_t ws_avail, const float *tau_given, int mode, float *out,
-             const float *sens, bool vec, hipStream_t st)
+             const float *sens, bool vec, int which, hipStream_t st)
 {
-    const Tuning t = tune(p, L.n);
-    if (back_need(p, L.n, mu != nullptr) > ws_avail)
+    const Tuning t = tune(p, L.n, mu != nullptr, which);
+    if (back_need(p, L.n, mu != nullptr, which) > ws_avail)
         return fail(SPECT_EINVAL, "workspace too small for a %d-angle back-projection launch", L.n);
     const float *tau = nullptr;
     size_t off = 0;
@@ -997,7 +1085,7 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
     b.nchunk = t.nchunk;
     b.dchunk = t.dchunk;
     b.vec = vec;
-    BackFn bk = back_kernel(mu != nullptr, p->kmc);
+    BackFn bk = back_kernel(mu != nullptr, p->kmc, vec);
     allow_smem(reinterpret_cast<const void *>(bk), back_smem(p));
     hipLaunchKernelGGL(bk, dim3(t.nslab, t.nchunk, L.n), dim3(block_threads(p->N)), back_smem(p), st, b);
     GatherArgs gg;
@@ -1008,7 +1096,7 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
     gg.mode = mode;
     gg.out = out;
     gg.sens = sens;
-    const int tiles = (p->N + GATHER_TILE - 1) / GATHER_TILE;
+    const int tiles = (p->N + GT - 1) / GT;
     hipLaunchKernelGGL(back_gather, dim3(tiles * tiles, t.nslab), dim3(256), 0, st, gg);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "back projection launch");
@@ -1074,7 +1162,7 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
     p->A = g.n_angles;
     p->voxel_cm = g.voxel_cm;
     p->kmax = kmax;
-    p->kmc = kmax == 0 ? 0 : ((kmax + 7) / 8) * 8;
+    p->kmc = ((kmax + 3) / 4) * 4;
     p->TS = p->kmc + 1;
     if (hipGetDevice(&p->device) != hipSuccess) {
         delete p;
@@ -1126,6 +1214,24 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
     p->g.A = A;
     p->g.TS = p->TS;
     p->g.tau_scale = (float)(g.voxel_cm / std::log(2.0));
+    // resident workgroups per device for the chunk tuning
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cus < 1)
+        cus = 256;
+    for (int mu = 0; mu < 2; ++mu) {
+        int nb = 0;
+        const void *fk = reinterpret_cast<const void *>(fwd_kernel(mu != 0, p->kmc, true));
+        allow_smem(fk, fwd_smem(p));
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk, block_threads(N), fwd_smem(p)) != hipSuccess)
+            nb = 1;
+        p->fwd_slots[mu] = std::max(1, nb) * cus;
+        const void *bk = reinterpret_cast<const void *>(back_kernel(mu != 0, p->kmc, true));
+        allow_smem(bk, back_smem(p));
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bk, block_threads(N), back_smem(p)) != hipSuccess)
+            nb = 1;
+        p->back_slots[mu] = std::max(1, nb) * cus;
+    }
+    (void)hipGetLastError();
     *out = p;
     return ok();
 }
@@ -1175,7 +1281,7 @@ int spect_fwd(const spect_plan *plan, const float *f, const float *mu, float *pr
         const int n = (int)std::min<size_t>(MAXL, list.size() - b);
         const AngleList L = to_list(list.data() + b, n);
         if ((st = run_forward(plan, f, mu, L, static_cast<char *>(ws), ws_bytes, nullptr, 0, proj, nullptr, nullptr,
-                              nullptr, vec, s)))
+                              nullptr, vec, T_FWD, s)))
             return st;
     }
     return ok();
@@ -1205,7 +1311,7 @@ int spect_back(const spect_plan *plan, const float *proj, const float *mu, float
         const AngleList L = to_list(list.data() + b, n);
         const int mode = (b == 0 && !accumulate) ? 0 : 1;
         if ((st = run_back(plan, proj, 0, 0, mu, L, static_cast<char *>(ws), ws_bytes, nullptr, mode, f_out, nullptr, vec,
-                            s)))
+                            T_BACK, s)))
             return st;
     }
     return ok();
@@ -1230,7 +1336,7 @@ int spect_sensitivity(const spect_plan *plan, const float *mu, float *sens, cons
         const int n = (int)std::min<size_t>(G, list.size() - b);
         const AngleList L = to_list(list.data() + b, n);
         if ((st = run_back(plan, nullptr, 0, 1, mu, L, static_cast<char *>(ws), ws_bytes, nullptr, b == 0 ? 0 : 1, sens,
-                           nullptr, vec, s)))
+                           nullptr, vec, T_BACK, s)))
             return st;
     }
     return ok();
@@ -1261,10 +1367,11 @@ int osem_subset_step(const spect_plan *plan, float *f, const float *mu, const fl
     const size_t qb = osem_q_bytes(plan, n_subsets);
     char *rest = w + qb;
     const size_t avail = ws_bytes - qb;
-    if ((st = run_forward(plan, f, mu, L, rest, avail, nullptr, 1, nullptr, g, s_add, q, vec, s))) return st;
+    if ((st = run_forward(plan, f, mu, L, rest, avail, nullptr, 1, nullptr, g, s_add, q, vec, T_BOTH, s)))
+        return st;
     // same list, same tuning: the attenuation offsets at the start of rest are reused
     if ((st = run_back(plan, q, 1, 0, mu, L, rest, avail, reinterpret_cast<const float *>(rest), 2, f, sens_m,
-                       vec, s)))
+                       vec, T_BOTH, s)))
         return st;
     return ok();
 }
