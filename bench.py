@@ -12,18 +12,20 @@ clinical and Monte Carlo SPECT acquisitions (Section 3.1, Appendix A).
 One step = one whole reconstruction with the data, the attenuation map and
 the initial image already resident in HBM: the 8 subset sensitivities
 H_m^T 1 and 32 subiterations (forward projection, ratio, back projection,
-multiplicative update).  The timed region covers exactly K steps between
-two device synchronisations.
+multiplicative update).  The timed region covers exactly K steps between two
+device synchronisations.
 
-value = voxel-angle projections per second, counting one forward plus one
-adjoint application of a voxel-angle pair as one projection:
+value = voxel-angle projections per second, one forward plus one adjoint
+application of a voxel-angle pair counted as one projection:
 N^2 Nz A (I + 1/2) per reconstruction (the sensitivities are one adjoint
 pass).  Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -38,19 +40,49 @@ if ROOT not in sys.path:
 import paper_2309_01977_amd as S  # noqa: E402
 from paper_2309_01977_amd import phantoms as P  # noqa: E402
 
-HBM_PEAK_GBS = 8000.0
-# Bytes a projector must move per voxel-angle when every angle streams the
-# object-space operands once: forward = activity + attenuation sample;
-# adjoint = attenuation sample + object accumulator contribution.
-BYTES_PER_VOXEL_ANGLE = 8.0
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+SOURCE = os.path.join(ROOT, "paper_2309_01977_amd", "csrc", "spect.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_osem_128cube_120ang.json")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def event_time_ms(fn, reps):
-    """Mean duration of fn() on the current stream, from HIP events."""
+def blur_radii(w):
+    """Collimator blur radius K per depth (sigma = a d + b, K = ceil(4 sigma/dx))."""
+    c = 0.5 * (w.n - 1)
+    out = []
+    for ip in range(w.n):
+        d = max(0.0, 0.5 * w.n * w.voxel_cm - (ip - c) * w.voxel_cm)
+        s = (w.psf_a * d + w.psf_b) / w.voxel_cm
+        out.append(max(0, math.ceil(w.psf_nsigma * s - 1e-9)) if s > 0 else 0)
+    return out
+
+
+def algorithmic_counts(w, kernel):
+    """(FP32 FLOP, bytes) per voxel-angle of the method for one kernel.
+
+    Forward: two bilinear samples (activity, attenuation: 7 FLOP each), the
+    attenuation exponent (5), the attenuated sample (1) and the separable
+    depth-dependent blur, 2 (2K+1) FLOP along each of the two detector axes;
+    bytes: the activity and attenuation samples (4 B each).
+    Adjoint rotated-frame pass: the same blur, one attenuation sample (7),
+    the exponent (5) and the product (1); bytes: attenuation sample + the
+    rotated-frame value handed to the gather (4 B each)."""
+    Ks = blur_radii(w)
+    blur = float(np.mean([4 * (2 * k + 1) for k in Ks]))
+    if kernel == "fwd_main":
+        return 20.0 + blur, 8.0
+    if kernel == "back_rot":
+        return 13.0 + blur, 8.0
+    if kernel == "back_gather":   # 9 bilinear candidates x (weight 9 + 1 FMA) ; reads 9 x 4 B
+        return 9 * 11.0, 4.0
+    return None, None
+
+
+def event_ms(fn, reps):
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(st)
@@ -61,21 +93,32 @@ def event_time_ms(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def cpu_baseline(w, f_true, mu):
-    """The FP64 oracle on the host: one forward + adjoint pass over all angles."""
+def traffic_record(kernel):
+    """HBM bytes per launch measured with rocprofv3 counters, if they were
+    taken on the current kernel source."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        src = hashlib.sha256(open(SOURCE, "rb").read()).hexdigest()
+        if rec.get("source_sha256") != src:
+            return None
+        return rec["kernels"].get(kernel, {}).get("hbm_bytes_per_launch")
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def cpu_baseline(w, f_true, mu, g):
+    """The FP64 oracle on the host: the same whole reconstruction."""
     from oracle import oracle as O
     O.build(force=False)
     og = O.Geometry(w.n, w.nz, w.n_angles, w.voxel_cm, w.psf_a, w.psf_b, w.psf_nsigma)
-    f64, mu64 = f_true.astype(np.float64), mu.astype(np.float64)
     t0 = time.perf_counter()
-    p = O.forward(og, f64, mu64)
-    O.back(og, p, mu64)
+    O.osem(og, g.astype(np.float64), mu.astype(np.float64), w.n_iters, w.n_subsets)
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": w.voxel_angles / dt, "unit": "voxel-angle projections/s (fwd+adj)",
+    return {"value": w.voxel_angles * (w.n_iters + 0.5) / dt, "unit": "voxel-angle projections/s",
             "cores": threads, "kind": "oracle",
-            "sample": f"one FP64 forward + adjoint pass over all {w.n_angles} angles of the "
-                      f"{w.n}^3 workload ({dt:.1f} s)"}
+            "sample": f"one whole FP64 OSEM reconstruction of the {w.n}^3 x {w.n_angles} workload "
+                      f"({w.n_iters} it x {w.n_subsets} subsets, sensitivities included): {dt:.1f} s"}
 
 
 def main():
@@ -87,7 +130,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              f"(the reconstruction is not sharded across GPUs)", file=sys.stderr)
+              f"(a reconstruction is not sharded across GPUs)", file=sys.stderr)
         sys.exit(2)
     if not torch.cuda.is_available():
         print("no GPU available", file=sys.stderr)
@@ -102,7 +145,8 @@ def main():
     ft = torch.from_numpy(f_true).cuda()
     gbar = plan.forward(ft, mu).cpu().numpy()
     _, noise = P.rngs(w.seed_index)
-    g = torch.from_numpy(P.poisson_counts(gbar, w.total_counts, noise)).cuda()
+    g_np = P.poisson_counts(gbar, w.total_counts, noise)
+    g = torch.from_numpy(g_np).cuda()
     f = torch.empty(w.object_shape, device="cuda")
     log(f"workload {w.name}: data ready")
 
@@ -111,7 +155,6 @@ def main():
 
     for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
     st = torch.cuda.current_stream()
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
@@ -124,22 +167,41 @@ def main():
     wall = time.perf_counter() - t0
     per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
     ms = float(per.mean())
-    log(f"OSEM reconstruction: mean {ms:.3f} ms, wall {wall * 1e3 / args.steps:.3f} ms/step")
+    log(f"OSEM reconstruction: mean {ms:.3f} ms (events), {wall * 1e3 / args.steps:.3f} ms (wall)")
+    value = w.voxel_angles * (w.n_iters + 0.5) / (ms * 1e-3)
 
-    pairs = w.voxel_angles * (w.n_iters + 0.5)
-    value = pairs / (ms * 1e-3)
+    # per-kernel durations from HIP events the library records on its stream
+    with S.KernelTimer() as kt:
+        for _ in range(3):
+            step()
+        torch.cuda.synchronize()
+    kstats = kt.stats()
+    kernels = {k: {"launches": n, "avg_ms": t / n, "share": t / sum(v[1] for v in kstats.values())}
+               for k, (n, t) in kstats.items()}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    flop_va, bytes_va = algorithmic_counts(w, dom)
+    per_launch_va = w.voxel_angles / w.n_subsets          # one subset of angles per launch
+    dur = kernels[dom]["avg_ms"] * 1e-3
+    tflops = flop_va * per_launch_va / dur / 1e12
+    gbs = bytes_va * per_launch_va / dur / 1e9
+    traffic = traffic_record(dom)
+    log(f"dominant kernel {dom}: {kernels[dom]['avg_ms'] * 1e3:.1f} us/launch, "
+        f"{tflops:.1f} TFLOP/s, {gbs:.0f} GB/s algorithmic")
 
-    # projector passes over all angles (forward, adjoint) for the roofline
+    # whole-angle projector passes (context)
     proj = torch.empty(w.proj_shape, device="cuda")
     back = torch.empty(w.object_shape, device="cuda")
     for _ in range(3):
         plan.forward(f, mu, out=proj)
         plan.back(proj, mu, out=back)
-    t_fwd = event_time_ms(lambda: plan.forward(f, mu, out=proj), 20)
-    t_adj = event_time_ms(lambda: plan.back(proj, mu, out=back), 20)
-    bytes_fwd = BYTES_PER_VOXEL_ANGLE * w.voxel_angles
-    achieved = bytes_fwd / (t_fwd * 1e-3) / 1e9
-    log(f"forward pass {t_fwd:.3f} ms, adjoint pass {t_adj:.3f} ms")
+    t_fwd = event_ms(lambda: plan.forward(f, mu, out=proj), 10)
+    t_adj = event_ms(lambda: plan.back(proj, mu, out=back), 10)
+
+    # traffic calibration reference: one plain 256 MiB device copy
+    src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
 
     out = {
         "metric": "voxel-angle projections/s (fwd+adj) at 128^3x120; OSEM recon p50/p99 latency",
@@ -160,15 +222,18 @@ def main():
                    "subsets": w.n_subsets, "counts": w.total_counts},
         "osem_latency_ms": {"p50": float(np.percentile(per, 50)),
                             "p99": float(np.percentile(per, 99))},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": tflops,
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic},
+        "roofline_hbm": {"kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS},
+        "kernels": kernels,
         "projector_pass_ms": {"fwd": t_fwd, "adj": t_adj,
                               "voxel_angles_per_s": w.voxel_angles / ((t_fwd + t_adj) * 1e-3)},
-        "roofline": {"bound": "hbm", "kernel": "fwd_main (+fwd_reduce)", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None},
     }
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(w, f_true, mu_np)
+        out["cpu_baseline"] = cpu_baseline(w, f_true, mu_np, g_np)
     print(json.dumps(out), flush=True)
 
 

@@ -150,6 +150,17 @@ int osem_subset_step(const spect_plan *plan, float *f, const float *mu, const fl
                      const float *s_add, const float *sens_m, int32_t m, int32_t n_subsets,
                      void *ws, size_t ws_bytes, void *stream);
 
+/* Kernel timing, a tracing aid.  While enabled (process-wide), every kernel
+ * the library launches is bracketed by two HIP events recorded on the
+ * launch's own stream.  spect_profile_query waits for the recorded launches of
+ * the named kernel ("tau_prepass", "fwd_main", "fwd_reduce", "back_rot",
+ * "back_gather", "fill_zero") and returns their count and summed duration in
+ * milliseconds; spect_profile_reset waits for and frees all records.
+ * Errors: SPECT_EINVAL (NULL argument, unknown name), SPECT_EHIP. */
+int spect_profile_enable(int enable);
+int spect_profile_reset(void);
+int spect_profile_query(const char *kernel, int32_t *launches, double *total_ms);
+
 /* Message for the last error on the calling thread ("" if none). */
 const char *spect_last_error(void);
 

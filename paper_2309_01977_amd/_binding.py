@@ -24,7 +24,9 @@ SPECT_EUNSUPPORTED = -4
 OP_FWD, OP_BACK, OP_SENS, OP_OSEM = 0, 1, 2, 3
 
 EXPORTS = ("spect_plan_create", "spect_plan_destroy", "spect_workspace_size", "spect_fwd",
-           "spect_back", "spect_sensitivity", "osem_subset_step", "spect_last_error")
+           "spect_back", "spect_sensitivity", "osem_subset_step", "spect_profile_enable",
+           "spect_profile_reset", "spect_profile_query", "spect_last_error")
+KERNELS = ("tau_prepass", "fwd_main", "fwd_reduce", "back_rot", "back_gather", "fill_zero")
 
 
 class SpectError(RuntimeError):
@@ -63,6 +65,10 @@ def load_library(path: Optional[str] = None):
     lib.spect_back.argtypes = [vp, vp, vp, vp, i32p, i32, ctypes.c_int, vp, sz, vp]
     lib.spect_sensitivity.argtypes = [vp, vp, vp, i32p, i32, vp, sz, vp]
     lib.osem_subset_step.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, vp, sz, vp]
+    lib.spect_profile_enable.argtypes = [ctypes.c_int]
+    lib.spect_profile_reset.argtypes = []
+    lib.spect_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_double)]
     lib.spect_last_error.restype = ctypes.c_char_p
     for name in EXPORTS[:-1]:
         getattr(lib, name).restype = ctypes.c_int
@@ -211,6 +217,36 @@ class Plan:
             _ptr(sens_m, self.object_shape, "sens_m"), int(m), int(n_subsets),
             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
         return f
+
+
+class KernelTimer:
+    """Per-kernel HIP-event timing of the library's launches (spect_profile_*).
+
+    with KernelTimer() as kt:
+        ...library calls...
+    kt.stats()  -> {kernel: (launches, total_ms)}
+    """
+
+    def __enter__(self):
+        lib = load_library()
+        _check(lib.spect_profile_reset())
+        _check(lib.spect_profile_enable(1))
+        return self
+
+    def __exit__(self, *exc):
+        _check(load_library().spect_profile_enable(0))
+        return False
+
+    def stats(self):
+        lib = load_library()
+        out = {}
+        for k in KERNELS:
+            n, ms = ctypes.c_int32(), ctypes.c_double()
+            _check(lib.spect_profile_query(k.encode(), ctypes.byref(n), ctypes.byref(ms)))
+            if n.value:
+                out[k] = (n.value, ms.value)
+        _check(lib.spect_profile_reset())
+        return out
 
 
 def subset_angles(n_angles: int, n_subsets: int, m: int):

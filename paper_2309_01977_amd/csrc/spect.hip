@@ -36,6 +36,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -673,6 +674,46 @@ struct spect_plan {
 
 namespace {
 
+// ------------------------------------------------------------- timing ----
+// Optional per-kernel timing: while enabled, every launch is bracketed by two
+// HIP events recorded on the launch's own stream.
+
+enum KernelId { K_TAU = 0, K_FWD, K_REDUCE, K_BACK_ROT, K_GATHER, K_FILL, K_COUNT };
+const char *const kKernelNames[K_COUNT] = {"tau_prepass", "fwd_main", "fwd_reduce", "back_rot",
+                                           "back_gather", "fill_zero"};
+
+struct ProfRec {
+    int kernel;
+    hipEvent_t a, b;
+};
+
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+
+struct ProfScope {
+    int kernel;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    bool on;
+    ProfScope(int k, hipStream_t s) : kernel(k), st(s)
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        on = g_prof_on;
+        if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            (void)hipEventRecord(a, st);
+        else
+            on = false;
+    }
+    ~ProfScope()
+    {
+        if (!on) return;
+        (void)hipEventRecord(b, st);
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof.push_back({kernel, a, b});
+    }
+};
+
 thread_local std::string g_err;
 
 int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
@@ -991,6 +1032,7 @@ void launch_tau(const spect_plan *p, const AngleList &L, const Tuning &t, const 
     a.vec = vec;
     const int ngrp = (p->Nz + ROWS - 1) / ROWS;
     dim3 grid((p->N * ngrp + 255) / 256, t.nchunk - 1, L.n);
+    ProfScope ps(K_TAU, st);
     hipLaunchKernelGGL(vec ? tau_prepass<true> : tau_prepass<false>, grid, dim3(256), 0, st, a);
 }
 
@@ -1030,7 +1072,10 @@ int run_forward(const spect_plan *p, const float *f, const float *mu, const Angl
     a.vec = vec;
     KernelFn fk = fwd_kernel(mu != nullptr, p->kmc, vec);
     allow_smem(reinterpret_cast<const void *>(fk), fwd_smem(p));
-    hipLaunchKernelGGL(fk, dim3(t.nslab, t.nchunk, L.n), dim3(block_threads(p->N)), fwd_smem(p), st, a);
+    {
+        ProfScope ps(K_FWD, st);
+        hipLaunchKernelGGL(fk, dim3(t.nslab, t.nchunk, L.n), dim3(block_threads(p->N)), fwd_smem(p), st, a);
+    }
     ReduceArgs r;
     r.L = L;
     r.part = part;
@@ -1044,7 +1089,10 @@ int run_forward(const spect_plan *p, const float *f, const float *mu, const Angl
     r.g = g;
     r.s_add = s_add;
     r.q = q;
-    hipLaunchKernelGGL(fwd_reduce, dim3((p->N * p->Nz + 255) / 256, L.n), dim3(256), 0, st, r);
+    {
+        ProfScope ps(K_REDUCE, st);
+        hipLaunchKernelGGL(fwd_reduce, dim3((p->N * p->Nz + 255) / 256, L.n), dim3(256), 0, st, r);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     return SPECT_OK;
@@ -1087,7 +1135,10 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
     b.vec = vec;
     BackFn bk = back_kernel(mu != nullptr, p->kmc, vec);
     allow_smem(reinterpret_cast<const void *>(bk), back_smem(p));
-    hipLaunchKernelGGL(bk, dim3(t.nslab, t.nchunk, L.n), dim3(block_threads(p->N)), back_smem(p), st, b);
+    {
+        ProfScope ps(K_BACK_ROT, st);
+        hipLaunchKernelGGL(bk, dim3(t.nslab, t.nchunk, L.n), dim3(block_threads(p->N)), back_smem(p), st, b);
+    }
     GatherArgs gg;
     gg.g = p->g;
     gg.L = L;
@@ -1097,7 +1148,10 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
     gg.out = out;
     gg.sens = sens;
     const int tiles = (p->N + GT - 1) / GT;
-    hipLaunchKernelGGL(back_gather, dim3(tiles * tiles, t.nslab), dim3(256), 0, st, gg);
+    {
+        ProfScope ps(K_GATHER, st);
+        hipLaunchKernelGGL(back_gather, dim3(tiles * tiles, t.nslab), dim3(256), 0, st, gg);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "back projection launch");
     return SPECT_OK;
@@ -1105,6 +1159,7 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
 
 int clear(float *p, size_t n, hipStream_t st)
 {
+    ProfScope ps(K_FILL, st);
     hipLaunchKernelGGL(fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? SPECT_OK : hip_fail(e, "clear launch");
@@ -1125,6 +1180,48 @@ bool want_vec(const spect_plan *p, std::initializer_list<const void *> ptrs)
 extern "C" {
 
 const char *spect_last_error(void) { return g_err.c_str(); }
+
+int spect_profile_enable(int enable)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = enable != 0;
+    return ok();
+}
+
+int spect_profile_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &r : g_prof) {
+        if (hipEventSynchronize(r.b) != hipSuccess) return fail(SPECT_EHIP, "waiting for a timing event failed");
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof.clear();
+    return ok();
+}
+
+int spect_profile_query(const char *kernel, int32_t *launches, double *total_ms)
+{
+    if (!kernel || !launches || !total_ms) return fail(SPECT_EINVAL, "NULL argument");
+    int id = -1;
+    for (int k = 0; k < K_COUNT; ++k)
+        if (std::strcmp(kernel, kKernelNames[k]) == 0) id = k;
+    if (id < 0) return fail(SPECT_EINVAL, "unknown kernel name '%s'", kernel);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    int n = 0;
+    double ms = 0;
+    for (auto &r : g_prof) {
+        if (r.kernel != id) continue;
+        float e = 0;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&e, r.a, r.b) != hipSuccess)
+            return fail(SPECT_EHIP, "reading a timing event failed");
+        ++n;
+        ms += e;
+    }
+    *launches = n;
+    *total_ms = ms;
+    return ok();
+}
 
 int spect_plan_create(const spect_geometry *geom, spect_plan **out)
 {

@@ -88,3 +88,14 @@ def test_null_arguments_are_rejected_before_any_device_call():
 def test_binding_has_no_cpu_fallback(tmp_path):
     with pytest.raises(RuntimeError, match="not built"):
         B.load_library(str(tmp_path / "missing.so"))
+
+
+def test_profile_query_rejects_bad_arguments():
+    lib = S.load_library()
+    n, ms = ctypes.c_int32(), ctypes.c_double()
+    assert lib.spect_profile_query(b"no_such_kernel", ctypes.byref(n), ctypes.byref(ms)) == B.SPECT_EINVAL
+    assert lib.spect_profile_query(None, ctypes.byref(n), ctypes.byref(ms)) == B.SPECT_EINVAL
+    assert lib.spect_profile_query(b"fwd_main", ctypes.byref(n), ctypes.byref(ms)) == B.SPECT_OK
+    assert n.value == 0 and ms.value == 0.0
+    assert lib.spect_profile_enable(0) == B.SPECT_OK
+    assert lib.spect_profile_reset() == B.SPECT_OK

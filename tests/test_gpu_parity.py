@@ -264,3 +264,20 @@ def test_osem_full_run_parity(which):
     e = rel_l2(got, ref)
     say(f"  {which}: OSEM rel L2 {e:.2e}")
     assert e <= OSEM_TOL
+
+
+def test_kernel_timer_counts_launches():
+    og, plan = both(32, 16, 8)
+    r = np.random.default_rng(15)
+    f = dev(P.random_object(og.object_shape, r))
+    mu = dev(P.random_mu(og.object_shape, r, 0.1))
+    with S.KernelTimer() as kt:
+        for _ in range(3):
+            plan.forward(f, mu)
+        torch.cuda.synchronize()
+    st = kt.stats()
+    assert st["fwd_main"][0] == 3 and st["fwd_main"][1] > 0
+    assert st["fwd_reduce"][0] == 3
+    plan.forward(f, mu)   # not recorded once the timer is closed
+    torch.cuda.synchronize()
+    assert kt.stats() == {}
