@@ -71,6 +71,7 @@ extern "C" {
 #define SPECT_OP_BACK 1
 #define SPECT_OP_SENS 2
 #define SPECT_OP_OSEM 3
+#define SPECT_OP_RECON 4
 
 /* Limits of this build. */
 #define SPECT_MAX_N 256        /* transverse size N */
@@ -108,7 +109,7 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out);
 int spect_plan_destroy(spect_plan *plan);
 
 /* Workspace bytes needed by op (SPECT_OP_*) over n_idx angles; for
- * SPECT_OP_OSEM n_idx is the number of subsets M.  with_mu != 0 when an
+ * SPECT_OP_OSEM and SPECT_OP_RECON n_idx is the number of subsets M.  with_mu != 0 when an
  * attenuation map will be passed. */
 int spect_workspace_size(const spect_plan *plan, int op, int32_t n_idx, int with_mu,
                          size_t *bytes);
@@ -149,6 +150,20 @@ int spect_sensitivity(const spect_plan *plan, const float *mu, float *sens,
 int osem_subset_step(const spect_plan *plan, float *f, const float *mu, const float *g,
                      const float *s_add, const float *sens_m, int32_t m, int32_t n_subsets,
                      void *ws, size_t ws_bytes, void *stream);
+
+/* A whole OSEM reconstruction f = A(L) (Section 2.1.3, Eq. 4 and Eq. 5 with
+ * the Table 1 OSEM preconditioner and Poisson gradient): computes the subset
+ * sensitivities H_m^T 1, then runs n_iters iterations, each visiting the
+ * interleaved subsets m = 0 .. n_subsets-1 in order with the update of
+ * osem_subset_step.  The attenuation offsets of each subset are computed once
+ * and reused by its sensitivity and every subiteration.  f: device
+ * (N, N, Nz), the initial image on entry (the paper leaves it open; 1
+ * everywhere is the usual choice) and the reconstruction on return; g, s_add,
+ * mu as in osem_subset_step.  The workspace (SPECT_OP_RECON, n_idx =
+ * n_subsets) also holds the M sensitivity volumes.  n_iters >= 0. */
+int osem_reconstruct(const spect_plan *plan, float *f, const float *mu, const float *g,
+                     const float *s_add, int32_t n_iters, int32_t n_subsets, void *ws,
+                     size_t ws_bytes, void *stream);
 
 /* Kernel timing, a tracing aid.  While enabled (process-wide), every kernel
  * the library launches is bracketed by two HIP events recorded on the

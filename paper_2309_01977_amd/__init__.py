@@ -5,9 +5,9 @@ OSEM subset update (Eq. 5, Table 1) run as hand-written gfx950 HIP kernels
 behind the C ABI in include/spect.h; this package is the thin Python binding
 (torch supplies device memory and streams) plus the OSEM driver loop.
 """
-from ._binding import (EXPORTS, KERNELS, LIB_PATH, OP_BACK, OP_FWD, OP_OSEM, OP_SENS, KernelTimer,
+from ._binding import (EXPORTS, KERNELS, LIB_PATH, OP_BACK, OP_FWD, OP_OSEM, OP_RECON, OP_SENS, KernelTimer,
                        Plan, SpectError, load_library, subset_angles)
-from .recon import osem, sensitivities
+from .recon import osem, osem_steps, sensitivities
 
-__all__ = ["Plan", "SpectError", "KernelTimer", "load_library", "osem", "sensitivities",
-           "subset_angles", "EXPORTS", "KERNELS", "LIB_PATH", "OP_FWD", "OP_BACK", "OP_SENS", "OP_OSEM"]
+__all__ = ["Plan", "SpectError", "KernelTimer", "load_library", "osem", "osem_steps", "sensitivities",
+           "subset_angles", "EXPORTS", "KERNELS", "LIB_PATH", "OP_FWD", "OP_BACK", "OP_SENS", "OP_OSEM", "OP_RECON"]

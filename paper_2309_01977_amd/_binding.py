@@ -21,10 +21,11 @@ SPECT_EINVAL = -1
 SPECT_ENOMEM = -2
 SPECT_EHIP = -3
 SPECT_EUNSUPPORTED = -4
-OP_FWD, OP_BACK, OP_SENS, OP_OSEM = 0, 1, 2, 3
+OP_FWD, OP_BACK, OP_SENS, OP_OSEM, OP_RECON = 0, 1, 2, 3, 4
 
 EXPORTS = ("spect_plan_create", "spect_plan_destroy", "spect_workspace_size", "spect_fwd",
-           "spect_back", "spect_sensitivity", "osem_subset_step", "spect_profile_enable",
+           "spect_back", "spect_sensitivity", "osem_subset_step", "osem_reconstruct",
+           "spect_profile_enable",
            "spect_profile_reset", "spect_profile_query", "spect_last_error")
 KERNELS = ("tau_prepass", "fwd_main", "fwd_reduce", "back_rot", "back_gather", "fill_zero")
 
@@ -65,6 +66,7 @@ def load_library(path: Optional[str] = None):
     lib.spect_back.argtypes = [vp, vp, vp, vp, i32p, i32, ctypes.c_int, vp, sz, vp]
     lib.spect_sensitivity.argtypes = [vp, vp, vp, i32p, i32, vp, sz, vp]
     lib.osem_subset_step.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, vp, sz, vp]
+    lib.osem_reconstruct.argtypes = [vp, vp, vp, vp, vp, i32, i32, vp, sz, vp]
     lib.spect_profile_enable.argtypes = [ctypes.c_int]
     lib.spect_profile_reset.argtypes = []
     lib.spect_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
@@ -247,6 +249,24 @@ class KernelTimer:
                 out[k] = (n.value, ms.value)
         _check(lib.spect_profile_reset())
         return out
+
+
+def _recon_method(self, g: torch.Tensor, n_iters: int, n_subsets: int,
+                  mu: Optional[torch.Tensor] = None, s_add: Optional[torch.Tensor] = None,
+                  f: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Whole OSEM reconstruction (osem_reconstruct); f holds the initial image
+    (1 everywhere if None) and receives the result."""
+    if f is None:
+        f = torch.ones(self.object_shape, dtype=torch.float32, device=g.device)
+    ws = self.workspace(OP_RECON, n_subsets, mu is not None)
+    _check(load_library().osem_reconstruct(
+        self._h, _ptr(f, self.object_shape, "f"), _ptr(mu, self.object_shape, "mu"),
+        _ptr(g, self.proj_shape, "g"), _ptr(s_add, self.proj_shape, "s_add"), int(n_iters),
+        int(n_subsets), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return f
+
+
+Plan.reconstruct = _recon_method
 
 
 def subset_angles(n_angles: int, n_subsets: int, m: int):

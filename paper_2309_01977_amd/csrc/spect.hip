@@ -1,39 +1,12 @@
-// spect.hip - gfx950 kernels and C ABI of the SPECT projector library.
-//
-// The operator is the parallel-hole SPECT system matrix of the paper (Section
-// 2.1.1, Eq. 1): per angle, rotate the object (bilinear, per axial slice),
-// attenuate along the rotated depth axis, blur every depth plane with its own
-// separable Gaussian collimator-detector kernel, and sum over depth.  The
-// transpose runs the same steps backwards.  include/spect.h states the
-// discretisation and the array layouts.
-//
-// Parallel decomposition (one launch covers a list of angles):
-//   workgroup = (angle, axial slab of 16 slices, depth chunk); thread (j', h)
-//   owns detector bin j' and axial rows 8h..8h+7 of the slab and walks the
-//   depth axis of its chunk from the detector side.  Per depth it samples the
-//   object (four bilinear corners, each a contiguous z-run), updates its
-//   running attenuation sum, blurs along the bin axis through LDS (the
-//   neighbouring bins belong to other threads), and scatters the axial blur
-//   of its own eight rows into registers that hold the slab's partial
-//   projection rows.  A reduction kernel adds the partial rows of
-//   neighbouring slabs and of the depth chunks.
-//   Depth chunks raise parallelism for small angle subsets; their
-//   attenuation offsets come from a pre-pass that walks each ray once.
-// Back projection:
-//   back_rot  : same workgroups; per depth, axial blur of the projection in
-//               registers, bin-axis blur through LDS, times exp(-tau); writes
-//               the rotated-frame volume Z of each angle to the workspace;
-//   back_gather: thread per (x, y, slab) gathers from the <= 3x3 rotated
-//               samples whose bilinear footprint covers the voxel, with the
-//               forward's own FP32 weights, so the pair is an exact transpose
-//               up to summation order; the OSEM update is fused here.
-// No MFMA: nothing on this path is a dense contraction.
-#include <hip/hip_runtime.h>
+// spect.hip - host side and C ABI of the SPECT projector library, plus the
+// kernels that do not depend on the blur-radius class (the blur-class kernels
+// are instantiated in spect_kmc.hip, compiled once per class).
+#define SPECT_HOST_TU
+#include "spect_device.h"
 
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
-#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -42,620 +15,7 @@
 
 #include "spect.h"
 
-namespace {
-
-constexpr int SLAB = 16;   // axial rows per workgroup
-constexpr int ROWS = 8;    // axial rows per thread
-constexpr int MAXL = 128;  // angles per launch
-
-struct AngleList {
-    int n;
-    int idx[MAXL];
-};
-
-// Device view of the plan tables.
-struct DevGeom {
-    const float2 *cs;   // [A] (cos, sin)
-    const float2 *xy0;  // [A][N] rotated-frame origin of ray j': X = X0 + i' cos, Y = Y0 + i' sin
-    const int *kdep;    // [A][N] blur radius per depth
-    const float *taps;  // [A][N][TS] one-sided taps g[0..K]
-    int N, Nz, A, TS;
-    float tau_scale;    // dx * log2(e): exp(-tau) = exp2(-tau_scale * (sum mu))
-};
-
-// --------------------------------------------------------------- helpers --
-
-struct Corners {
-    int o00, o10, o01, o11;      // element offsets of (x0,y0), (x0+1,y0), (x0,y0+1), (x0+1,y0+1)
-    float w00, w10, w01, w11;    // bilinear weights, 0 for corners outside the grid
-};
-
-// Bilinear footprint of point (X, Y) in an N x N slice with z-runs of length Nz.
-__device__ __forceinline__ Corners corners(float X, float Y, int N, int Nz)
-{
-    const float xf = floorf(X), yf = floorf(Y);
-    const int x0 = (int)xf, y0 = (int)yf;
-    const float fx = X - xf, fy = Y - yf;
-    const float gx = 1.f - fx, gy = 1.f - fy;
-    const bool vx0 = (unsigned)x0 < (unsigned)N, vx1 = (unsigned)(x0 + 1) < (unsigned)N;
-    const bool vy0 = (unsigned)y0 < (unsigned)N, vy1 = (unsigned)(y0 + 1) < (unsigned)N;
-    Corners c;
-    c.w00 = (vx0 && vy0) ? gx * gy : 0.f;
-    c.w10 = (vx1 && vy0) ? fx * gy : 0.f;
-    c.w01 = (vx0 && vy1) ? gx * fy : 0.f;
-    c.w11 = (vx1 && vy1) ? fx * fy : 0.f;
-    const int xa = min(max(x0, 0), N - 1), xb = min(max(x0 + 1, 0), N - 1);
-    const int ya = min(max(y0, 0), N - 1), yb = min(max(y0 + 1, 0), N - 1);
-    c.o00 = (xa * N + ya) * Nz;
-    c.o10 = (xb * N + ya) * Nz;
-    c.o01 = (xa * N + yb) * Nz;
-    c.o11 = (xb * N + yb) * Nz;
-    return c;
-}
-
-// Raw corner values of ROWS axial rows starting at kb: v[corner][row] for the
-// corners (x0,y0), (x0+1,y0), (x0,y0+1), (x0+1,y0+1).  Every load is issued
-// unconditionally (rows past Nz read a clamped, valid address and are zeroed
-// when combined), so all of them are in flight together.  Vector path:
-// Nz % 4 == 0 and a 16-byte aligned volume.
-struct Raw {
-    float v[4][ROWS];
-};
-
-template <bool VEC>
-__device__ __forceinline__ void load_raw(const float *__restrict__ vol, const Corners &c, int kb, int Nz, Raw &r)
-{
-    const int o[4] = {c.o00, c.o10, c.o01, c.o11};
-    if constexpr (VEC) {
-#pragma unroll
-        for (int q = 0; q < ROWS / 4; ++q) {
-            const int k = min(kb + 4 * q, Nz - 4);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float4 t = *reinterpret_cast<const float4 *>(vol + o[j] + k);
-                r.v[j][4 * q + 0] = t.x;
-                r.v[j][4 * q + 1] = t.y;
-                r.v[j][4 * q + 2] = t.z;
-                r.v[j][4 * q + 3] = t.w;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int rr = 0; rr < ROWS; ++rr) {
-            const int k = min(kb + rr, Nz - 1);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) r.v[j][rr] = vol[o[j] + k];
-        }
-    }
-}
-
-// Bilinear combination of raw corner values; rows >= Nz give 0.
-__device__ __forceinline__ void combine(const Raw &r, const Corners &c, int kb, int Nz, float (&v)[ROWS])
-{
-#pragma unroll
-    for (int rr = 0; rr < ROWS; ++rr) {
-        const float z = (kb + rr < Nz) ? 1.f : 0.f;
-        v[rr] = z * fmaf(c.w11, r.v[3][rr], fmaf(c.w01, r.v[2][rr], fmaf(c.w10, r.v[1][rr], c.w00 * r.v[0][rr])));
-    }
-}
-
-template <bool VEC>
-__device__ __forceinline__ void sample_rows(const float *__restrict__ vol, const Corners &c, int kb, int Nz,
-                                            float (&v)[ROWS])
-{
-    Raw r;
-    load_raw<VEC>(vol, c, kb, Nz, r);
-    combine(r, c, kb, Nz, v);
-}
-
-// Attenuation factors for one depth: exp(-dx (mu/2 + sum beyond)), then add
-// this depth's samples to the running sum.
-__device__ __forceinline__ void attenuate(const float (&m)[ROWS], float (&S)[ROWS], float scale,
-                                          float (&att)[ROWS])
-{
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-        att[r] = __builtin_amdgcn_exp2f(-scale * fmaf(0.5f, m[r], S[r]));
-        S[r] += m[r];
-    }
-}
-
-// LDS row buffers for the bin-axis blur: [buf][q][row][h] float4, row = j' + KMC,
-// KMC zero rows on each side.
-__device__ __forceinline__ int wb_index(int buf, int q, int row, int h, int nrows)
-{
-    return ((buf * 2 + q) * nrows + row) * 2 + h;
-}
-
-// Zero the KMC padding rows on both sides of both row buffers.
-template <int KMC>
-__device__ __forceinline__ void zero_padding(float4 *smem, int N, int nrows)
-{
-    if constexpr (KMC > 0) {
-        for (int i = threadIdx.x; i < 2 * 2 * 2 * KMC * 2; i += blockDim.x) {
-            const int hh = i & 1, rest = i >> 1;
-            const int prow = rest % (2 * KMC), bq = rest / (2 * KMC);
-            const int row = prow < KMC ? prow : prow + N;
-            smem[wb_index(bq >> 1, bq & 1, row, hh, nrows)] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-    }
-}
-
-// Bin-axis blur of the thread's 8 rows: U = g0 W(j') + sum_m g_m (W(j'-m) + W(j'+m)).
-__device__ __forceinline__ void blur_bins(const float4 *__restrict__ wb, int buf, int row, int h,
-                                          int nrows, int K, const float *__restrict__ g,
-                                          const float (&self)[ROWS], float (&u)[ROWS])
-{
-    const float g0 = g[0];
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) u[r] = g0 * self[r];
-    for (int m = 1; m <= K; ++m) {
-        const float gm = g[m];
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const float4 a = wb[wb_index(buf, q, row - m, h, nrows)];
-            const float4 b = wb[wb_index(buf, q, row + m, h, nrows)];
-            u[4 * q + 0] = fmaf(gm, a.x + b.x, u[4 * q + 0]);
-            u[4 * q + 1] = fmaf(gm, a.y + b.y, u[4 * q + 1]);
-            u[4 * q + 2] = fmaf(gm, a.z + b.z, u[4 * q + 2]);
-            u[4 * q + 3] = fmaf(gm, a.w + b.w, u[4 * q + 3]);
-        }
-    }
-}
-
-// Axial blur as a scatter: input row s (0..7) adds g(|l|) u[s] to output row
-// s + l, l in [-K, K]; acc[t] holds output row kb - KMC + t.
-template <int K, int KMC>
-__device__ __forceinline__ void zscatter(float (&acc)[ROWS + 2 * KMC], const float (&u)[ROWS],
-                                         const float *__restrict__ g)
-{
-    float gk[K + 1];
-#pragma unroll
-    for (int l = 0; l <= K; ++l) gk[l] = g[l];
-#pragma unroll
-    for (int s = 0; s < ROWS; ++s)
-#pragma unroll
-        for (int l = -K; l <= K; ++l) acc[s + l + KMC] = fmaf(gk[l < 0 ? -l : l], u[s], acc[s + l + KMC]);
-}
-
-template <int K, int KMC>
-struct ZScatter {
-    static __device__ __forceinline__ void run(int k, float (&acc)[ROWS + 2 * KMC], const float (&u)[ROWS],
-                                               const float *__restrict__ g)
-    {
-        if (k == K)
-            zscatter<K, KMC>(acc, u, g);
-        else
-            ZScatter<K - 1, KMC>::run(k, acc, u, g);
-    }
-};
-template <int KMC>
-struct ZScatter<-1, KMC> {
-    static __device__ __forceinline__ void run(int, float (&)[ROWS + 2 * KMC], const float (&)[ROWS],
-                                               const float *__restrict__)
-    {
-    }
-};
-
-// Axial blur as a gather from a column of LDS values: win[t] is axial row
-// kb - K + t; out[s] = sum_l g(|l|) win[s + K - l].
-template <int K>
-__device__ __forceinline__ void zgather(const float *__restrict__ win, const float *__restrict__ g,
-                                        float (&out)[ROWS])
-{
-    float v[ROWS + 2 * K];
-#pragma unroll
-    for (int t = 0; t < ROWS + 2 * K; ++t) v[t] = win[t];
-    float gk[K + 1];
-#pragma unroll
-    for (int l = 0; l <= K; ++l) gk[l] = g[l];
-#pragma unroll
-    for (int s = 0; s < ROWS; ++s) {
-        float a = gk[0] * v[s + K];
-#pragma unroll
-        for (int l = 1; l <= K; ++l) a = fmaf(gk[l], v[s + K - l] + v[s + K + l], a);
-        out[s] = a;
-    }
-}
-
-template <int K>
-struct ZGather {
-    static __device__ __forceinline__ void run(int k, const float *__restrict__ col, int base,
-                                               const float *__restrict__ g, float (&out)[ROWS])
-    {
-        if (k == K)
-            zgather<K>(col + base - K, g, out);
-        else
-            ZGather<K - 1>::run(k, col, base, g, out);
-    }
-};
-template <>
-struct ZGather<-1> {
-    static __device__ __forceinline__ void run(int, const float *__restrict__, int, const float *__restrict__,
-                                               float (&)[ROWS])
-    {
-    }
-};
-
-// ----------------------------------------------------------- attenuation --
-
-struct TauArgs {
-    DevGeom g;
-    AngleList L;
-    const float *mu;
-    float *tau;      // [L][nchunk][N][Nz]: sum of mu samples over the depths of chunk c
-    int nchunk, dchunk;
-    int vec;
-};
-
-// One thread per (angle, chunk, bin, 8 axial rows): sum the attenuation
-// samples of the chunk's depths.  Chunk c covers depths
-// [N - (c+1) D, N - c D); chunk 0 touches the detector.  A chunk's starting
-// attenuation is the sum of the partial sums of the chunks nearer the
-// detector (the last chunk's own sum is never needed).
-template <bool VEC>
-__global__ __launch_bounds__(256) void tau_prepass(TauArgs a)
-{
-    const int N = a.g.N, Nz = a.g.Nz;
-    const int ngrp = (Nz + ROWS - 1) / ROWS;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= N * ngrp) return;
-    const int ch = blockIdx.y, al = blockIdx.z;
-    const int ang = a.L.idx[al];
-    const int jp = t / ngrp, kb = (t % ngrp) * ROWS;
-    const float2 cs = a.g.cs[ang];
-    const float2 o = a.g.xy0[(size_t)ang * N + jp];
-    float S[ROWS];
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) S[r] = 0.f;
-    const int ihi = N - ch * a.dchunk - 1;
-    const int ilo = max(0, N - (ch + 1) * a.dchunk);
-#pragma unroll 2
-    for (int ip = ihi; ip >= ilo; --ip) {
-        const Corners c = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, Nz);
-        float m[ROWS];
-        sample_rows<VEC>(a.mu, c, kb, Nz, m);
-#pragma unroll
-        for (int r = 0; r < ROWS; ++r) S[r] += m[r];
-    }
-    float *dst = a.tau + (((size_t)al * a.nchunk + ch) * N + jp) * Nz;
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r)
-        if (kb + r < Nz) dst[kb + r] = S[r];
-}
-
-// Attenuation sum at the detector side of chunk `chunk`: the partial sums of
-// chunks 0 .. chunk-1.
-__device__ __forceinline__ void chunk_start(const float *__restrict__ tau, int al, int nchunk, int chunk, int N,
-                                            int Nz, int jp, int kb, float (&S)[ROWS])
-{
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) S[r] = 0.f;
-    for (int c = 0; c < chunk; ++c) {
-        const float *src = tau + (((size_t)al * nchunk + c) * N + jp) * Nz;
-#pragma unroll
-        for (int r = 0; r < ROWS; ++r) S[r] += (kb + r < Nz) ? src[kb + r] : 0.f;
-    }
-}
-
-// ------------------------------------------------------------- forward ----
-
-struct FwdArgs {
-    DevGeom g;
-    AngleList L;
-    const float *f;
-    const float *mu;
-    const float *tau;   // chunk offsets or nullptr when nchunk == 1
-    float *part;        // [L][nslab][nchunk][N][SLAB + 2 KMC]
-    int nslab, nchunk, dchunk;
-    int vec;
-};
-
-template <bool MU, int KMC, bool VEC>
-__global__ __launch_bounds__(512) void fwd_main(FwdArgs a)
-{
-    extern __shared__ float4 smem[];
-    const int N = a.g.N, Nz = a.g.Nz;
-    const int slab = blockIdx.x, chunk = blockIdx.y, al = blockIdx.z;
-    const int ang = a.L.idx[al];
-    const int jp = threadIdx.x >> 1, h = threadIdx.x & 1;
-    const bool active = jp < N;
-    const int nrows = N + 2 * KMC;
-    const int kb = slab * SLAB + h * ROWS;
-
-    zero_padding<KMC>(smem, N, nrows);
-
-    const float2 cs = a.g.cs[ang];
-    const float2 o = active ? a.g.xy0[(size_t)ang * N + jp] : make_float2(0.f, 0.f);
-    float S[ROWS];
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) S[r] = 0.f;
-    if (MU && chunk > 0 && active) chunk_start(a.tau, al, a.nchunk, chunk, N, Nz, jp, kb, S);
-    float acc[ROWS + 2 * KMC];
-#pragma unroll
-    for (int t = 0; t < ROWS + 2 * KMC; ++t) acc[t] = 0.f;
-
-    const int ihi = N - chunk * a.dchunk - 1;
-    const int ilo = max(0, N - (chunk + 1) * a.dchunk);
-    const int *kd = a.g.kdep + (size_t)ang * N;
-    int buf = 0;
-    __syncthreads();
-    for (int ip = ihi; ip >= ilo; --ip) {
-        const int K = kd[ip];
-        const float *gt = a.g.taps + ((size_t)ang * N + ip) * a.g.TS;
-        float w[ROWS];
-        if (active) {
-            const Corners cn = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, Nz);
-            Raw rf, rm;
-            load_raw<VEC>(a.f, cn, kb, Nz, rf);
-            if (MU) load_raw<VEC>(a.mu, cn, kb, Nz, rm);
-            combine(rf, cn, kb, Nz, w);
-            if (MU) {
-                float m[ROWS], att[ROWS];
-                combine(rm, cn, kb, Nz, m);
-                attenuate(m, S, a.g.tau_scale, att);
-#pragma unroll
-                for (int r = 0; r < ROWS; ++r) w[r] *= att[r];
-            }
-            smem[wb_index(buf, 0, jp + KMC, h, nrows)] = make_float4(w[0], w[1], w[2], w[3]);
-            smem[wb_index(buf, 1, jp + KMC, h, nrows)] = make_float4(w[4], w[5], w[6], w[7]);
-        }
-        __syncthreads();
-        if (active) {
-            float u[ROWS];
-            blur_bins(smem, buf, jp + KMC, h, nrows, K, gt, w, u);
-            ZScatter<KMC, KMC>::run(K, acc, u, gt);
-        }
-        buf ^= 1;
-    }
-
-    // merge the two half-slabs of each bin and write the partial rows
-    __syncthreads();
-    float *mb = reinterpret_cast<float *>(smem);
-    constexpr int AC = ROWS + 2 * KMC;
-    constexpr int R = SLAB + 2 * KMC;
-    if (active && h == 1) {
-#pragma unroll
-        for (int t = 0; t < AC; ++t) mb[jp * (AC + 1) + t] = acc[t];
-    }
-    __syncthreads();
-    if (active && h == 0) {
-        float *dst = a.part + ((((size_t)al * a.nslab + slab) * a.nchunk + chunk) * N + jp) * R;
-#pragma unroll
-        for (int t = 0; t < R; t += 4) {
-            float v[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int tt = t + e;
-                float x = (tt < AC) ? acc[tt < AC ? tt : 0] : 0.f;
-                if (tt >= ROWS) x += mb[jp * (AC + 1) + tt - ROWS];
-                v[e] = x;
-            }
-            *reinterpret_cast<float4 *>(dst + t) = make_float4(v[0], v[1], v[2], v[3]);
-        }
-    }
-}
-
-struct ReduceArgs {
-    AngleList L;
-    const float *part;
-    int N, Nz, nslab, nchunk, kmc;
-    int mode;           // 0: write projection rows; 1: OSEM ratio into q
-    float *proj;        // mode 0: (A, N, Nz)
-    const float *g;     // mode 1: measured data (A, N, Nz)
-    const float *s_add; // mode 1: additive term or nullptr
-    float *q;           // mode 1: [L][N][Nz]
-};
-
-// Sum the partial rows of all chunks and overlapping slabs for one output
-// element (angle, bin, row).
-__global__ __launch_bounds__(256) void fwd_reduce(ReduceArgs a)
-{
-    const int N = a.N, Nz = a.Nz;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= N * Nz) return;
-    const int al = blockIdx.y;
-    const int ang = a.L.idx[al];
-    const int r = t / Nz, k = t % Nz;
-    const int R = SLAB + 2 * a.kmc;
-    const int slo = max(0, (k + a.kmc - R) / SLAB);  // loose bound; rows are checked below
-    const int shi = min(a.nslab - 1, (k + a.kmc) / SLAB);
-    float sum = 0.f;
-    for (int c = 0; c < a.nchunk; ++c)
-        for (int s = slo; s <= shi; ++s) {
-            const int row = k - s * SLAB + a.kmc;
-            if (row < 0 || row >= R) continue;
-            sum += a.part[((((size_t)al * a.nslab + s) * a.nchunk + c) * N + r) * R + row];
-        }
-    const size_t o = ((size_t)ang * N + r) * Nz + k;
-    if (a.mode == 0) {
-        a.proj[o] = sum;
-    } else {
-        const float e = a.s_add ? sum + a.s_add[o] : sum;
-        a.q[((size_t)al * N + r) * Nz + k] = e > 0.f ? a.g[o] / e : 0.f;
-    }
-}
-
-// ---------------------------------------------------------- back project --
-
-struct BackRotArgs {
-    DevGeom g;
-    AngleList L;
-    const float *y;     // projections; row of list entry al at y + row_index * N * Nz
-    int y_compact;      // 1: row_index = al (compact list buffer); 0: row_index = angle
-    int ones;           // 1: y is all ones (sensitivity)
-    const float *mu;
-    const float *tau;
-    float *z;           // [L][nslab][N][N][SLAB] rotated-frame values
-    int nslab, nchunk, dchunk;
-    int vec;
-};
-
-template <bool MU, int KMC, bool VEC>
-__global__ __launch_bounds__(512) void back_rot(BackRotArgs a)
-{
-    extern __shared__ float4 smem[];
-    const int N = a.g.N, Nz = a.g.Nz;
-    const int slab = blockIdx.x, chunk = blockIdx.y, al = blockIdx.z;
-    const int ang = a.L.idx[al];
-    const int jp = threadIdx.x >> 1, h = threadIdx.x & 1;
-    const bool active = jp < N;
-    const int nrows = N + 2 * KMC;
-    const int k0 = slab * SLAB;
-    const int kb = k0 + h * ROWS;
-    constexpr int R = SLAB + 2 * KMC;
-    constexpr int YP = R + 1;
-    float *ybuf = reinterpret_cast<float *>(smem + 2 * 2 * nrows * 2);
-
-    zero_padding<KMC>(smem, N, nrows);
-    // axial rows k0 - KMC .. k0 + SLAB + KMC - 1 of the projection, per bin
-    if (active) {
-        const float *yr = a.y + ((size_t)(a.y_compact ? al : ang) * N + jp) * Nz;
-        for (int t = h; t < R; t += 2) {
-            const int k = k0 - KMC + t;
-            float v = 0.f;
-            if (k >= 0 && k < Nz) v = a.ones ? 1.f : yr[k];
-            ybuf[jp * YP + t] = v;
-        }
-    }
-
-    const float2 cs = a.g.cs[ang];
-    const float2 o = active ? a.g.xy0[(size_t)ang * N + jp] : make_float2(0.f, 0.f);
-    float S[ROWS];
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) S[r] = 0.f;
-    if (MU && chunk > 0 && active) chunk_start(a.tau, al, a.nchunk, chunk, N, Nz, jp, kb, S);
-    const int ihi = N - chunk * a.dchunk - 1;
-    const int ilo = max(0, N - (chunk + 1) * a.dchunk);
-    const int *kd = a.g.kdep + (size_t)ang * N;
-    int buf = 0;
-    __syncthreads();
-    for (int ip = ihi; ip >= ilo; --ip) {
-        const int K = kd[ip];
-        const float *gt = a.g.taps + ((size_t)ang * N + ip) * a.g.TS;
-        float v[ROWS];
-        Corners cn;
-        Raw rm;
-        if (active) {
-            if (MU) {
-                // attenuation samples of this depth, in flight during the blur
-                cn = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, Nz);
-                load_raw<VEC>(a.mu, cn, kb, Nz, rm);
-            }
-            ZGather<KMC>::run(K, ybuf + jp * YP, h * ROWS + KMC, gt, v);
-            smem[wb_index(buf, 0, jp + KMC, h, nrows)] = make_float4(v[0], v[1], v[2], v[3]);
-            smem[wb_index(buf, 1, jp + KMC, h, nrows)] = make_float4(v[4], v[5], v[6], v[7]);
-        }
-        __syncthreads();
-        if (active) {
-            float u[ROWS];
-            blur_bins(smem, buf, jp + KMC, h, nrows, K, gt, v, u);
-            if (MU) {
-                float m[ROWS], att[ROWS];
-                combine(rm, cn, kb, Nz, m);
-                attenuate(m, S, a.g.tau_scale, att);
-#pragma unroll
-                for (int r = 0; r < ROWS; ++r) u[r] *= att[r];
-            }
-            float *dst = a.z + ((((size_t)al * a.nslab + slab) * N + ip) * N + jp) * SLAB + h * ROWS;
-            reinterpret_cast<float4 *>(dst)[0] = make_float4(u[0], u[1], u[2], u[3]);
-            reinterpret_cast<float4 *>(dst)[1] = make_float4(u[4], u[5], u[6], u[7]);
-        }
-        buf ^= 1;
-    }
-}
-
-struct GatherArgs {
-    DevGeom g;
-    AngleList L;
-    const float *z;
-    int nslab;
-    int mode;            // 0: out = sum; 1: out += sum; 2: OSEM update of out with sens
-    float *out;
-    const float *sens;
-};
-
-// Transpose of the bilinear rotation, as a gather.  Workgroup = 8 x 8 object
-// columns x one slab; a wave covers 16 columns and four lanes share a column,
-// one per 16-byte quad of its 16 axial rows, so that every candidate brick
-// (64 bytes) is read by four adjacent lanes.  For each angle a column takes
-// the <= 3 x 3 rotated samples around its rotated position; the weight of
-// sample P is the bilinear hat max(0, 1 - |X_P - x|) max(0, 1 - |Y_P - y|),
-// with X_P, Y_P computed by the forward's own FP32 expression, so the weights
-// equal the forward's to within one rounding.
-constexpr int GT = 8;  // gather tile edge
-
-__global__ __launch_bounds__(256) void back_gather(GatherArgs a)
-{
-    const int N = a.g.N, Nz = a.g.Nz;
-    const int tiles = (N + GT - 1) / GT;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int col = lane >> 2, q = lane & 3;
-    const int x = (blockIdx.x / tiles) * GT + wave * 2 + (col >> 3);
-    const int y = (blockIdx.x % tiles) * GT + (col & 7);
-    const int slab = blockIdx.y;
-    if (x >= N || y >= N) return;
-    const float c = 0.5f * (float)(N - 1);
-    const float xx = (float)x - c, yy = (float)y - c;
-    const float fxv = (float)x, fyv = (float)y;
-    float acc[4] = {0.f, 0.f, 0.f, 0.f};
-    const size_t zstride = (size_t)a.nslab * N * N * SLAB;
-    const float *zq = a.z + (size_t)slab * N * N * SLAB + 4 * q;
-    for (int al = 0; al < a.L.n; ++al) {
-        const int ang = a.L.idx[al];
-        const float2 cs = a.g.cs[ang];
-        const float2 *xy0 = a.g.xy0 + (size_t)ang * N;
-        const float wdw = fabsf(cs.x) + fabsf(cs.y) + 1e-3f;
-        const float ic = c + cs.x * xx + cs.y * yy;
-        const float jc = c - cs.y * xx + cs.x * yy;
-        const int ilo = (int)ceilf(ic - wdw), jlo = (int)ceilf(jc - wdw);
-        const float *zb = zq + (size_t)al * zstride;
-        float2 o[3];
-        float4 v[9];
-#pragma unroll
-        for (int dj = 0; dj < 3; ++dj) o[dj] = xy0[min(max(jlo + dj, 0), N - 1)];
-#pragma unroll
-        for (int d = 0; d < 9; ++d) {
-            const int ipc = min(max(ilo + d / 3, 0), N - 1), jpc = min(max(jlo + d % 3, 0), N - 1);
-            v[d] = *reinterpret_cast<const float4 *>(zb + ((size_t)ipc * N + jpc) * SLAB);
-        }
-#pragma unroll
-        for (int d = 0; d < 9; ++d) {
-            const int ip = ilo + d / 3, jp = jlo + d % 3;
-            const bool inr = (unsigned)ip < (unsigned)N && (unsigned)jp < (unsigned)N;
-            const float X = fmaf((float)ip, cs.x, o[d % 3].x), Y = fmaf((float)ip, cs.y, o[d % 3].y);
-            const float wx = fmaxf(0.f, 1.f - fabsf(X - fxv)), wy = fmaxf(0.f, 1.f - fabsf(Y - fyv));
-            const float w = inr ? wx * wy : 0.f;
-            acc[0] = fmaf(w, v[d].x, acc[0]);
-            acc[1] = fmaf(w, v[d].y, acc[1]);
-            acc[2] = fmaf(w, v[d].z, acc[2]);
-            acc[3] = fmaf(w, v[d].w, acc[3]);
-        }
-    }
-    const size_t base = ((size_t)x * N + y) * Nz;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int k = slab * SLAB + 4 * q + r;
-        if (k >= Nz) break;
-        float *p = a.out + base + k;
-        if (a.mode == 0) {
-            *p = acc[r];
-        } else if (a.mode == 1) {
-            *p += acc[r];
-        } else {
-            const float sv = a.sens[base + k];
-            if (sv > 0.f) *p = *p * acc[r] / sv;
-        }
-    }
-}
-
-__global__ __launch_bounds__(256) void fill_zero(float *p, size_t n)
-{
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0.f;
-}
-
-}  // namespace
+using namespace spectk;
 
 // ================================================================= host ===
 
@@ -887,6 +247,25 @@ size_t osem_q_bytes(const spect_plan *p, int M)
     return align256(sizeof(float) * (size_t)nl_max * p->N * p->Nz);
 }
 
+// Whole-reconstruction workspace: [sens: M volumes][tau table of each subset]
+// [q][tau scratch + max(partial, z)].
+size_t vol_bytes(const spect_plan *p) { return align256(sizeof(float) * (size_t)p->N * p->N * p->Nz); }
+
+size_t recon_tau_bytes(const spect_plan *p, int M, int m, bool mu)
+{
+    const int nl = (p->A - m + M - 1) / M;
+    return tau_bytes(p, tune(p, nl, mu, T_BOTH), nl, mu);
+}
+
+size_t osem_ws(const spect_plan *p, int M, bool mu);
+
+size_t recon_ws(const spect_plan *p, int M, bool mu)
+{
+    size_t b = (size_t)M * vol_bytes(p);
+    for (int m = 0; m < M; ++m) b += recon_tau_bytes(p, M, m, mu);
+    return b + osem_ws(p, M, mu);
+}
+
 size_t osem_ws(const spect_plan *p, int M, bool mu)
 {
     size_t b = 0;
@@ -898,51 +277,34 @@ size_t osem_ws(const spect_plan *p, int M, bool mu)
     return osem_q_bytes(p, M) + b;
 }
 
-typedef void (*KernelFn)(FwdArgs);
-typedef void (*BackFn)(BackRotArgs);
-
-template <bool MU, bool VEC>
-KernelFn fwd_kernel_k(int kmc)
-{
-    switch (kmc) {
-    case 0: return fwd_main<MU, 0, VEC>;
-    case 4: return fwd_main<MU, 4, VEC>;
-    case 8: return fwd_main<MU, 8, VEC>;
-    case 12: return fwd_main<MU, 12, VEC>;
-    case 16: return fwd_main<MU, 16, VEC>;
-    case 20: return fwd_main<MU, 20, VEC>;
-    case 24: return fwd_main<MU, 24, VEC>;
-    case 28: return fwd_main<MU, 28, VEC>;
-    default: return fwd_main<MU, 32, VEC>;
-    }
-}
-
 KernelFn fwd_kernel(bool mu, int kmc, bool vec)
 {
-    if (mu) return vec ? fwd_kernel_k<true, true>(kmc) : fwd_kernel_k<true, false>(kmc);
-    return vec ? fwd_kernel_k<false, true>(kmc) : fwd_kernel_k<false, false>(kmc);
-}
-
-template <bool MU, bool VEC>
-BackFn back_kernel_k(int kmc)
-{
     switch (kmc) {
-    case 0: return back_rot<MU, 0, VEC>;
-    case 4: return back_rot<MU, 4, VEC>;
-    case 8: return back_rot<MU, 8, VEC>;
-    case 12: return back_rot<MU, 12, VEC>;
-    case 16: return back_rot<MU, 16, VEC>;
-    case 20: return back_rot<MU, 20, VEC>;
-    case 24: return back_rot<MU, 24, VEC>;
-    case 28: return back_rot<MU, 28, VEC>;
-    default: return back_rot<MU, 32, VEC>;
+    case 0: return fwd_kernel_kmc0(mu, vec);
+    case 4: return fwd_kernel_kmc4(mu, vec);
+    case 8: return fwd_kernel_kmc8(mu, vec);
+    case 12: return fwd_kernel_kmc12(mu, vec);
+    case 16: return fwd_kernel_kmc16(mu, vec);
+    case 20: return fwd_kernel_kmc20(mu, vec);
+    case 24: return fwd_kernel_kmc24(mu, vec);
+    case 28: return fwd_kernel_kmc28(mu, vec);
+    default: return fwd_kernel_kmc32(mu, vec);
     }
 }
 
 BackFn back_kernel(bool mu, int kmc, bool vec)
 {
-    if (mu) return vec ? back_kernel_k<true, true>(kmc) : back_kernel_k<true, false>(kmc);
-    return vec ? back_kernel_k<false, true>(kmc) : back_kernel_k<false, false>(kmc);
+    switch (kmc) {
+    case 0: return back_kernel_kmc0(mu, vec);
+    case 4: return back_kernel_kmc4(mu, vec);
+    case 8: return back_kernel_kmc8(mu, vec);
+    case 12: return back_kernel_kmc12(mu, vec);
+    case 16: return back_kernel_kmc16(mu, vec);
+    case 20: return back_kernel_kmc20(mu, vec);
+    case 24: return back_kernel_kmc24(mu, vec);
+    case 28: return back_kernel_kmc28(mu, vec);
+    default: return back_kernel_kmc32(mu, vec);
+    }
 }
 
 int block_threads(int N) { return std::min(512, ((2 * N + 63) / 64) * 64); }
@@ -1355,6 +717,10 @@ int spect_workspace_size(const spect_plan *plan, int op, int32_t n_idx, int with
         if (n_idx > plan->A) return fail(SPECT_EINVAL, "n_subsets %d exceeds n_angles %d", n_idx, plan->A);
         *bytes = osem_ws(plan, n_idx, mu);
         break;
+    case SPECT_OP_RECON:
+        if (n_idx > plan->A) return fail(SPECT_EINVAL, "n_subsets %d exceeds n_angles %d", n_idx, plan->A);
+        *bytes = recon_ws(plan, n_idx, mu);
+        break;
     default: return fail(SPECT_EINVAL, "unknown op %d", op);
     }
     return ok();
@@ -1470,6 +836,62 @@ int osem_subset_step(const spect_plan *plan, float *f, const float *mu, const fl
     if ((st = run_back(plan, q, 1, 0, mu, L, rest, avail, reinterpret_cast<const float *>(rest), 2, f, sens_m,
                        vec, T_BOTH, s)))
         return st;
+    return ok();
+}
+
+int osem_reconstruct(const spect_plan *plan, float *f, const float *mu, const float *g, const float *s_add,
+                     int32_t n_iters, int32_t n_subsets, void *ws, size_t ws_bytes, void *stream)
+{
+    int st;
+    if ((st = check_plan(plan))) return st;
+    if ((st = check_ptr(f, "f", false)) || (st = check_ptr(mu, "mu", true)) || (st = check_ptr(g, "g", false)) ||
+        (st = check_ptr(s_add, "s_add", true)))
+        return st;
+    if (n_subsets < 1 || n_subsets > plan->A)
+        return fail(SPECT_EINVAL, "n_subsets = %d outside [1, %d]", n_subsets, plan->A);
+    if (n_iters < 0) return fail(SPECT_EINVAL, "n_iters = %d is negative", n_iters);
+    const int M = n_subsets;
+    const int nl_max = (plan->A + M - 1) / M;
+    if (nl_max > MAXL) return fail(SPECT_EUNSUPPORTED, "subsets of more than %d angles", MAXL);
+    if ((st = check_ws(ws, ws_bytes, recon_ws(plan, M, mu != nullptr)))) return st;
+    const bool vec = want_vec(plan, {f, mu});
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    const size_t vb = vol_bytes(plan);
+    std::vector<float *> sens(M);
+    std::vector<const float *> tau(M, nullptr);
+    size_t off = (size_t)M * vb;
+    for (int m = 0; m < M; ++m) sens[m] = reinterpret_cast<float *>(w + (size_t)m * vb);
+    std::vector<AngleList> lists(M);
+    for (int m = 0; m < M; ++m) {
+        std::vector<int> list;
+        for (int n = m; n < plan->A; n += M) list.push_back(n);
+        lists[m] = to_list(list.data(), (int)list.size());
+        const size_t tb = recon_tau_bytes(plan, M, m, mu != nullptr);
+        if (tb) {
+            float *t = reinterpret_cast<float *>(w + off);
+            launch_tau(plan, lists[m], tune(plan, lists[m].n, true, T_BOTH), mu, t, vec, s);
+            tau[m] = t;
+        }
+        off += tb;
+    }
+    float *q = reinterpret_cast<float *>(w + off);
+    const size_t qb = osem_q_bytes(plan, M);
+    char *rest = w + off + qb;
+    const size_t avail = ws_bytes - off - qb;
+    // subset sensitivities H_m^T 1 with each subset's attenuation offsets
+    for (int m = 0; m < M; ++m)
+        if ((st = run_back(plan, nullptr, 0, 1, mu, lists[m], rest, avail, tau[m], 0, sens[m], nullptr, vec, T_BOTH,
+                           s)))
+            return st;
+    for (int it = 0; it < n_iters; ++it)
+        for (int m = 0; m < M; ++m) {
+            if ((st = run_forward(plan, f, mu, lists[m], rest, avail, tau[m], 1, nullptr, g, s_add, q, vec, T_BOTH,
+                                  s)))
+                return st;
+            if ((st = run_back(plan, q, 1, 0, mu, lists[m], rest, avail, tau[m], 2, f, sens[m], vec, T_BOTH, s)))
+                return st;
+        }
     return ok();
 }
 
