@@ -155,12 +155,16 @@ int osem_subset_step(const spect_plan *plan, float *f, const float *mu, const fl
  * the Table 1 OSEM preconditioner and Poisson gradient): computes the subset
  * sensitivities H_m^T 1, then runs n_iters iterations, each visiting the
  * interleaved subsets m = 0 .. n_subsets-1 in order with the update of
- * osem_subset_step.  The attenuation offsets of each subset are computed once
- * and reused by its sensitivity and every subiteration.  f: device
- * (N, N, Nz), the initial image on entry (the paper leaves it open; 1
- * everywhere is the usual choice) and the reconstruction on return; g, s_add,
- * mu as in osem_subset_step.  The workspace (SPECT_OP_RECON, n_idx =
- * n_subsets) also holds the M sensitivity volumes.  n_iters >= 0. */
+ * osem_subset_step.  With an attenuation map, the sensitivity pass of each
+ * subset stores that subset's attenuation factors exp(-tau) (64 bytes per
+ * angle, 16-slice slab, depth and bin) in the workspace and every
+ * subiteration reads them back instead of resampling mu; if the tables of all
+ * subsets would exceed 32 GiB, each subset keeps only its depth-chunk
+ * attenuation offsets and every pass samples mu.  f: device (N, N, Nz), the
+ * initial image on entry (the paper leaves it open; 1 everywhere is the usual
+ * choice) and the reconstruction on return; g, s_add, mu as in
+ * osem_subset_step.  The workspace (SPECT_OP_RECON, n_idx = n_subsets) also
+ * holds the M sensitivity volumes.  n_iters >= 0. */
 int osem_reconstruct(const spect_plan *plan, float *f, const float *mu, const float *g,
                      const float *s_add, int32_t n_iters, int32_t n_subsets, void *ws,
                      size_t ws_bytes, void *stream);

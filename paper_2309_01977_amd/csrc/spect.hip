@@ -26,8 +26,8 @@ struct spect_plan {
     int kmc;    // compile-time radius class (multiple of 4, <= 32)
     int TS;     // tap row stride
     int device;
-    int fwd_slots[2];   // resident forward workgroups on the device, without / with attenuation
-    int back_slots[2];  // same for the rotated-frame back-projection kernel
+    int fwd_slots[4];   // resident forward workgroups on the device, per attenuation mode
+    int back_slots[4];  // same for the rotated-frame back-projection kernel
     void *dmem;
     DevGeom g;
 };
@@ -146,8 +146,11 @@ enum { T_FWD = 1, T_BACK = 2, T_BOTH = 3 };
 // minimises (waves of resident workgroups) x (depths per workgroup + a fixed
 // per-workgroup cost), summed over the kernels that share the split (both
 // passes of an OSEM step share the attenuation offsets).  Splitting adds an
-// attenuation pre-pass when a map is given.
-Tuning tune(const spect_plan *p, int n_list, bool mu, int which)
+// attenuation pre-pass when the kernels sample the attenuation map.
+bool samples_mu(int att) { return att == ATT_SAMPLE || att == ATT_WRITE; }
+int att_of(bool mu) { return mu ? ATT_SAMPLE : ATT_NONE; }
+
+Tuning tune(const spect_plan *p, int n_list, int att, int which)
 {
     Tuning t;
     t.nslab = (p->Nz + SLAB - 1) / SLAB;
@@ -162,9 +165,9 @@ Tuning tune(const spect_plan *p, int n_list, bool mu, int which)
         if (ncc != nc) continue;
         const long wgs = base * ncc;
         double cost = 0;
-        if (which & T_FWD) cost += (double)((wgs + p->fwd_slots[mu] - 1) / p->fwd_slots[mu]) * (D + 6);
-        if (which & T_BACK) cost += (double)((wgs + p->back_slots[mu] - 1) / p->back_slots[mu]) * (D + 6);
-        if (mu && ncc > 1) cost += 2 + D / 4.0;
+        if (which & T_FWD) cost += (double)((wgs + p->fwd_slots[att] - 1) / p->fwd_slots[att]) * (D + 6);
+        if (which & T_BACK) cost += (double)((wgs + p->back_slots[att] - 1) / p->back_slots[att]) * (D + 6);
+        if (samples_mu(att) && ncc > 1) cost += 2 + D / 4.0;
         if (cost < best - 1e-9) {
             best = cost;
             t.nchunk = ncc;
@@ -176,9 +179,9 @@ Tuning tune(const spect_plan *p, int n_list, bool mu, int which)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-size_t tau_bytes(const spect_plan *p, const Tuning &t, int n_list, bool mu)
+size_t tau_bytes(const spect_plan *p, const Tuning &t, int n_list, int att)
 {
-    if (!mu || t.nchunk <= 1) return 0;
+    if (!samples_mu(att) || t.nchunk <= 1) return 0;
     return align256(sizeof(float) * (size_t)n_list * t.nchunk * p->N * p->Nz);
 }
 
@@ -211,22 +214,22 @@ std::vector<int> batch_sizes(int n, int B)
     return v;
 }
 
-size_t fwd_need(const spect_plan *p, int nl, bool mu, int which = T_FWD)
+size_t fwd_need(const spect_plan *p, int nl, int att, int which = T_FWD)
 {
-    const Tuning t = tune(p, nl, mu, which);
-    return tau_bytes(p, t, nl, mu) + part_bytes(p, t, nl);
+    const Tuning t = tune(p, nl, att, which);
+    return tau_bytes(p, t, nl, att) + part_bytes(p, t, nl);
 }
 
-size_t back_need(const spect_plan *p, int nl, bool mu, int which = T_BACK)
+size_t back_need(const spect_plan *p, int nl, int att, int which = T_BACK)
 {
-    const Tuning t = tune(p, nl, mu, which);
-    return tau_bytes(p, t, nl, mu) + z_bytes(p, t, nl);
+    const Tuning t = tune(p, nl, att, which);
+    return tau_bytes(p, t, nl, att) + z_bytes(p, t, nl);
 }
 
 size_t fwd_ws(const spect_plan *p, int n_idx, bool mu)
 {
     size_t b = 0;
-    for (int nl : batch_sizes(std::max(n_idx, 1), MAXL)) b = std::max(b, fwd_need(p, nl, mu));
+    for (int nl : batch_sizes(std::max(n_idx, 1), MAXL)) b = std::max(b, fwd_need(p, nl, att_of(mu)));
     return b;
 }
 
@@ -234,7 +237,7 @@ size_t back_ws(const spect_plan *p, int n_idx, bool mu)
 {
     size_t b = 0;
     const int G = back_group(p, n_idx);
-    for (int nl : batch_sizes(std::max(n_idx, 1), G)) b = std::max(b, back_need(p, nl, mu));
+    for (int nl : batch_sizes(std::max(n_idx, 1), G)) b = std::max(b, back_need(p, nl, att_of(mu)));
     return b;
 }
 
@@ -247,14 +250,37 @@ size_t osem_q_bytes(const spect_plan *p, int M)
     return align256(sizeof(float) * (size_t)nl_max * p->N * p->Nz);
 }
 
-// Whole-reconstruction workspace: [sens: M volumes][tau table of each subset]
-// [q][tau scratch + max(partial, z)].
+// Whole-reconstruction workspace.  With an attenuation map the sensitivity
+// pass of each subset stores its attenuation factors in a table (the
+// rotated-frame brick layout, 64 bytes per angle, slab, depth and bin) and
+// every later pass reads it: [sens: M volumes][table of each subset][q]
+// [scratch].  Tables larger than kMaxTableBytes in total fall back to
+// sampling mu in every pass, keeping each subset's chunk offsets instead:
+// [sens][tau offsets of each subset][q][scratch].
+constexpr size_t kMaxTableBytes = size_t(32) << 30;
+
 size_t vol_bytes(const spect_plan *p) { return align256(sizeof(float) * (size_t)p->N * p->N * p->Nz); }
+
+int subset_size(const spect_plan *p, int M, int m) { return (p->A - m + M - 1) / M; }
+
+size_t table_bytes(const spect_plan *p, int nl)
+{
+    return align256(sizeof(float) * (size_t)nl * ((p->Nz + SLAB - 1) / SLAB) * p->N * p->N * SLAB);
+}
+
+bool use_table(const spect_plan *p, int M, bool mu)
+{
+    if (!mu) return false;
+    size_t b = 0;
+    for (int m = 0; m < M; ++m) b += table_bytes(p, subset_size(p, M, m));
+    return b <= kMaxTableBytes;
+}
 
 size_t recon_tau_bytes(const spect_plan *p, int M, int m, bool mu)
 {
-    const int nl = (p->A - m + M - 1) / M;
-    return tau_bytes(p, tune(p, nl, mu, T_BOTH), nl, mu);
+    const int nl = subset_size(p, M, m);
+    if (use_table(p, M, mu)) return table_bytes(p, nl);
+    return tau_bytes(p, tune(p, nl, att_of(mu), T_BOTH), nl, att_of(mu));
 }
 
 size_t osem_ws(const spect_plan *p, int M, bool mu);
@@ -263,7 +289,15 @@ size_t recon_ws(const spect_plan *p, int M, bool mu)
 {
     size_t b = (size_t)M * vol_bytes(p);
     for (int m = 0; m < M; ++m) b += recon_tau_bytes(p, M, m, mu);
-    return b + osem_ws(p, M, mu);
+    if (!use_table(p, M, mu)) return b + osem_ws(p, M, mu);
+    size_t scratch = 0;
+    for (int nl : {p->A / M, (p->A + M - 1) / M}) {
+        if (nl < 1) continue;
+        scratch = std::max(scratch, back_need(p, nl, ATT_WRITE, T_BACK));
+        scratch = std::max(scratch, fwd_need(p, nl, ATT_READ, T_BOTH));
+        scratch = std::max(scratch, back_need(p, nl, ATT_READ, T_BOTH));
+    }
+    return b + osem_q_bytes(p, M) + scratch;
 }
 
 size_t osem_ws(const spect_plan *p, int M, bool mu)
@@ -271,39 +305,39 @@ size_t osem_ws(const spect_plan *p, int M, bool mu)
     size_t b = 0;
     for (int nl : {p->A / M, (p->A + M - 1) / M}) {
         if (nl < 1) continue;
-        const Tuning t = tune(p, nl, mu, T_BOTH);
-        b = std::max(b, tau_bytes(p, t, nl, mu) + std::max(part_bytes(p, t, nl), z_bytes(p, t, nl)));
+        const Tuning t = tune(p, nl, att_of(mu), T_BOTH);
+        b = std::max(b, tau_bytes(p, t, nl, att_of(mu)) + std::max(part_bytes(p, t, nl), z_bytes(p, t, nl)));
     }
     return osem_q_bytes(p, M) + b;
 }
 
-KernelFn fwd_kernel(bool mu, int kmc, bool vec)
+KernelFn fwd_kernel(int att, int kmc, bool vec)
 {
     switch (kmc) {
-    case 0: return fwd_kernel_kmc0(mu, vec);
-    case 4: return fwd_kernel_kmc4(mu, vec);
-    case 8: return fwd_kernel_kmc8(mu, vec);
-    case 12: return fwd_kernel_kmc12(mu, vec);
-    case 16: return fwd_kernel_kmc16(mu, vec);
-    case 20: return fwd_kernel_kmc20(mu, vec);
-    case 24: return fwd_kernel_kmc24(mu, vec);
-    case 28: return fwd_kernel_kmc28(mu, vec);
-    default: return fwd_kernel_kmc32(mu, vec);
+    case 0: return fwd_kernel_kmc0(att, vec);
+    case 4: return fwd_kernel_kmc4(att, vec);
+    case 8: return fwd_kernel_kmc8(att, vec);
+    case 12: return fwd_kernel_kmc12(att, vec);
+    case 16: return fwd_kernel_kmc16(att, vec);
+    case 20: return fwd_kernel_kmc20(att, vec);
+    case 24: return fwd_kernel_kmc24(att, vec);
+    case 28: return fwd_kernel_kmc28(att, vec);
+    default: return fwd_kernel_kmc32(att, vec);
     }
 }
 
-BackFn back_kernel(bool mu, int kmc, bool vec)
+BackFn back_kernel(int att, int kmc, bool vec)
 {
     switch (kmc) {
-    case 0: return back_kernel_kmc0(mu, vec);
-    case 4: return back_kernel_kmc4(mu, vec);
-    case 8: return back_kernel_kmc8(mu, vec);
-    case 12: return back_kernel_kmc12(mu, vec);
-    case 16: return back_kernel_kmc16(mu, vec);
-    case 20: return back_kernel_kmc20(mu, vec);
-    case 24: return back_kernel_kmc24(mu, vec);
-    case 28: return back_kernel_kmc28(mu, vec);
-    default: return back_kernel_kmc32(mu, vec);
+    case 0: return back_kernel_kmc0(att, vec);
+    case 4: return back_kernel_kmc4(att, vec);
+    case 8: return back_kernel_kmc8(att, vec);
+    case 12: return back_kernel_kmc12(att, vec);
+    case 16: return back_kernel_kmc16(att, vec);
+    case 20: return back_kernel_kmc20(att, vec);
+    case 24: return back_kernel_kmc24(att, vec);
+    case 28: return back_kernel_kmc28(att, vec);
+    default: return back_kernel_kmc32(att, vec);
     }
 }
 
@@ -399,18 +433,19 @@ void launch_tau(const spect_plan *p, const AngleList &L, const Tuning &t, const 
 }
 
 // Forward projection of one list into partial rows, then the reduction.
+// att: ATT_NONE / ATT_SAMPLE (from mu) / ATT_READ (from table).
 // ws holds [tau][partial]; tau_given != nullptr reuses attenuation offsets
 // already computed for the same list (the tau region is then skipped).
-int run_forward(const spect_plan *p, const float *f, const float *mu, const AngleList &L, char *ws,
-                size_t ws_avail, const float *tau_given, int mode, float *proj, const float *g,
-                const float *s_add, float *q, bool vec, int which, hipStream_t st)
+int run_forward(const spect_plan *p, const float *f, const float *mu, int att, const float *table,
+                const AngleList &L, char *ws, size_t ws_avail, const float *tau_given, int mode, float *proj,
+                const float *g, const float *s_add, float *q, bool vec, int which, hipStream_t st)
 {
-    const Tuning t = tune(p, L.n, mu != nullptr, which);
-    if (fwd_need(p, L.n, mu != nullptr, which) > ws_avail)
+    const Tuning t = tune(p, L.n, att, which);
+    if (fwd_need(p, L.n, att, which) > ws_avail)
         return fail(SPECT_EINVAL, "workspace too small for a %d-angle forward launch", L.n);
     const float *tau = nullptr;
     size_t off = 0;
-    const size_t tb = tau_bytes(p, t, L.n, mu != nullptr);
+    const size_t tb = tau_bytes(p, t, L.n, att);
     if (tb) {
         off += tb;
         if (tau_given) {
@@ -427,12 +462,13 @@ int run_forward(const spect_plan *p, const float *f, const float *mu, const Angl
     a.f = f;
     a.mu = mu;
     a.tau = tau;
+    a.att = table;
     a.part = part;
     a.nslab = t.nslab;
     a.nchunk = t.nchunk;
     a.dchunk = t.dchunk;
     a.vec = vec;
-    KernelFn fk = fwd_kernel(mu != nullptr, p->kmc, vec);
+    KernelFn fk = fwd_kernel(att, p->kmc, vec);
     allow_smem(reinterpret_cast<const void *>(fk), fwd_smem(p));
     {
         ProfScope ps(K_FWD, st);
@@ -461,17 +497,18 @@ int run_forward(const spect_plan *p, const float *f, const float *mu, const Angl
 }
 
 // Back projection of one list: rotated-frame pass, then the gather.
-// ws holds [tau][z]; tau_given as in run_forward.
-int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const float *mu,
-             const AngleList &L, char *ws, size_t ws_avail, const float *tau_given, int mode, float *out,
-             const float *sens, bool vec, int which, hipStream_t st)
+// att: ATT_NONE / ATT_SAMPLE / ATT_WRITE (sample mu and fill table) /
+// ATT_READ (from table).  ws holds [tau][z]; tau_given as in run_forward.
+int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const float *mu, int att,
+             float *table, const AngleList &L, char *ws, size_t ws_avail, const float *tau_given, int mode,
+             float *out, const float *sens, bool vec, int which, hipStream_t st)
 {
-    const Tuning t = tune(p, L.n, mu != nullptr, which);
-    if (back_need(p, L.n, mu != nullptr, which) > ws_avail)
+    const Tuning t = tune(p, L.n, att, which);
+    if (back_need(p, L.n, att, which) > ws_avail)
         return fail(SPECT_EINVAL, "workspace too small for a %d-angle back-projection launch", L.n);
     const float *tau = nullptr;
     size_t off = 0;
-    const size_t tb = tau_bytes(p, t, L.n, mu != nullptr);
+    const size_t tb = tau_bytes(p, t, L.n, att);
     if (tb) {
         off += tb;
         if (tau_given) {
@@ -490,12 +527,13 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
     b.ones = ones;
     b.mu = mu;
     b.tau = tau;
+    b.att = table;
     b.z = z;
     b.nslab = t.nslab;
     b.nchunk = t.nchunk;
     b.dchunk = t.dchunk;
     b.vec = vec;
-    BackFn bk = back_kernel(mu != nullptr, p->kmc, vec);
+    BackFn bk = back_kernel(att, p->kmc, vec);
     allow_smem(reinterpret_cast<const void *>(bk), back_smem(p));
     {
         ProfScope ps(K_BACK_ROT, st);
@@ -677,18 +715,18 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cus < 1)
         cus = 256;
-    for (int mu = 0; mu < 2; ++mu) {
+    for (int att = ATT_NONE; att <= ATT_READ; ++att) {
         int nb = 0;
-        const void *fk = reinterpret_cast<const void *>(fwd_kernel(mu != 0, p->kmc, true));
+        const void *fk = reinterpret_cast<const void *>(fwd_kernel(att == ATT_WRITE ? ATT_SAMPLE : att, p->kmc, true));
         allow_smem(fk, fwd_smem(p));
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk, block_threads(N), fwd_smem(p)) != hipSuccess)
             nb = 1;
-        p->fwd_slots[mu] = std::max(1, nb) * cus;
-        const void *bk = reinterpret_cast<const void *>(back_kernel(mu != 0, p->kmc, true));
+        p->fwd_slots[att] = std::max(1, nb) * cus;
+        const void *bk = reinterpret_cast<const void *>(back_kernel(att, p->kmc, true));
         allow_smem(bk, back_smem(p));
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bk, block_threads(N), back_smem(p)) != hipSuccess)
             nb = 1;
-        p->back_slots[mu] = std::max(1, nb) * cus;
+        p->back_slots[att] = std::max(1, nb) * cus;
     }
     (void)hipGetLastError();
     *out = p;
@@ -743,7 +781,7 @@ int spect_fwd(const spect_plan *plan, const float *f, const float *mu, float *pr
     for (size_t b = 0; b < list.size(); b += MAXL) {
         const int n = (int)std::min<size_t>(MAXL, list.size() - b);
         const AngleList L = to_list(list.data() + b, n);
-        if ((st = run_forward(plan, f, mu, L, static_cast<char *>(ws), ws_bytes, nullptr, 0, proj, nullptr, nullptr,
+        if ((st = run_forward(plan, f, mu, att_of(mu), nullptr, L, static_cast<char *>(ws), ws_bytes, nullptr, 0, proj, nullptr, nullptr,
                               nullptr, vec, T_FWD, s)))
             return st;
     }
@@ -773,7 +811,7 @@ int spect_back(const spect_plan *plan, const float *proj, const float *mu, float
         const int n = (int)std::min<size_t>(G, list.size() - b);
         const AngleList L = to_list(list.data() + b, n);
         const int mode = (b == 0 && !accumulate) ? 0 : 1;
-        if ((st = run_back(plan, proj, 0, 0, mu, L, static_cast<char *>(ws), ws_bytes, nullptr, mode, f_out, nullptr, vec,
+        if ((st = run_back(plan, proj, 0, 0, mu, att_of(mu), nullptr, L, static_cast<char *>(ws), ws_bytes, nullptr, mode, f_out, nullptr, vec,
                             T_BACK, s)))
             return st;
     }
@@ -798,7 +836,7 @@ int spect_sensitivity(const spect_plan *plan, const float *mu, float *sens, cons
     for (size_t b = 0; b < list.size(); b += G) {
         const int n = (int)std::min<size_t>(G, list.size() - b);
         const AngleList L = to_list(list.data() + b, n);
-        if ((st = run_back(plan, nullptr, 0, 1, mu, L, static_cast<char *>(ws), ws_bytes, nullptr, b == 0 ? 0 : 1, sens,
+        if ((st = run_back(plan, nullptr, 0, 1, mu, att_of(mu), nullptr, L, static_cast<char *>(ws), ws_bytes, nullptr, b == 0 ? 0 : 1, sens,
                            nullptr, vec, T_BACK, s)))
             return st;
     }
@@ -830,10 +868,10 @@ int osem_subset_step(const spect_plan *plan, float *f, const float *mu, const fl
     const size_t qb = osem_q_bytes(plan, n_subsets);
     char *rest = w + qb;
     const size_t avail = ws_bytes - qb;
-    if ((st = run_forward(plan, f, mu, L, rest, avail, nullptr, 1, nullptr, g, s_add, q, vec, T_BOTH, s)))
+    if ((st = run_forward(plan, f, mu, att_of(mu), nullptr, L, rest, avail, nullptr, 1, nullptr, g, s_add, q, vec, T_BOTH, s)))
         return st;
     // same list, same tuning: the attenuation offsets at the start of rest are reused
-    if ((st = run_back(plan, q, 1, 0, mu, L, rest, avail, reinterpret_cast<const float *>(rest), 2, f, sens_m,
+    if ((st = run_back(plan, q, 1, 0, mu, att_of(mu), nullptr, L, rest, avail, reinterpret_cast<const float *>(rest), 2, f, sens_m,
                        vec, T_BOTH, s)))
         return st;
     return ok();
@@ -858,8 +896,9 @@ int osem_reconstruct(const spect_plan *plan, float *f, const float *mu, const fl
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *w = static_cast<char *>(ws);
     const size_t vb = vol_bytes(plan);
-    std::vector<float *> sens(M);
-    std::vector<const float *> tau(M, nullptr);
+    const bool table = use_table(plan, M, mu != nullptr);
+    const int att = table ? ATT_READ : att_of(mu != nullptr);
+    std::vector<float *> sens(M), per(M, nullptr);  // per subset: attenuation table or chunk offsets
     size_t off = (size_t)M * vb;
     for (int m = 0; m < M; ++m) sens[m] = reinterpret_cast<float *>(w + (size_t)m * vb);
     std::vector<AngleList> lists(M);
@@ -868,28 +907,33 @@ int osem_reconstruct(const spect_plan *plan, float *f, const float *mu, const fl
         for (int n = m; n < plan->A; n += M) list.push_back(n);
         lists[m] = to_list(list.data(), (int)list.size());
         const size_t tb = recon_tau_bytes(plan, M, m, mu != nullptr);
-        if (tb) {
-            float *t = reinterpret_cast<float *>(w + off);
-            launch_tau(plan, lists[m], tune(plan, lists[m].n, true, T_BOTH), mu, t, vec, s);
-            tau[m] = t;
-        }
+        if (tb) per[m] = reinterpret_cast<float *>(w + off);
+        if (tb && !table) launch_tau(plan, lists[m], tune(plan, lists[m].n, ATT_SAMPLE, T_BOTH), mu, per[m], vec, s);
         off += tb;
     }
     float *q = reinterpret_cast<float *>(w + off);
     const size_t qb = osem_q_bytes(plan, M);
     char *rest = w + off + qb;
     const size_t avail = ws_bytes - off - qb;
-    // subset sensitivities H_m^T 1 with each subset's attenuation offsets
-    for (int m = 0; m < M; ++m)
-        if ((st = run_back(plan, nullptr, 0, 1, mu, lists[m], rest, avail, tau[m], 0, sens[m], nullptr, vec, T_BOTH,
-                           s)))
-            return st;
+    // subset sensitivities H_m^T 1; with a table this pass also fills it
+    for (int m = 0; m < M; ++m) {
+        if (table)
+            st = run_back(plan, nullptr, 0, 1, mu, ATT_WRITE, per[m], lists[m], rest, avail, nullptr, 0, sens[m],
+                          nullptr, vec, T_BACK, s);
+        else
+            st = run_back(plan, nullptr, 0, 1, mu, att, nullptr, lists[m], rest, avail, per[m], 0, sens[m], nullptr,
+                          vec, T_BOTH, s);
+        if (st) return st;
+    }
     for (int it = 0; it < n_iters; ++it)
         for (int m = 0; m < M; ++m) {
-            if ((st = run_forward(plan, f, mu, lists[m], rest, avail, tau[m], 1, nullptr, g, s_add, q, vec, T_BOTH,
-                                  s)))
+            float *tab = table ? per[m] : nullptr;
+            const float *tau = table ? nullptr : per[m];
+            if ((st = run_forward(plan, f, mu, att, tab, lists[m], rest, avail, tau, 1, nullptr, g, s_add, q, vec,
+                                  T_BOTH, s)))
                 return st;
-            if ((st = run_back(plan, q, 1, 0, mu, lists[m], rest, avail, tau[m], 2, f, sens[m], vec, T_BOTH, s)))
+            if ((st = run_back(plan, q, 1, 0, mu, att, tab, lists[m], rest, avail, tau, 2, f, sens[m], vec, T_BOTH,
+                               s)))
                 return st;
         }
     return ok();

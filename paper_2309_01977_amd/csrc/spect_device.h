@@ -19,6 +19,11 @@
 //   neighbouring slabs and of the depth chunks.
 //   Depth chunks raise parallelism for small angle subsets; their
 //   attenuation offsets come from a pre-pass that walks each ray once.
+// Attenuation modes (template parameter ATT): none; sample mu and form
+// exp(-tau) in the kernel; the same and also store the factors in a table
+// laid out like the rotated-frame volume, [angle][slab][i'][j'][16]; read
+// the factors from that table.  A whole reconstruction writes the table once
+// per subset (its sensitivity pass) and every later pass streams it.
 // Back projection:
 //   back_rot  : same workgroups; per depth, axial blur of the projection in
 //               registers, bin-axis blur through LDS, times exp(-tau); writes
@@ -40,6 +45,16 @@ namespace spectk {
 constexpr int SLAB = 16;   // axial rows per workgroup
 constexpr int ROWS = 8;    // axial rows per thread
 constexpr int MAXL = 128;  // angles per launch
+
+enum AttMode { ATT_NONE = 0, ATT_SAMPLE = 1, ATT_WRITE = 2, ATT_READ = 3 };
+
+// Element offset of the 16 axial rows of (angle al, slab, depth i', bin j')
+// in a rotated-frame brick volume [L][nslab][N][N][16] (the back-projection
+// workspace and the attenuation table share this layout).
+__device__ __forceinline__ size_t brick_offset(int al, int nslab, int slab, int N, int ip, int jp)
+{
+    return ((((size_t)al * nslab + slab) * N + ip) * N + jp) * SLAB;
+}
 
 struct AngleList {
     int n;
@@ -369,14 +384,17 @@ struct FwdArgs {
     const float *f;
     const float *mu;
     const float *tau;   // chunk offsets or nullptr when nchunk == 1
+    const float *att;   // ATT_READ: attenuation table [L][nslab][N][N][16]
     float *part;        // [L][nslab][nchunk][N][SLAB + 2 KMC]
     int nslab, nchunk, dchunk;
     int vec;
 };
 
-template <bool MU, int KMC, bool VEC>
+template <int ATT, int KMC, bool VEC>
 __global__ __launch_bounds__(512) void fwd_main(FwdArgs a)
 {
+    static_assert(ATT != ATT_WRITE, "the forward kernel does not write the table");
+    constexpr bool MU = ATT == ATT_SAMPLE;
     extern __shared__ float4 smem[];
     const int N = a.g.N, Nz = a.g.Nz;
     const int slab = blockIdx.x, chunk = blockIdx.y, al = blockIdx.z;
@@ -411,9 +429,26 @@ __global__ __launch_bounds__(512) void fwd_main(FwdArgs a)
         if (active) {
             const Corners cn = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, Nz);
             Raw rf, rm;
+            float4 t0, t1;
             load_raw<VEC>(a.f, cn, kb, Nz, rf);
             if (MU) load_raw<VEC>(a.mu, cn, kb, Nz, rm);
+            if (ATT == ATT_READ) {
+                const float4 *src = reinterpret_cast<const float4 *>(
+                    a.att + brick_offset(al, a.nslab, slab, N, ip, jp) + h * ROWS);
+                t0 = src[0];
+                t1 = src[1];
+            }
             combine(rf, cn, kb, Nz, w, full);
+            if (ATT == ATT_READ) {
+                w[0] *= t0.x;
+                w[1] *= t0.y;
+                w[2] *= t0.z;
+                w[3] *= t0.w;
+                w[4] *= t1.x;
+                w[5] *= t1.y;
+                w[6] *= t1.z;
+                w[7] *= t1.w;
+            }
             if (MU) {
                 float m[ROWS], att[ROWS];
                 combine(rm, cn, kb, Nz, m, full);
@@ -514,14 +549,16 @@ struct BackRotArgs {
     int ones;           // 1: y is all ones (sensitivity)
     const float *mu;
     const float *tau;
+    float *att;         // ATT_WRITE / ATT_READ: attenuation table [L][nslab][N][N][16]
     float *z;           // [L][nslab][N][N][SLAB] rotated-frame values
     int nslab, nchunk, dchunk;
     int vec;
 };
 
-template <bool MU, int KMC, bool VEC>
+template <int ATT, int KMC, bool VEC>
 __global__ __launch_bounds__(512) void back_rot(BackRotArgs a)
 {
+    constexpr bool MU = ATT == ATT_SAMPLE || ATT == ATT_WRITE;
     extern __shared__ float4 smem[];
     const int N = a.g.N, Nz = a.g.Nz;
     const int slab = blockIdx.x, chunk = blockIdx.y, al = blockIdx.z;
@@ -565,11 +602,18 @@ __global__ __launch_bounds__(512) void back_rot(BackRotArgs a)
         float v[ROWS];
         Corners cn;
         Raw rm;
+        float4 t0, t1;
+        const size_t bo = brick_offset(al, a.nslab, slab, N, ip, jp) + h * ROWS;
         if (active) {
+            // attenuation samples (or factors) of this depth, in flight during the blur
             if (MU) {
-                // attenuation samples of this depth, in flight during the blur
                 cn = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, Nz);
                 load_raw<VEC>(a.mu, cn, kb, Nz, rm);
+            }
+            if (ATT == ATT_READ) {
+                const float4 *src = reinterpret_cast<const float4 *>(a.att + bo);
+                t0 = src[0];
+                t1 = src[1];
             }
             ZGather<KMC>::run(K, ybuf + jp * YP, h * ROWS + KMC, gt, v);
             smem[wb_index(buf, 0, jp + KMC, h, nrows)] = make_float4(v[0], v[1], v[2], v[3]);
@@ -586,8 +630,23 @@ __global__ __launch_bounds__(512) void back_rot(BackRotArgs a)
                 attenuate(m, S, a.g.tau_scale, att);
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r) u[r] *= att[r];
+                if (ATT == ATT_WRITE) {
+                    float4 *tb = reinterpret_cast<float4 *>(a.att + bo);
+                    tb[0] = make_float4(att[0], att[1], att[2], att[3]);
+                    tb[1] = make_float4(att[4], att[5], att[6], att[7]);
+                }
             }
-            float *dst = a.z + ((((size_t)al * a.nslab + slab) * N + ip) * N + jp) * SLAB + h * ROWS;
+            if (ATT == ATT_READ) {
+                u[0] *= t0.x;
+                u[1] *= t0.y;
+                u[2] *= t0.z;
+                u[3] *= t0.w;
+                u[4] *= t1.x;
+                u[5] *= t1.y;
+                u[6] *= t1.z;
+                u[7] *= t1.w;
+            }
+            float *dst = a.z + bo;
             reinterpret_cast<float4 *>(dst)[0] = make_float4(u[0], u[1], u[2], u[3]);
             reinterpret_cast<float4 *>(dst)[1] = make_float4(u[4], u[5], u[6], u[7]);
         }
@@ -695,9 +754,10 @@ __global__ __launch_bounds__(256) void fill_zero(float *p, size_t n)
 // own translation unit (spect_kmc.hip compiled with -DSPECT_KMC=<class>).
 typedef void (*KernelFn)(FwdArgs);
 typedef void (*BackFn)(BackRotArgs);
-#define SPECT_DECLARE_CLASS(K)                        \
-    KernelFn fwd_kernel_kmc##K(bool mu, bool vec); \
-    BackFn back_kernel_kmc##K(bool mu, bool vec);
+// att is an AttMode (the forward kernel has no ATT_WRITE variant).
+#define SPECT_DECLARE_CLASS(K)                       \
+    KernelFn fwd_kernel_kmc##K(int att, bool vec); \
+    BackFn back_kernel_kmc##K(int att, bool vec);
 SPECT_DECLARE_CLASS(0)
 SPECT_DECLARE_CLASS(4)
 SPECT_DECLARE_CLASS(8)

@@ -12,16 +12,25 @@
 
 namespace spectk {
 
-KernelFn SPECT_PASTE(fwd_kernel_kmc, SPECT_KMC)(bool mu, bool vec)
+KernelFn SPECT_PASTE(fwd_kernel_kmc, SPECT_KMC)(int att, bool vec)
 {
-    if (mu) return vec ? fwd_main<true, SPECT_KMC, true> : fwd_main<true, SPECT_KMC, false>;
-    return vec ? fwd_main<false, SPECT_KMC, true> : fwd_main<false, SPECT_KMC, false>;
+    switch (att) {
+    case ATT_NONE: return vec ? fwd_main<ATT_NONE, SPECT_KMC, true> : fwd_main<ATT_NONE, SPECT_KMC, false>;
+    case ATT_SAMPLE: return vec ? fwd_main<ATT_SAMPLE, SPECT_KMC, true> : fwd_main<ATT_SAMPLE, SPECT_KMC, false>;
+    case ATT_READ: return vec ? fwd_main<ATT_READ, SPECT_KMC, true> : fwd_main<ATT_READ, SPECT_KMC, false>;
+    default: return nullptr;
+    }
 }
 
-BackFn SPECT_PASTE(back_kernel_kmc, SPECT_KMC)(bool mu, bool vec)
+BackFn SPECT_PASTE(back_kernel_kmc, SPECT_KMC)(int att, bool vec)
 {
-    if (mu) return vec ? back_rot<true, SPECT_KMC, true> : back_rot<true, SPECT_KMC, false>;
-    return vec ? back_rot<false, SPECT_KMC, true> : back_rot<false, SPECT_KMC, false>;
+    switch (att) {
+    case ATT_NONE: return vec ? back_rot<ATT_NONE, SPECT_KMC, true> : back_rot<ATT_NONE, SPECT_KMC, false>;
+    case ATT_SAMPLE: return vec ? back_rot<ATT_SAMPLE, SPECT_KMC, true> : back_rot<ATT_SAMPLE, SPECT_KMC, false>;
+    case ATT_WRITE: return vec ? back_rot<ATT_WRITE, SPECT_KMC, true> : back_rot<ATT_WRITE, SPECT_KMC, false>;
+    case ATT_READ: return vec ? back_rot<ATT_READ, SPECT_KMC, true> : back_rot<ATT_READ, SPECT_KMC, false>;
+    default: return nullptr;
+    }
 }
 
 }  // namespace spectk
