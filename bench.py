@@ -61,24 +61,42 @@ def blur_radii(w):
     return out
 
 
-def algorithmic_counts(w, kernel):
-    """(FP32 FLOP, bytes) per voxel-angle of the method for one kernel.
+TABLE_LIMIT = 32 << 30   # the library keeps attenuation tables up to this total size
 
-    Forward: two bilinear samples (activity, attenuation: 7 FLOP each), the
-    attenuation exponent (5), the attenuated sample (1) and the separable
-    depth-dependent blur, 2 (2K+1) FLOP along each of the two detector axes;
-    bytes: the activity and attenuation samples (4 B each).
-    Adjoint rotated-frame pass: the same blur, one attenuation sample (7),
-    the exponent (5) and the product (1); bytes: attenuation sample + the
-    rotated-frame value handed to the gather (4 B each)."""
-    Ks = blur_radii(w)
-    blur = float(np.mean([4 * (2 * k + 1) for k in Ks]))
+
+def uses_att_table(w):
+    """Whether a whole reconstruction of w stores the attenuation factors of
+    every subset (64 B per angle, 16-slice slab, depth and bin) and reads
+    them back, as the library does while the tables fit in 32 GiB."""
+    slabs = -(-w.nz // 16)
+    return 4 * w.n_angles * slabs * 16 * w.n * w.n <= TABLE_LIMIT
+
+
+def recon_work(w, kernel, table):
+    """(FP32 FLOP, bytes) that `kernel` performs algorithmically over one
+    whole reconstruction (sensitivities + n_iters x n_subsets subiterations).
+
+    Per voxel-angle: the separable depth-dependent blur costs 2 (2K+1) FLOP
+    along each detector axis.  Forward, sampling mu: two bilinear samples
+    (activity, attenuation: 7 FLOP each), the attenuation exponent (5) and
+    the product (1); bytes: the two samples.  Forward, reading the factor
+    table: one bilinear sample (7) and the product (1); bytes: the sample and
+    the factor.  Rotated-frame adjoint pass, sampling mu: one bilinear sample
+    (7), the exponent (5) and the product (1); bytes: the mu sample and the
+    rotated-frame value handed to the gather (+ the stored factor when it
+    fills the table); reading the table: the product (1); bytes: factor and
+    rotated-frame value.  Gather: 9 bilinear candidates x (weight 9 + 1 FMA);
+    bytes: the rotated-frame value."""
+    blur = float(np.mean([4 * (2 * k + 1) for k in blur_radii(w)]))
+    va, it = float(w.voxel_angles), w.n_iters
     if kernel == "fwd_main":
-        return 20.0 + blur, 8.0
+        return (it * va * ((8.0 if table else 20.0) + blur), it * va * 8.0)
     if kernel == "back_rot":
-        return 13.0 + blur, 8.0
-    if kernel == "back_gather":   # 9 bilinear candidates x (weight 9 + 1 FMA) ; reads 9 x 4 B
-        return 9 * 11.0, 4.0
+        sens = (13.0 + blur, 12.0 if table else 8.0)
+        step = (1.0 + blur, 8.0) if table else (13.0 + blur, 8.0)
+        return (va * (sens[0] + it * step[0]), va * (sens[1] + it * step[1]))
+    if kernel == "back_gather":
+        return ((it + 1) * va * 99.0, (it + 1) * va * 4.0)
     return None, None
 
 
@@ -179,11 +197,13 @@ def main():
     kernels = {k: {"launches": n, "avg_ms": t / n, "share": t / sum(v[1] for v in kstats.values())}
                for k, (n, t) in kstats.items()}
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
-    flop_va, bytes_va = algorithmic_counts(w, dom)
-    per_launch_va = w.voxel_angles / w.n_subsets          # one subset of angles per launch
+    # per launch: one reconstruction's algorithmic work over its launches of
+    # the kernel, divided by the average launch duration
+    flop_r, bytes_r = recon_work(w, dom, uses_att_table(w))
+    per_recon = kernels[dom]["launches"] / 3
     dur = kernels[dom]["avg_ms"] * 1e-3
-    tflops = flop_va * per_launch_va / dur / 1e12
-    gbs = bytes_va * per_launch_va / dur / 1e9
+    tflops = flop_r / per_recon / dur / 1e12
+    gbs = bytes_r / per_recon / dur / 1e9
     traffic = traffic_record(dom)
     log(f"dominant kernel {dom}: {kernels[dom]['avg_ms'] * 1e3:.1f} us/launch, "
         f"{tflops:.1f} TFLOP/s, {gbs:.0f} GB/s algorithmic")

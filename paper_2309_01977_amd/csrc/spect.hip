@@ -638,8 +638,10 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
     if (!std::isfinite(g.psf_nsigma)) return fail(SPECT_EINVAL, "psf_nsigma must be finite");
     if (g.n > SPECT_MAX_N) return fail(SPECT_EUNSUPPORTED, "n = %d exceeds %d", g.n, SPECT_MAX_N);
     const double vol = (double)g.n * g.n * g.nz, prj = (double)g.n_angles * g.n * g.nz;
-    if (vol >= 2147483647.0 || prj >= 2147483647.0)
-        return fail(SPECT_EUNSUPPORTED, "object or projection element count exceeds 2^31");
+    // kernels address a volume with 32-bit byte offsets and 24-bit row products
+    if (vol >= 1073741824.0) return fail(SPECT_EUNSUPPORTED, "object of 2^30 voxels or more");
+    if (prj >= 2147483647.0) return fail(SPECT_EUNSUPPORTED, "projection element count exceeds 2^31");
+    if (g.nz >= (1 << 22)) return fail(SPECT_EUNSUPPORTED, "nz = %d is 2^22 or more", g.nz);
     std::vector<double> ang(g.n_angles), rad(g.n_angles);
     for (int i = 0; i < g.n_angles; ++i) {
         ang[i] = g.angles_deg ? g.angles_deg[i] : i * 360.0 / g.n_angles;

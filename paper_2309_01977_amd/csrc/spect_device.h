@@ -74,12 +74,30 @@ struct DevGeom {
 // --------------------------------------------------------------- helpers --
 
 struct Corners {
-    int o00, o10, o01, o11;      // element offsets of (x0,y0), (x0+1,y0), (x0,y0+1), (x0+1,y0+1)
-    float w00, w10, w01, w11;    // bilinear weights, 0 for corners outside the grid
+    uint32_t b00, b10, b01, b11;  // byte offsets of the z-runs of (x0,y0), (x0+1,y0), (x0,y0+1), (x0+1,y0+1)
+    float w00, w10, w01, w11;     // bilinear weights, 0 for corners outside the grid
 };
 
-// Bilinear footprint of point (X, Y) in an N x N slice with z-runs of length Nz.
-__device__ __forceinline__ Corners corners(float X, float Y, int N, int Nz)
+// Byte offsets of one volume row: rowb = 4 Nz (one z-run), per-thread axial
+// offsets dk0 / dk1 of its two quads of rows.  The plan guarantees that a
+// volume is below 4 GiB and that 4 Nz and N^2 fit 24 bits, so the offsets
+// are formed with 24-bit multiplies and used as 32-bit offsets from the
+// (uniform) volume base.
+struct RowGeom {
+    uint32_t rowb, dk0, dk1;
+};
+
+__device__ __forceinline__ RowGeom row_geom(int kb, int Nz)
+{
+    RowGeom r;
+    r.rowb = 4u * (uint32_t)Nz;
+    r.dk0 = 4u * (uint32_t)max(min(kb, Nz - 4), 0);
+    r.dk1 = 4u * (uint32_t)max(min(kb + 4, Nz - 4), 0);
+    return r;
+}
+
+// Bilinear footprint of point (X, Y) in an N x N slice of z-runs.
+__device__ __forceinline__ Corners corners(float X, float Y, int N, uint32_t rowb)
 {
     const float xf = floorf(X), yf = floorf(Y);
     const int x0 = (int)xf, y0 = (int)yf;
@@ -94,11 +112,20 @@ __device__ __forceinline__ Corners corners(float X, float Y, int N, int Nz)
     c.w11 = (vx1 && vy1) ? fx * fy : 0.f;
     const int xa = min(max(x0, 0), N - 1), xb = min(max(x0 + 1, 0), N - 1);
     const int ya = min(max(y0, 0), N - 1), yb = min(max(y0 + 1, 0), N - 1);
-    c.o00 = (xa * N + ya) * Nz;
-    c.o10 = (xb * N + ya) * Nz;
-    c.o01 = (xa * N + yb) * Nz;
-    c.o11 = (xb * N + yb) * Nz;
+    // (xb, yb) differ from (xa, ya) by 0 or 1 after clamping
+    c.b00 = __umul24(__umul24((uint32_t)xa, (uint32_t)N) + (uint32_t)ya, rowb);
+    const uint32_t dx = (xb != xa) ? __umul24((uint32_t)N, rowb) : 0u;
+    const uint32_t dy = (yb != ya) ? rowb : 0u;
+    c.b10 = c.b00 + dx;
+    c.b01 = c.b00 + dy;
+    c.b11 = c.b10 + dy;
     return c;
+}
+
+template <typename T>
+__device__ __forceinline__ const T &at_byte(const float *base, uint32_t off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
 }
 
 // Raw corner values of ROWS axial rows starting at kb: v[corner][row] for the
@@ -111,28 +138,30 @@ struct Raw {
 };
 
 template <bool VEC>
-__device__ __forceinline__ void load_raw(const float *__restrict__ vol, const Corners &c, int kb, int Nz, Raw &r)
+__device__ __forceinline__ void load_raw(const float *__restrict__ vol, const Corners &c, const RowGeom &rg, int kb,
+                                         int Nz, Raw &r)
 {
-    const int o[4] = {c.o00, c.o10, c.o01, c.o11};
+    const uint32_t o[4] = {c.b00, c.b10, c.b01, c.b11};
     if constexpr (VEC) {
 #pragma unroll
-        for (int q = 0; q < ROWS / 4; ++q) {
-            const int k = min(kb + 4 * q, Nz - 4);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float4 t = *reinterpret_cast<const float4 *>(vol + o[j] + k);
-                r.v[j][4 * q + 0] = t.x;
-                r.v[j][4 * q + 1] = t.y;
-                r.v[j][4 * q + 2] = t.z;
-                r.v[j][4 * q + 3] = t.w;
-            }
+        for (int j = 0; j < 4; ++j) {
+            const float4 t0 = at_byte<float4>(vol, o[j] + rg.dk0);
+            const float4 t1 = at_byte<float4>(vol, o[j] + rg.dk1);
+            r.v[j][0] = t0.x;
+            r.v[j][1] = t0.y;
+            r.v[j][2] = t0.z;
+            r.v[j][3] = t0.w;
+            r.v[j][4] = t1.x;
+            r.v[j][5] = t1.y;
+            r.v[j][6] = t1.z;
+            r.v[j][7] = t1.w;
         }
     } else {
 #pragma unroll
         for (int rr = 0; rr < ROWS; ++rr) {
-            const int k = min(kb + rr, Nz - 1);
+            const uint32_t k = 4u * (uint32_t)min(kb + rr, Nz - 1);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) r.v[j][rr] = vol[o[j] + k];
+            for (int j = 0; j < 4; ++j) r.v[j][rr] = at_byte<float>(vol, o[j] + k);
         }
     }
 }
@@ -152,11 +181,11 @@ __device__ __forceinline__ void combine(const Raw &r, const Corners &c, int kb, 
 }
 
 template <bool VEC>
-__device__ __forceinline__ void sample_rows(const float *__restrict__ vol, const Corners &c, int kb, int Nz,
-                                            float (&v)[ROWS])
+__device__ __forceinline__ void sample_rows(const float *__restrict__ vol, const Corners &c, const RowGeom &rg,
+                                            int kb, int Nz, float (&v)[ROWS])
 {
     Raw r;
-    load_raw<VEC>(vol, c, kb, Nz, r);
+    load_raw<VEC>(vol, c, rg, kb, Nz, r);
     combine(r, c, kb, Nz, v);
 }
 
@@ -193,17 +222,33 @@ __device__ __forceinline__ void zero_padding(float4 *smem, int N, int nrows)
     }
 }
 
+// Binary dispatch of a run-time blur radius k in [LO, HI] to f.template
+// go<k>(): about log2(HI - LO + 1) scalar branches per call.
+template <int LO, int HI>
+struct KSwitch {
+    template <class F>
+    static __device__ __forceinline__ void run(int k, F &f)
+    {
+        if constexpr (LO == HI) {
+            f.template go<LO>();
+        } else {
+            constexpr int MID = (LO + HI) / 2;
+            if (k <= MID)
+                KSwitch<LO, MID>::run(k, f);
+            else
+                KSwitch<MID + 1, HI>::run(k, f);
+        }
+    }
+};
+
 // Bin-axis blur of the thread's 8 rows with a compile-time radius:
 // U = g0 W(j') + sum_m g_m (W(j'-m) + W(j'+m)); i0/i1 index the thread's two
 // float4 of row j' in the row buffer (row stride 2 float4), so every read
 // uses an immediate offset.
 template <int K>
-__device__ __forceinline__ void blur_bins(const float4 *__restrict__ wb, int i0, int i1, const float *__restrict__ g,
+__device__ __forceinline__ void blur_bins(const float4 *__restrict__ wb, int i0, int i1, const float (&gk)[K + 1],
                                           const float (&self)[ROWS], float (&u)[ROWS])
 {
-    float gk[K + 1];
-#pragma unroll
-    for (int m = 0; m <= K; ++m) gk[m] = g[m];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) u[r] = gk[0] * self[r];
 #pragma unroll
@@ -222,96 +267,82 @@ __device__ __forceinline__ void blur_bins(const float4 *__restrict__ wb, int i0,
 }
 
 template <int K>
-struct BlurBins {
-    static __device__ __forceinline__ void run(int k, const float4 *__restrict__ wb, int i0, int i1,
-                                               const float *__restrict__ g, const float (&self)[ROWS],
-                                               float (&u)[ROWS])
-    {
-        if (k == K)
-            blur_bins<K>(wb, i0, i1, g, self, u);
-        else
-            BlurBins<K - 1>::run(k, wb, i0, i1, g, self, u);
-    }
-};
-template <>
-struct BlurBins<-1> {
-    static __device__ __forceinline__ void run(int, const float4 *__restrict__, int, int, const float *__restrict__,
-                                               const float (&)[ROWS], float (&)[ROWS])
-    {
-    }
-};
+__device__ __forceinline__ void load_taps(const float *__restrict__ g, float (&gk)[K + 1])
+{
+#pragma unroll
+    for (int m = 0; m <= K; ++m) gk[m] = g[m];
+}
 
 // Axial blur as a scatter: input row s (0..7) adds g(|l|) u[s] to output row
 // s + l, l in [-K, K]; acc[t] holds output row kb - KMC + t.
 template <int K, int KMC>
 __device__ __forceinline__ void zscatter(float (&acc)[ROWS + 2 * KMC], const float (&u)[ROWS],
-                                         const float *__restrict__ g)
+                                         const float (&gk)[K + 1])
 {
-    float gk[K + 1];
-#pragma unroll
-    for (int l = 0; l <= K; ++l) gk[l] = g[l];
 #pragma unroll
     for (int s = 0; s < ROWS; ++s)
 #pragma unroll
         for (int l = -K; l <= K; ++l) acc[s + l + KMC] = fmaf(gk[l < 0 ? -l : l], u[s], acc[s + l + KMC]);
 }
 
-template <int K, int KMC>
-struct ZScatter {
-    static __device__ __forceinline__ void run(int k, float (&acc)[ROWS + 2 * KMC], const float (&u)[ROWS],
-                                               const float *__restrict__ g)
-    {
-        if (k == K)
-            zscatter<K, KMC>(acc, u, g);
-        else
-            ZScatter<K - 1, KMC>::run(k, acc, u, g);
-    }
-};
+// Forward, after the row buffer of a depth is complete: bin-axis blur, then
+// the axial scatter into the partial rows, with one dispatch on the radius.
 template <int KMC>
-struct ZScatter<-1, KMC> {
-    static __device__ __forceinline__ void run(int, float (&)[ROWS + 2 * KMC], const float (&)[ROWS],
-                                               const float *__restrict__)
+struct FwdBlur {
+    float (&acc)[ROWS + 2 * KMC];
+    const float (&w)[ROWS];
+    const float4 *wb;
+    int i0, i1;
+    const float *g;
+    template <int K>
+    __device__ __forceinline__ void go()
     {
+        float gk[K + 1], u[ROWS];
+        load_taps<K>(g, gk);
+        blur_bins<K>(wb, i0, i1, gk, w, u);
+        zscatter<K, KMC>(acc, u, gk);
     }
 };
 
-// Axial blur as a gather from a column of LDS values: win[t] is axial row
-// kb - K + t; out[s] = sum_l g(|l|) win[s + K - l].
-template <int K>
-__device__ __forceinline__ void zgather(const float *__restrict__ win, const float *__restrict__ g,
-                                        float (&out)[ROWS])
-{
-    float v[ROWS + 2 * K];
-#pragma unroll
-    for (int t = 0; t < ROWS + 2 * K; ++t) v[t] = win[t];
-    float gk[K + 1];
-#pragma unroll
-    for (int l = 0; l <= K; ++l) gk[l] = g[l];
-#pragma unroll
-    for (int s = 0; s < ROWS; ++s) {
-        float a = gk[0] * v[s + K];
-#pragma unroll
-        for (int l = 1; l <= K; ++l) a = fmaf(gk[l], v[s + K - l] + v[s + K + l], a);
-        out[s] = a;
+// Adjoint, bin-axis blur of the row buffer.
+struct BackBlur {
+    const float (&v)[ROWS];
+    float (&u)[ROWS];
+    const float4 *wb;
+    int i0, i1;
+    const float *g;
+    template <int K>
+    __device__ __forceinline__ void go()
+    {
+        float gk[K + 1];
+        load_taps<K>(g, gk);
+        blur_bins<K>(wb, i0, i1, gk, v, u);
     }
-}
+};
 
-template <int K>
+// Axial blur as a gather from a column of LDS values: col[base - K + t] is
+// axial row kb - K + t; out[s] = sum_l g(|l|) win[s + K - l].
 struct ZGather {
-    static __device__ __forceinline__ void run(int k, const float *__restrict__ col, int base,
-                                               const float *__restrict__ g, float (&out)[ROWS])
+    const float *col;
+    int base;
+    const float *g;
+    float (&out)[ROWS];
+    template <int K>
+    __device__ __forceinline__ void go()
     {
-        if (k == K)
-            zgather<K>(col + base - K, g, out);
-        else
-            ZGather<K - 1>::run(k, col, base, g, out);
-    }
-};
-template <>
-struct ZGather<-1> {
-    static __device__ __forceinline__ void run(int, const float *__restrict__, int, const float *__restrict__,
-                                               float (&)[ROWS])
-    {
+        const float *win = col + base - K;
+        float v[ROWS + 2 * K];
+#pragma unroll
+        for (int t = 0; t < ROWS + 2 * K; ++t) v[t] = win[t];
+        float gk[K + 1];
+        load_taps<K>(g, gk);
+#pragma unroll
+        for (int s = 0; s < ROWS; ++s) {
+            float a = gk[0] * v[s + K];
+#pragma unroll
+            for (int l = 1; l <= K; ++l) a = fmaf(gk[l], v[s + K - l] + v[s + K + l], a);
+            out[s] = a;
+        }
     }
 };
 
@@ -348,11 +379,12 @@ __global__ __launch_bounds__(256) void tau_prepass(TauArgs a)
     for (int r = 0; r < ROWS; ++r) S[r] = 0.f;
     const int ihi = N - ch * a.dchunk - 1;
     const int ilo = max(0, N - (ch + 1) * a.dchunk);
+    const RowGeom rg = row_geom(kb, Nz);
 #pragma unroll 2
     for (int ip = ihi; ip >= ilo; --ip) {
-        const Corners c = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, Nz);
+        const Corners c = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, rg.rowb);
         float m[ROWS];
-        sample_rows<VEC>(a.mu, c, kb, Nz, m);
+        sample_rows<VEC>(a.mu, c, rg, kb, Nz, m);
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) S[r] += m[r];
     }
@@ -420,6 +452,10 @@ __global__ __launch_bounds__(512) void fwd_main(FwdArgs a)
     const int ihi = N - chunk * a.dchunk - 1;
     const int ilo = max(0, N - (chunk + 1) * a.dchunk);
     const int *kd = a.g.kdep + (size_t)ang * N;
+    const RowGeom rg = row_geom(kb, Nz);
+    // attenuation table: uniform base of this (angle, slab) + per-thread offset
+    const float *tab = ATT == ATT_READ ? a.att + brick_offset(al, a.nslab, slab, N, 0, 0) : nullptr;
+    const uint32_t toff = 4u * (uint32_t)(jp * SLAB + h * ROWS);
     int buf = 0;
     __syncthreads();
     for (int ip = ihi; ip >= ilo; --ip) {
@@ -427,16 +463,15 @@ __global__ __launch_bounds__(512) void fwd_main(FwdArgs a)
         const float *gt = a.g.taps + ((size_t)ang * N + ip) * a.g.TS;
         float w[ROWS];
         if (active) {
-            const Corners cn = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, Nz);
+            const Corners cn = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, rg.rowb);
             Raw rf, rm;
             float4 t0, t1;
-            load_raw<VEC>(a.f, cn, kb, Nz, rf);
-            if (MU) load_raw<VEC>(a.mu, cn, kb, Nz, rm);
+            load_raw<VEC>(a.f, cn, rg, kb, Nz, rf);
+            if (MU) load_raw<VEC>(a.mu, cn, rg, kb, Nz, rm);
             if (ATT == ATT_READ) {
-                const float4 *src = reinterpret_cast<const float4 *>(
-                    a.att + brick_offset(al, a.nslab, slab, N, ip, jp) + h * ROWS);
-                t0 = src[0];
-                t1 = src[1];
+                const float *trow = tab + (size_t)ip * N * SLAB;
+                t0 = at_byte<float4>(trow, toff);
+                t1 = at_byte<float4>(trow, toff + 16);
             }
             combine(rf, cn, kb, Nz, w, full);
             if (ATT == ATT_READ) {
@@ -461,10 +496,9 @@ __global__ __launch_bounds__(512) void fwd_main(FwdArgs a)
         }
         __syncthreads();
         if (active) {
-            float u[ROWS];
-            BlurBins<KMC>::run(K, smem, wb_index(buf, 0, jp + KMC, h, nrows), wb_index(buf, 1, jp + KMC, h, nrows),
-                               gt, w, u);
-            ZScatter<KMC, KMC>::run(K, acc, u, gt);
+            FwdBlur<KMC> op{acc, w, smem, wb_index(buf, 0, jp + KMC, h, nrows), wb_index(buf, 1, jp + KMC, h, nrows),
+                            gt};
+            KSwitch<0, KMC>::run(K, op);
         }
         buf ^= 1;
     }
@@ -594,6 +628,10 @@ __global__ __launch_bounds__(512) void back_rot(BackRotArgs a)
     const int ihi = N - chunk * a.dchunk - 1;
     const int ilo = max(0, N - (chunk + 1) * a.dchunk);
     const int *kd = a.g.kdep + (size_t)ang * N;
+    const RowGeom rg = row_geom(kb, Nz);
+    // table and rotated-frame bricks: uniform base of this (angle, slab) + per-thread offset
+    const size_t wg0 = brick_offset(al, a.nslab, slab, N, 0, 0);
+    const uint32_t toff = 4u * (uint32_t)(jp * SLAB + h * ROWS);
     int buf = 0;
     __syncthreads();
     for (int ip = ihi; ip >= ilo; --ip) {
@@ -603,27 +641,27 @@ __global__ __launch_bounds__(512) void back_rot(BackRotArgs a)
         Corners cn;
         Raw rm;
         float4 t0, t1;
-        const size_t bo = brick_offset(al, a.nslab, slab, N, ip, jp) + h * ROWS;
+        const size_t row0 = wg0 + (size_t)ip * N * SLAB;
         if (active) {
             // attenuation samples (or factors) of this depth, in flight during the blur
             if (MU) {
-                cn = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, Nz);
-                load_raw<VEC>(a.mu, cn, kb, Nz, rm);
+                cn = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, rg.rowb);
+                load_raw<VEC>(a.mu, cn, rg, kb, Nz, rm);
             }
             if (ATT == ATT_READ) {
-                const float4 *src = reinterpret_cast<const float4 *>(a.att + bo);
-                t0 = src[0];
-                t1 = src[1];
+                t0 = at_byte<float4>(a.att + row0, toff);
+                t1 = at_byte<float4>(a.att + row0, toff + 16);
             }
-            ZGather<KMC>::run(K, ybuf + jp * YP, h * ROWS + KMC, gt, v);
+            ZGather zg{ybuf + jp * YP, h * ROWS + KMC, gt, v};
+            KSwitch<0, KMC>::run(K, zg);
             smem[wb_index(buf, 0, jp + KMC, h, nrows)] = make_float4(v[0], v[1], v[2], v[3]);
             smem[wb_index(buf, 1, jp + KMC, h, nrows)] = make_float4(v[4], v[5], v[6], v[7]);
         }
         __syncthreads();
         if (active) {
             float u[ROWS];
-            BlurBins<KMC>::run(K, smem, wb_index(buf, 0, jp + KMC, h, nrows), wb_index(buf, 1, jp + KMC, h, nrows),
-                               gt, v, u);
+            BackBlur bb{v, u, smem, wb_index(buf, 0, jp + KMC, h, nrows), wb_index(buf, 1, jp + KMC, h, nrows), gt};
+            KSwitch<0, KMC>::run(K, bb);
             if (MU) {
                 float m[ROWS], att[ROWS];
                 combine(rm, cn, kb, Nz, m, full);
@@ -631,7 +669,7 @@ __global__ __launch_bounds__(512) void back_rot(BackRotArgs a)
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r) u[r] *= att[r];
                 if (ATT == ATT_WRITE) {
-                    float4 *tb = reinterpret_cast<float4 *>(a.att + bo);
+                    float4 *tb = reinterpret_cast<float4 *>(reinterpret_cast<char *>(a.att + row0) + toff);
                     tb[0] = make_float4(att[0], att[1], att[2], att[3]);
                     tb[1] = make_float4(att[4], att[5], att[6], att[7]);
                 }
@@ -646,9 +684,9 @@ __global__ __launch_bounds__(512) void back_rot(BackRotArgs a)
                 u[6] *= t1.z;
                 u[7] *= t1.w;
             }
-            float *dst = a.z + bo;
-            reinterpret_cast<float4 *>(dst)[0] = make_float4(u[0], u[1], u[2], u[3]);
-            reinterpret_cast<float4 *>(dst)[1] = make_float4(u[4], u[5], u[6], u[7]);
+            float4 *dst = reinterpret_cast<float4 *>(reinterpret_cast<char *>(a.z + row0) + toff);
+            dst[0] = make_float4(u[0], u[1], u[2], u[3]);
+            dst[1] = make_float4(u[4], u[5], u[6], u[7]);
         }
         buf ^= 1;
     }
