@@ -1,6 +1,11 @@
 """Benchmark of the SPECT OSEM hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--recon-only]
+
+--recon-only runs the data generation and the timed reconstructions only
+(no per-kernel timing, context passes or CPU baseline); hardware-counter
+runs use it so that every kernel they see after the data generation belongs
+to a reconstruction.
 
 Workload: OSEM at 128^3 voxels of 0.48 cm, 120 angles over 360 degrees,
 128 x 128 bins, attenuation map (water cylinder 0.15/cm, bone rod 0.25/cm,
@@ -23,7 +28,6 @@ pass).  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -39,10 +43,10 @@ if ROOT not in sys.path:
 
 import paper_2309_01977_amd as S  # noqa: E402
 from paper_2309_01977_amd import phantoms as P  # noqa: E402
+from paper_2309_01977_amd.traffic import source_digest  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-SOURCE = os.path.join(ROOT, "paper_2309_01977_amd", "csrc", "spect.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_osem_128cube_120ang.json")
 
 
@@ -112,12 +116,11 @@ def event_ms(fn, reps):
 
 
 def traffic_record(kernel):
-    """HBM bytes per launch measured with rocprofv3 counters, if they were
-    taken on the current kernel source."""
+    """HBM bytes per reconstruction launch of `kernel`, measured with
+    rocprofv3 counters, if they were taken on the current kernel sources."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
-        src = hashlib.sha256(open(SOURCE, "rb").read()).hexdigest()
-        if rec.get("source_sha256") != src:
+        if rec.get("source_sha256") != source_digest():
             return None
         return rec["kernels"].get(kernel, {}).get("hbm_bytes_per_launch")
     except (OSError, ValueError, KeyError):
@@ -145,6 +148,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--recon-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -157,6 +161,12 @@ def main():
     w = P.C2
     torch.cuda.set_device(0)
     S.load_library()
+    # traffic calibration reference for counter runs: one plain 256 MiB device copy
+    src = torch.zeros(64 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
     plan = S.Plan.for_workload(w)
     f_true, mu_np = P.make_phantom(w)
     mu = torch.from_numpy(mu_np).cuda()
@@ -187,6 +197,10 @@ def main():
     ms = float(per.mean())
     log(f"OSEM reconstruction: mean {ms:.3f} ms (events), {wall * 1e3 / args.steps:.3f} ms (wall)")
     value = w.voxel_angles * (w.n_iters + 0.5) / (ms * 1e-3)
+    if args.recon_only:
+        print(json.dumps({"metric": "OSEM reconstructions (recon-only run)", "ms_per_step": ms,
+                          "steps": args.steps, "warmup": args.warmup}), flush=True)
+        return
 
     # per-kernel durations from HIP events the library records on its stream
     with S.KernelTimer() as kt:
@@ -217,11 +231,6 @@ def main():
     t_fwd = event_ms(lambda: plan.forward(f, mu, out=proj), 10)
     t_adj = event_ms(lambda: plan.back(proj, mu, out=back), 10)
 
-    # traffic calibration reference: one plain 256 MiB device copy
-    src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
 
     out = {
         "metric": "voxel-angle projections/s (fwd+adj) at 128^3x120; OSEM recon p50/p99 latency",
