@@ -1,8 +1,11 @@
 """Benchmark of the SPECT OSEM hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--recon-only]
+                    [--workload osem|unrolled]
 
---recon-only runs the data generation and the timed reconstructions only
+The default workload (osem) is the headline measurement below;
+--workload unrolled measures the differentiable projector pair instead
+(bench_unrolled).  --recon-only runs the data generation and the timed reconstructions only
 (no per-kernel timing, context passes or CPU baseline); hardware-counter
 runs use it so that every kernel they see after the data generation belongs
 to a reconstruction.
@@ -127,11 +130,20 @@ def traffic_record(kernel):
         return None
 
 
-def cpu_baseline(w, f_true, mu, g):
-    """The FP64 oracle on the host: the same whole reconstruction."""
+def _oracle():
     from oracle import oracle as O
     O.build(force=False)
+    return O
+
+
+def cpu_baseline(w, f_true, mu):
+    """The FP64 oracle on the host: the same whole reconstruction, on data
+    it projects itself (the same phantom and noise stream)."""
+    O = _oracle()
     og = O.Geometry(w.n, w.nz, w.n_angles, w.voxel_cm, w.psf_a, w.psf_b, w.psf_nsigma)
+    _, noise = P.rngs(w.seed_index)
+    g = P.poisson_counts(O.forward(og, f_true.astype(np.float64), mu.astype(np.float64)),
+                         w.total_counts, noise)
     t0 = time.perf_counter()
     O.osem(og, g.astype(np.float64), mu.astype(np.float64), w.n_iters, w.n_subsets)
     dt = time.perf_counter() - t0
@@ -145,10 +157,11 @@ def cpu_baseline(w, f_true, mu, g):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--recon-only", action="store_true")
+    ap.add_argument("--workload", choices=("osem", "unrolled"), default="osem")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -157,8 +170,6 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU available", file=sys.stderr)
         sys.exit(2)
-
-    w = P.C2
     torch.cuda.set_device(0)
     S.load_library()
     # traffic calibration reference for counter runs: one plain 256 MiB device copy
@@ -167,6 +178,28 @@ def main():
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
+    if args.workload == "unrolled":
+        bench_unrolled(args)
+    else:
+        bench_osem(args)
+
+
+def kernel_stats(run, reps):
+    """Per-kernel launches and average duration from the library's own HIP
+    events on the launch stream, over `reps` runs of `run`."""
+    with S.KernelTimer() as kt:
+        for _ in range(reps):
+            run()
+        torch.cuda.synchronize()
+    kstats = kt.stats()
+    total = sum(v[1] for v in kstats.values())
+    return {k: {"launches": n, "avg_ms": t / n, "share": t / total} for k, (n, t) in kstats.items()}
+
+
+def bench_osem(args):
+    w = P.C2
+    args.steps = 20 if args.steps is None else args.steps
+    args.warmup = 3 if args.warmup is None else args.warmup
     plan = S.Plan.for_workload(w)
     f_true, mu_np = P.make_phantom(w)
     mu = torch.from_numpy(mu_np).cuda()
@@ -203,13 +236,7 @@ def main():
         return
 
     # per-kernel durations from HIP events the library records on its stream
-    with S.KernelTimer() as kt:
-        for _ in range(3):
-            step()
-        torch.cuda.synchronize()
-    kstats = kt.stats()
-    kernels = {k: {"launches": n, "avg_ms": t / n, "share": t / sum(v[1] for v in kstats.values())}
-               for k, (n, t) in kstats.items()}
+    kernels = kernel_stats(step, 3)
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     # per launch: one reconstruction's algorithmic work over its launches of
     # the kernel, divided by the average launch duration
@@ -262,7 +289,98 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(w, f_true, mu_np, g_np)
+        out["cpu_baseline"] = cpu_baseline(w, f_true, mu_np)
+    print(json.dumps(out), flush=True)
+
+
+
+def bench_unrolled(args):
+    """The differentiable workload: a batch of 8 torso phantoms at 128^3 with
+    120 angles; one step = loss and gradient of 10 unrolled OSEM
+    subiterations (8 subsets) from a uniform image, with checkpointing, loss =
+    mean squared error to the phantoms.  The subset sensitivities are
+    computed once before timing (they depend on geometry and mu only)."""
+    w, B, K = P.C4, P.C4_BATCH, P.C4_STEPS
+    args.steps = 5 if args.steps is None else args.steps
+    args.warmup = 1 if args.warmup is None else args.warmup
+    plan = S.Plan.for_workload(w)
+    f_true, mu_np = P.make_phantom_batch(w, B)
+    mu = torch.from_numpy(mu_np).cuda()
+    tgt = torch.from_numpy(f_true).cuda()
+    _, noise = P.rngs(w.seed_index)
+    g = torch.stack([torch.from_numpy(P.poisson_counts(plan.forward(tgt[b], mu[b]).cpu().numpy(),
+                                                       w.total_counts, noise)) for b in range(B)]).cuda()
+    sens = S.autograd.subset_sensitivities(plan, w.n_subsets, mu)
+    log(f"workload {w.name}: data ready")
+
+    def step():
+        f0 = torch.ones((B,) + w.object_shape, device="cuda", requires_grad=True)
+        fk = S.unrolled_osem(plan, g, f0, K, w.n_subsets, mu, sens=sens)
+        loss = ((fk - tgt) ** 2).mean(dim=(1, 2, 3)).sum()
+        loss.backward()
+        return f0.grad
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    t0 = time.perf_counter()
+    evs[0].record(st)
+    for i in range(args.steps):
+        step()
+        evs[i + 1].record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+    ms = float(per.mean())
+    log(f"unrolled loss + gradient, batch {B}: mean {ms:.2f} ms (events), {wall * 1e3 / args.steps:.2f} ms (wall)")
+    # projector passes per member: K forward subiterations (H, H^T) + K recomputed
+    # in the backward pass + K backward (H^T of one adjoint, H of the other)
+    passes = 6 * K
+    sub_va = w.voxel_angles / w.n_subsets
+    kernels = kernel_stats(step, 1)
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    flop_va, bytes_va = {"fwd_main": (20.0, 8.0), "back_rot": (13.0, 8.0),
+                         "back_gather": (99.0, 4.0)}.get(dom, (None, None))
+    blur = float(np.mean([4 * (2 * k + 1) for k in blur_radii(w)]))
+    if dom in ("fwd_main", "back_rot"):
+        flop_va += blur
+    dur = kernels[dom]["avg_ms"] * 1e-3
+    tflops = flop_va * sub_va / dur / 1e12
+    gbs = bytes_va * sub_va / dur / 1e9
+    out = {
+        "metric": "unrolled OSEM loss+gradient evaluations/s (batch 8, 128^3x120, 10 subiterations, checkpointed)",
+        "value": B / (ms * 1e-3),
+        "unit": "reconstruction gradients/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "batch": B, "n": w.n, "nz": w.nz, "n_angles": w.n_angles,
+                   "subsets": w.n_subsets, "unrolled_steps": K, "checkpointing": True,
+                   "loss": "mean squared error to the phantom"},
+        "voxel_angle_projections_per_s": B * passes * sub_va / (ms * 1e-3),
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": tflops,
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": None},
+        "roofline_hbm": {"kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS},
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle gradient of one member on the host")
+        O = _oracle()
+        og = O.Geometry(w.n, w.nz, w.n_angles, w.voxel_cm, w.psf_a, w.psf_b, w.psf_nsigma)
+        f0, m0 = f_true[0].astype(np.float64), mu_np[0].astype(np.float64)
+        _, noise = P.rngs(w.seed_index)
+        g0 = P.poisson_counts(O.forward(og, f0, m0), w.total_counts, noise).astype(np.float64)
+        t0 = time.perf_counter()
+        O.unrolled_osem_grad(og, g0, np.ones(w.object_shape), f0, K, w.n_subsets, m0)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 1.0 / dt, "unit": "reconstruction gradients/s",
+                               "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                               "kind": "oracle",
+                               "sample": f"one member's FP64 loss and gradient (sensitivities included): {dt:.1f} s"}
     print(json.dumps(out), flush=True)
 
 

@@ -15,6 +15,10 @@ Contents
     preconditioner of Table 1, f / (H^(n)T 1), and no prior (V = 0), over
     M subsets of the projection angles (Section 2.1.3).
   * ``dense_matrix``: H as an explicit matrix for tiny grids (brute force).
+  * ``unrolled_osem_grad``: the mean-squared error of K unrolled OSEM
+    subiterations to a target image and its gradient with respect to the
+    initial image, by the chain rule applied to the update backwards (the
+    reference for the differentiable projector pair).
 
 Readings where the paper is silent (also listed in the C source):
   subsets are interleaved (angle n belongs to subset n mod M) and are visited
@@ -264,3 +268,56 @@ def log_likelihood(geom: Geometry, f, g, mu=None, s=None, idx=None) -> float:
         gbar = gbar + np.asarray(s, np.float64)[ix]
     gi = np.asarray(g, np.float64)[ix]
     return float(np.sum(np.where(gi > 0, gi * np.log(np.maximum(gbar, 1e-300)), 0.0) - gbar))
+
+
+def unrolled_osem_grad(geom: Geometry, g, f0, target, n_steps: int, n_subsets: int, mu=None,
+                       s=None):
+    """Loss L = sum((f_K - target)^2) / n_voxels after K = n_steps OSEM
+    subiterations from f0 (subiteration k uses subset k mod M, the update of
+    ``osem`` in its multiplicative form f * H_m^T q / sens_m), and dL/df0.
+
+    Reverse mode, written out: with q_k = g / ghat_k (0 where ghat_k <= 0),
+    ghat_k = H_m f_k + s, b_k = H_m^T q_k and f_(k+1) = f_k b_k / sens_m where
+    sens_m > 0 (else f_k), an adjoint gbar = dL/df_(k+1) gives
+        u = gbar f_k / sens_m           (dL/db_k, 0 where sens_m = 0)
+        v = H_m u                       (dL/dq_k)
+        w = -v g / ghat_k^2             (dL/dghat_k, 0 where ghat_k <= 0)
+        dL/df_k = gbar b_k / sens_m + H_m^T w   (gbar where sens_m = 0).
+    Returns (L, dL/df0)."""
+    subs = subsets(geom.n_angles, n_subsets)
+    sens = [back(geom, np.ones(geom.proj_shape), mu, ix) for ix in subs]
+    g = np.asarray(g, np.float64)
+    f = np.array(f0, dtype=np.float64)
+    tape = []
+    for k in range(n_steps):
+        m = k % n_subsets
+        ix = subs[m]
+        ghat = forward(geom, f, mu, ix)
+        if s is not None:
+            ghat[ix] += np.asarray(s, np.float64)[ix]
+        pos_g = np.zeros(geom.proj_shape, dtype=bool)
+        pos_g[ix] = ghat[ix] > 0
+        q = np.zeros(geom.proj_shape)
+        q[pos_g] = g[pos_g] / ghat[pos_g]
+        b = back(geom, q, mu, ix)
+        pos = sens[m] > 0
+        f1 = f.copy()
+        f1[pos] = f[pos] * b[pos] / sens[m][pos]
+        tape.append((m, f, ghat, pos_g, b))
+        f = f1
+    n_vox = f.size
+    diff = f - np.asarray(target, np.float64)
+    loss = float(np.sum(diff * diff) / n_vox)
+    gbar = 2.0 * diff / n_vox
+    for m, fk, ghat, pos_g, b in reversed(tape):
+        ix = subs[m]
+        pos = sens[m] > 0
+        u = np.zeros(geom.object_shape)
+        u[pos] = gbar[pos] * fk[pos] / sens[m][pos]
+        v = forward(geom, u, mu, ix)
+        w = np.zeros(geom.proj_shape)
+        w[pos_g] = -v[pos_g] * g[pos_g] / (ghat[pos_g] * ghat[pos_g])
+        prev = gbar.copy()
+        prev[pos] = gbar[pos] * b[pos] / sens[m][pos]
+        gbar = prev + back(geom, w, mu, ix)
+    return loss, gbar

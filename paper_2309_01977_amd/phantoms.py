@@ -63,6 +63,15 @@ C2 = Workload("osem_128cube_120ang_att", n=128, nz=128, n_angles=120, with_mu=Tr
               n_subsets=8, total_counts=5e6, seed_index=1)
 
 
+# The differentiable-projector workload: a batch of 8 torso phantoms at the
+# 128^3, 120-angle geometry; 10 unrolled OSEM subiterations (8 subsets) from
+# a uniform image, loss = mean squared error to each phantom.
+C4 = Workload("unrolled_osem_128cube_120ang_b8", n=128, nz=128, n_angles=120, with_mu=True,
+              n_iters=1, n_subsets=8, total_counts=5e6, seed_index=3)
+C4_BATCH = 8
+C4_STEPS = 10
+
+
 def rngs(seed_index: int) -> Tuple[np.random.Generator, np.random.Generator]:
     """(phantom rng, noise rng) for workload ``seed_index``."""
     child = np.random.SeedSequence(MASTER_SEED).spawn(5)[seed_index]
@@ -184,6 +193,19 @@ def make_phantom(w: Workload, ss: int = 4):
             _, mu_shapes = _torso(rng, (w.n * w.voxel_cm) / 61.44, n_spheres=0)
         mu = voxelise(mu_shapes, w.n, w.nz, w.voxel_cm, ss).astype(np.float32)
     return f, mu
+
+
+def make_phantom_batch(w: Workload, batch: int, ss: int = 4):
+    """``batch`` different torso phantoms for the geometry of ``w``:
+    (f_true, mu), each float32 of shape (batch, N, N, Nz)."""
+    rng, _ = rngs(w.seed_index)
+    scale = (w.n * w.voxel_cm) / 61.44
+    fs, mus = [], []
+    for _ in range(batch):
+        act, mu_shapes = _torso(rng, scale)
+        fs.append(voxelise(act, w.n, w.nz, w.voxel_cm, ss).astype(np.float32))
+        mus.append(voxelise(mu_shapes, w.n, w.nz, w.voxel_cm, ss).astype(np.float32))
+    return np.stack(fs), np.stack(mus)
 
 
 def random_object(shape, rng: np.random.Generator, signed: bool = False) -> np.ndarray:

@@ -381,3 +381,65 @@ def test_zero_sensitivity_voxels_keep_their_value():
     f = O.osem(g, data, None, 1, 1, f0=f0)
     np.testing.assert_array_equal(f[sens == 0], 2.0)
     assert np.all(f[sens > 0] != 2.0)
+
+
+# ---------------------------------------------- P15, P16: unrolled OSEM ----
+
+def _unrolled_problem(seed=21):
+    r = rng(seed)
+    g = O.Geometry(5, 3, 6, 0.7, 0.05, 0.4, angles_deg=[0.0, 45.0, 100.0, 170.0, 225.0, 300.0])
+    mu = r.random(g.object_shape) * 0.3
+    f_true = r.random(g.object_shape) + 0.2
+    data = O.forward(g, f_true, mu) * 3.0
+    s = r.random(g.proj_shape) * 0.05
+    f0 = r.random(g.object_shape) + 0.5
+    target = r.random(g.object_shape)
+    return g, mu, data, s, f0, target
+
+
+@pytest.mark.parametrize("with_s", [False, True])
+def test_p15_unrolled_osem_gradient_equals_autograd_of_dense_osem(with_s):
+    """Brute force: OSEM written with the dense matrix H in float64 torch and
+    differentiated by autograd gives the same loss and gradient as the
+    oracle's hand-written reverse recursion (rays that miss the object give
+    zero expected counts at 45 degrees, exercising the q = 0 branch)."""
+    g, mu, data, s, f0, target = _unrolled_problem()
+    s = s if with_s else None
+    K, M = 5, 2
+    loss, grad = O.unrolled_osem_grad(g, data, f0, target, K, M, mu, s)
+    H = torch.from_numpy(O.dense_matrix(g, mu))
+    A, n_bin = g.n_angles, g.proj_shape[1] * g.proj_shape[2]
+    rows = [torch.from_numpy(np.repeat(np.isin(np.arange(A), ix), n_bin)) for ix in O.subsets(A, M)]
+    gd = torch.from_numpy(data.ravel())
+    sd = torch.zeros_like(gd) if s is None else torch.from_numpy(s.ravel())
+    f = torch.from_numpy(f0.ravel()).clone().requires_grad_(True)
+    x = f
+    for k in range(K):
+        Hm = H[rows[k % M]]
+        sens = Hm.sum(0)
+        ghat = Hm @ x + sd[rows[k % M]]
+        q = torch.where(ghat > 0, gd[rows[k % M]] / torch.where(ghat > 0, ghat, torch.ones_like(ghat)),
+                        torch.zeros_like(ghat))
+        b = Hm.T @ q
+        x = torch.where(sens > 0, x * b / torch.where(sens > 0, sens, torch.ones_like(sens)), x)
+    L = ((x - torch.from_numpy(target.ravel())) ** 2).mean()
+    L.backward()
+    assert abs(L.item() - loss) <= 1e-12 * max(1.0, abs(loss))
+    np.testing.assert_allclose(grad.ravel(), f.grad.numpy(), rtol=1e-9, atol=1e-14)
+
+
+def test_p16_unrolled_osem_gradient_matches_central_differences():
+    """Directional derivatives of the unrolled loss by central differences in
+    FP64 (eps 1e-5, error O(eps^2)) agree with the oracle gradient."""
+    g, mu, data, s, f0, target = _unrolled_problem(22)
+    K, M = 4, 3
+    _, grad = O.unrolled_osem_grad(g, data, f0, target, K, M, mu, s)
+    r = rng(23)
+    for _ in range(3):
+        v = r.standard_normal(g.object_shape)
+        eps = 1e-5
+        lp, _ = O.unrolled_osem_grad(g, data, f0 + eps * v, target, K, M, mu, s)
+        lm, _ = O.unrolled_osem_grad(g, data, f0 - eps * v, target, K, M, mu, s)
+        fd = (lp - lm) / (2 * eps)
+        an = float(np.sum(grad * v))
+        assert abs(fd - an) <= 1e-7 * abs(an) + 1e-12, (fd, an)
