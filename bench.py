@@ -299,7 +299,9 @@ def bench_unrolled(args):
     120 angles; one step = loss and gradient of 10 unrolled OSEM
     subiterations (8 subsets) from a uniform image, with checkpointing, loss =
     mean squared error to the phantoms.  The subset sensitivities are
-    computed once before timing (they depend on geometry and mu only)."""
+    computed once before timing, together with each subset's
+    attenuation-factor table (they depend on geometry and mu only); every
+    projection in the timed region reads the tables."""
     w, B, K = P.C4, P.C4_BATCH, P.C4_STEPS
     args.steps = 5 if args.steps is None else args.steps
     args.warmup = 1 if args.warmup is None else args.warmup
@@ -310,12 +312,12 @@ def bench_unrolled(args):
     _, noise = P.rngs(w.seed_index)
     g = torch.stack([torch.from_numpy(P.poisson_counts(plan.forward(tgt[b], mu[b]).cpu().numpy(),
                                                        w.total_counts, noise)) for b in range(B)]).cuda()
-    sens = S.autograd.subset_sensitivities(plan, w.n_subsets, mu)
+    sens, tables = S.autograd.subset_sensitivities(plan, w.n_subsets, mu, tables=True)
     log(f"workload {w.name}: data ready")
 
     def step():
         f0 = torch.ones((B,) + w.object_shape, device="cuda", requires_grad=True)
-        fk = S.unrolled_osem(plan, g, f0, K, w.n_subsets, mu, sens=sens)
+        fk = S.unrolled_osem(plan, g, f0, K, w.n_subsets, mu, sens=sens, tables=tables)
         loss = ((fk - tgt) ** 2).mean(dim=(1, 2, 3)).sum()
         loss.backward()
         return f0.grad
@@ -341,7 +343,8 @@ def bench_unrolled(args):
     sub_va = w.voxel_angles / w.n_subsets
     kernels = kernel_stats(step, 1)
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
-    flop_va, bytes_va = {"fwd_main": (20.0, 8.0), "back_rot": (13.0, 8.0),
+    # per voxel-angle with the factors read from the tables (see recon_work)
+    flop_va, bytes_va = {"fwd_main": (8.0, 8.0), "back_rot": (1.0, 8.0),
                          "back_gather": (99.0, 4.0)}.get(dom, (None, None))
     blur = float(np.mean([4 * (2 * k + 1) for k in blur_radii(w)]))
     if dom in ("fwd_main", "back_rot"):

@@ -73,6 +73,9 @@ extern "C" {
 #define SPECT_OP_OSEM 3
 #define SPECT_OP_RECON 4
 
+/* with_mu value of spect_workspace_size for the attenuation-table calls. */
+#define SPECT_ATT_TABLE 2
+
 /* Limits of this build. */
 #define SPECT_MAX_N 256        /* transverse size N */
 #define SPECT_MAX_K 32         /* collimator blur radius in pixels */
@@ -110,8 +113,10 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out);
 int spect_plan_destroy(spect_plan *plan);
 
 /* Workspace bytes needed by op (SPECT_OP_*) over n_idx angles; for
- * SPECT_OP_OSEM and SPECT_OP_RECON n_idx is the number of subsets M.  with_mu != 0 when an
- * attenuation map will be passed. */
+ * SPECT_OP_OSEM and SPECT_OP_RECON n_idx is the number of subsets M.  with_mu:
+ * 0 no attenuation, 1 an attenuation map will be passed, SPECT_ATT_TABLE the
+ * table calls (spect_fwd_table, spect_back_table with SPECT_OP_FWD /
+ * SPECT_OP_BACK; spect_sensitivity_table with SPECT_OP_SENS). */
 int spect_workspace_size(const spect_plan *plan, int op, int32_t n_idx, int with_mu,
                          size_t *bytes);
 
@@ -138,6 +143,37 @@ int spect_back(const spect_plan *plan, const float *proj, const float *mu, float
 int spect_sensitivity(const spect_plan *plan, const float *mu, float *sens,
                       const int32_t *angle_idx, int32_t n_idx, void *ws, size_t ws_bytes,
                       void *stream);
+
+/* Attenuation-factor tables (T_att of Eq. 1 evaluated once).  For a fixed
+ * attenuation map and angle list the factors exp(-tau) do not change between
+ * projections, so repeated projections of the same list (OSEM iterations,
+ * unrolled reconstructions) can read them instead of resampling mu.  A table
+ * holds, for list position i, axial slab s of 16 slices, rotated depth i' and
+ * bin j', the factors of the slab's 16 axial rows:
+ *     table[((i * ceil(Nz/16) + s) * N + i') * N + j'][16]   (float32)
+ * (rows past Nz hold unused values).  Tables are device memory owned by the
+ * caller, 16-byte aligned.
+ *
+ * spect_table_size: bytes of a table for n_idx angles, n_idx * ceil(Nz/16) *
+ * N * N * 64. */
+int spect_table_size(const spect_plan *plan, int32_t n_idx, size_t *bytes);
+
+/* spect_sensitivity for the listed angles (mu required) that also writes the
+ * attenuation factors of those angles, in list order, to table. */
+int spect_sensitivity_table(const spect_plan *plan, const float *mu, float *sens, float *table,
+                            const int32_t *angle_idx, int32_t n_idx, void *ws, size_t ws_bytes,
+                            void *stream);
+
+/* spect_fwd / spect_back with the attenuation factors read from a table that
+ * spect_sensitivity_table wrote for the same angle list in the same order
+ * (results equal spect_fwd / spect_back with that mu up to FP32 rounding of
+ * the attenuation sums).  Workspace: spect_workspace_size(..., SPECT_ATT_TABLE). */
+int spect_fwd_table(const spect_plan *plan, const float *f, const float *table, float *proj,
+                    const int32_t *angle_idx, int32_t n_idx, void *ws, size_t ws_bytes,
+                    void *stream);
+int spect_back_table(const spect_plan *plan, const float *proj, const float *table, float *f_out,
+                     const int32_t *angle_idx, int32_t n_idx, int accumulate, void *ws,
+                     size_t ws_bytes, void *stream);
 
 /* One OSEM subiteration (Eq. 5 with Table 1: PoissonLogLikelihood gradient
  * H^T(g/(Hf+s)) - H^T 1, OSEM preconditioner f / (H_m^T 1), no prior) on the

@@ -22,9 +22,11 @@ SPECT_ENOMEM = -2
 SPECT_EHIP = -3
 SPECT_EUNSUPPORTED = -4
 OP_FWD, OP_BACK, OP_SENS, OP_OSEM, OP_RECON = 0, 1, 2, 3, 4
+ATT_TABLE = 2   # with_mu code of the attenuation-table calls
 
 EXPORTS = ("spect_plan_create", "spect_plan_destroy", "spect_workspace_size", "spect_fwd",
-           "spect_back", "spect_sensitivity", "osem_subset_step", "osem_reconstruct",
+           "spect_back", "spect_sensitivity", "spect_table_size", "spect_sensitivity_table",
+           "spect_fwd_table", "spect_back_table", "osem_subset_step", "osem_reconstruct",
            "spect_profile_enable",
            "spect_profile_reset", "spect_profile_query", "spect_last_error")
 KERNELS = ("tau_prepass", "fwd_main", "fwd_reduce", "back_rot", "back_gather", "fill_zero")
@@ -65,6 +67,10 @@ def load_library(path: Optional[str] = None):
     lib.spect_fwd.argtypes = [vp, vp, vp, vp, i32p, i32, vp, sz, vp]
     lib.spect_back.argtypes = [vp, vp, vp, vp, i32p, i32, ctypes.c_int, vp, sz, vp]
     lib.spect_sensitivity.argtypes = [vp, vp, vp, i32p, i32, vp, sz, vp]
+    lib.spect_table_size.argtypes = [vp, i32, ctypes.POINTER(sz)]
+    lib.spect_sensitivity_table.argtypes = [vp, vp, vp, vp, i32p, i32, vp, sz, vp]
+    lib.spect_fwd_table.argtypes = [vp, vp, vp, vp, i32p, i32, vp, sz, vp]
+    lib.spect_back_table.argtypes = [vp, vp, vp, vp, i32p, i32, ctypes.c_int, vp, sz, vp]
     lib.osem_subset_step.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, vp, sz, vp]
     lib.osem_reconstruct.argtypes = [vp, vp, vp, vp, vp, i32, i32, vp, sz, vp]
     lib.spect_profile_enable.argtypes = [ctypes.c_int]
@@ -146,14 +152,21 @@ class Plan:
         except Exception:
             pass
 
-    def workspace_size(self, op: int, n_idx: int, with_mu: bool) -> int:
+    @staticmethod
+    def _mu_code(with_mu) -> int:
+        if isinstance(with_mu, bool) or with_mu is None:
+            return int(bool(with_mu))
+        return int(with_mu)
+
+    def workspace_size(self, op: int, n_idx: int, with_mu) -> int:
+        """with_mu: False / True, or ATT_TABLE for the table calls."""
         b = ctypes.c_size_t()
-        _check(load_library().spect_workspace_size(self._h, op, int(n_idx), int(bool(with_mu)),
+        _check(load_library().spect_workspace_size(self._h, op, int(n_idx), self._mu_code(with_mu),
                                                    ctypes.byref(b)))
         return b.value
 
-    def workspace(self, op: int, n_idx: int, with_mu: bool) -> torch.Tensor:
-        key = (op, int(n_idx), int(bool(with_mu)))
+    def workspace(self, op: int, n_idx: int, with_mu) -> torch.Tensor:
+        key = (op, int(n_idx), self._mu_code(with_mu))
         ws = self._ws.get(key)
         if ws is None:
             nbytes = max(self.workspace_size(op, n_idx, with_mu), 256)
@@ -206,6 +219,63 @@ class Plan:
                                                  _ptr(out, self.object_shape, "sens"), arr, n,
                                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                                  _stream()))
+        return out
+
+    # ------------------------------------------------ attenuation tables --
+
+    def table_size(self, n_idx: int) -> int:
+        b = ctypes.c_size_t()
+        _check(load_library().spect_table_size(self._h, int(n_idx), ctypes.byref(b)))
+        return b.value
+
+    def _table(self, table: torch.Tensor, n: int) -> ctypes.c_void_p:
+        if not isinstance(table, torch.Tensor) or table.device.type != "cuda" or table.dtype != torch.float32:
+            raise TypeError("table must be a float32 CUDA tensor")
+        if not table.is_contiguous() or table.numel() * 4 < self.table_size(n):
+            raise ValueError(f"table must be contiguous with at least {self.table_size(n)} bytes")
+        return ctypes.c_void_p(table.data_ptr())
+
+    def new_table(self, n_idx: int) -> torch.Tensor:
+        return torch.empty(self.table_size(n_idx) // 4, dtype=torch.float32, device="cuda")
+
+    def sensitivity_table(self, mu: torch.Tensor, idx=None, out: Optional[torch.Tensor] = None,
+                          table: Optional[torch.Tensor] = None):
+        """(H_idx^T 1, attenuation-factor table of the listed angles) (spect_sensitivity_table)."""
+        arr, n = self._idx(idx)
+        if out is None:
+            out = torch.empty(self.object_shape, dtype=torch.float32, device="cuda")
+        if table is None:
+            table = self.new_table(n)
+        ws = self.workspace(OP_SENS, max(n, 1), ATT_TABLE)
+        _check(load_library().spect_sensitivity_table(
+            self._h, _ptr(mu, self.object_shape, "mu"), _ptr(out, self.object_shape, "sens"),
+            self._table(table, n), arr, n, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+        return out, table
+
+    def forward_table(self, f: torch.Tensor, table: torch.Tensor, idx=None,
+                      out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Rows idx of H f with the factors of ``table`` (spect_fwd_table)."""
+        if out is None:
+            out = torch.zeros(self.proj_shape, dtype=torch.float32, device=f.device)
+        arr, n = self._idx(idx)
+        ws = self.workspace(OP_FWD, max(n, 1), ATT_TABLE)
+        _check(load_library().spect_fwd_table(self._h, _ptr(f, self.object_shape, "f"), self._table(table, n),
+                                               _ptr(out, self.proj_shape, "proj"), arr, n,
+                                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+        return out
+
+    def back_table(self, proj: torch.Tensor, table: torch.Tensor, idx=None,
+                   out: Optional[torch.Tensor] = None, accumulate: bool = False) -> torch.Tensor:
+        """sum over n in idx of H_n^T proj[n] with the factors of ``table`` (spect_back_table)."""
+        if out is None:
+            out = torch.empty(self.object_shape, dtype=torch.float32, device=proj.device)
+            accumulate = False
+        arr, n = self._idx(idx)
+        ws = self.workspace(OP_BACK, max(n, 1), ATT_TABLE)
+        _check(load_library().spect_back_table(self._h, _ptr(proj, self.proj_shape, "proj"),
+                                                self._table(table, n), _ptr(out, self.object_shape, "f_out"),
+                                                arr, n, int(bool(accumulate)), ctypes.c_void_p(ws.data_ptr()),
+                                                ws.numel(), _stream()))
         return out
 
     def osem_subset_step(self, f: torch.Tensor, g: torch.Tensor, sens_m: torch.Tensor, m: int,

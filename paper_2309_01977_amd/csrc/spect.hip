@@ -226,19 +226,25 @@ size_t back_need(const spect_plan *p, int nl, int att, int which = T_BACK)
     return tau_bytes(p, t, nl, att) + z_bytes(p, t, nl);
 }
 
-size_t fwd_ws(const spect_plan *p, int n_idx, bool mu)
+size_t fwd_ws(const spect_plan *p, int n_idx, int att)
 {
     size_t b = 0;
-    for (int nl : batch_sizes(std::max(n_idx, 1), MAXL)) b = std::max(b, fwd_need(p, nl, att_of(mu)));
+    for (int nl : batch_sizes(std::max(n_idx, 1), MAXL)) b = std::max(b, fwd_need(p, nl, att));
     return b;
 }
 
-size_t back_ws(const spect_plan *p, int n_idx, bool mu)
+size_t back_ws(const spect_plan *p, int n_idx, int att)
 {
     size_t b = 0;
     const int G = back_group(p, n_idx);
-    for (int nl : batch_sizes(std::max(n_idx, 1), G)) b = std::max(b, back_need(p, nl, att_of(mu)));
+    for (int nl : batch_sizes(std::max(n_idx, 1), G)) b = std::max(b, back_need(p, nl, att));
     return b;
+}
+
+// Floats of the attenuation-factor table per listed angle: [slab][i'][j'][16].
+size_t table_angle_floats(const spect_plan *p)
+{
+    return (size_t)((p->Nz + SLAB - 1) / SLAB) * p->N * p->N * SLAB;
 }
 
 // OSEM workspace: [q][tau][partial | z]; the back pass reuses the forward's
@@ -265,7 +271,7 @@ int subset_size(const spect_plan *p, int M, int m) { return (p->A - m + M - 1) /
 
 size_t table_bytes(const spect_plan *p, int nl)
 {
-    return align256(sizeof(float) * (size_t)nl * ((p->Nz + SLAB - 1) / SLAB) * p->N * p->N * SLAB);
+    return align256(sizeof(float) * (size_t)nl * table_angle_floats(p));
 }
 
 bool use_table(const spect_plan *p, int M, bool mu)
@@ -748,11 +754,15 @@ int spect_workspace_size(const spect_plan *plan, int op, int32_t n_idx, int with
     if (!plan) return fail(SPECT_EINVAL, "plan is NULL");
     if (!bytes) return fail(SPECT_EINVAL, "bytes is NULL");
     if (n_idx < 1) return fail(SPECT_EINVAL, "n_idx must be >= 1");
+    if (with_mu < 0 || with_mu > SPECT_ATT_TABLE) return fail(SPECT_EINVAL, "with_mu = %d outside [0, 2]", with_mu);
     const bool mu = with_mu != 0;
+    const bool tab = with_mu == SPECT_ATT_TABLE;
+    if (tab && op != SPECT_OP_FWD && op != SPECT_OP_BACK && op != SPECT_OP_SENS)
+        return fail(SPECT_EINVAL, "with_mu = SPECT_ATT_TABLE applies to SPECT_OP_FWD, _BACK and _SENS only");
     switch (op) {
-    case SPECT_OP_FWD: *bytes = fwd_ws(plan, n_idx, mu); break;
-    case SPECT_OP_BACK:
-    case SPECT_OP_SENS: *bytes = back_ws(plan, n_idx, mu); break;
+    case SPECT_OP_FWD: *bytes = fwd_ws(plan, n_idx, tab ? ATT_READ : att_of(mu)); break;
+    case SPECT_OP_BACK: *bytes = back_ws(plan, n_idx, tab ? ATT_READ : att_of(mu)); break;
+    case SPECT_OP_SENS: *bytes = back_ws(plan, n_idx, tab ? ATT_WRITE : att_of(mu)); break;
     case SPECT_OP_OSEM:
         if (n_idx > plan->A) return fail(SPECT_EINVAL, "n_subsets %d exceeds n_angles %d", n_idx, plan->A);
         *bytes = osem_ws(plan, n_idx, mu);
@@ -766,39 +776,44 @@ int spect_workspace_size(const spect_plan *plan, int op, int32_t n_idx, int with
     return ok();
 }
 
-int spect_fwd(const spect_plan *plan, const float *f, const float *mu, float *proj,
-              const int32_t *angle_idx, int32_t n_idx, void *ws, size_t ws_bytes, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Shared bodies of the projector calls.  table == nullptr: attenuation from
+// mu (or none); otherwise the factors of the listed angles are read from
+// (forward, adjoint) or written to (sensitivity) the table, whose list
+// position i starts at table + i * table_angle_floats.
+int do_fwd(const spect_plan *plan, const float *f, const float *mu, const float *table, float *proj,
+           const int32_t *angle_idx, int32_t n_idx, void *ws, size_t ws_bytes, void *stream)
 {
     int st;
     if ((st = check_plan(plan))) return st;
-    if ((st = check_ptr(f, "f", false)) || (st = check_ptr(mu, "mu", true)) ||
-        (st = check_ptr(proj, "proj", false)))
-        return st;
+    if ((st = check_ptr(f, "f", false)) || (st = check_ptr(proj, "proj", false))) return st;
     std::vector<int> list;
     if ((st = make_list(plan, angle_idx, n_idx, &list))) return st;
     if (list.empty()) return ok();
-    if ((st = check_ws(ws, ws_bytes, fwd_ws(plan, (int)list.size(), mu != nullptr)))) return st;
+    const int att = table ? ATT_READ : att_of(mu != nullptr);
+    if ((st = check_ws(ws, ws_bytes, fwd_ws(plan, (int)list.size(), att)))) return st;
     const bool vec = want_vec(plan, {f, mu});
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (size_t b = 0; b < list.size(); b += MAXL) {
         const int n = (int)std::min<size_t>(MAXL, list.size() - b);
         const AngleList L = to_list(list.data() + b, n);
-        if ((st = run_forward(plan, f, mu, att_of(mu), nullptr, L, static_cast<char *>(ws), ws_bytes, nullptr, 0, proj, nullptr, nullptr,
-                              nullptr, vec, T_FWD, s)))
+        const float *tb = table ? table + b * table_angle_floats(plan) : nullptr;
+        if ((st = run_forward(plan, f, mu, att, tb, L, static_cast<char *>(ws), ws_bytes, nullptr, 0, proj,
+                              nullptr, nullptr, nullptr, vec, T_FWD, s)))
             return st;
     }
     return ok();
 }
 
-int spect_back(const spect_plan *plan, const float *proj, const float *mu, float *f_out,
-               const int32_t *angle_idx, int32_t n_idx, int accumulate, void *ws, size_t ws_bytes,
-               void *stream)
+int do_back(const spect_plan *plan, const float *proj, const float *mu, const float *table, float *f_out,
+            const int32_t *angle_idx, int32_t n_idx, int accumulate, void *ws, size_t ws_bytes, void *stream)
 {
     int st;
     if ((st = check_plan(plan))) return st;
-    if ((st = check_ptr(proj, "proj", false)) || (st = check_ptr(mu, "mu", true)) ||
-        (st = check_ptr(f_out, "f_out", false)))
-        return st;
+    if ((st = check_ptr(proj, "proj", false)) || (st = check_ptr(f_out, "f_out", false))) return st;
     std::vector<int> list;
     if ((st = make_list(plan, angle_idx, n_idx, &list))) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -806,43 +821,110 @@ int spect_back(const spect_plan *plan, const float *proj, const float *mu, float
         if (accumulate) return ok();
         return (st = clear(f_out, (size_t)plan->N * plan->N * plan->Nz, s)) ? st : ok();
     }
-    if ((st = check_ws(ws, ws_bytes, back_ws(plan, (int)list.size(), mu != nullptr)))) return st;
+    const int att = table ? ATT_READ : att_of(mu != nullptr);
+    if ((st = check_ws(ws, ws_bytes, back_ws(plan, (int)list.size(), att)))) return st;
     const bool vec = want_vec(plan, {mu});
     const int G = back_group(plan, (int)list.size());
     for (size_t b = 0; b < list.size(); b += G) {
         const int n = (int)std::min<size_t>(G, list.size() - b);
         const AngleList L = to_list(list.data() + b, n);
         const int mode = (b == 0 && !accumulate) ? 0 : 1;
-        if ((st = run_back(plan, proj, 0, 0, mu, att_of(mu), nullptr, L, static_cast<char *>(ws), ws_bytes, nullptr, mode, f_out, nullptr, vec,
-                            T_BACK, s)))
+        float *tb = table ? const_cast<float *>(table) + b * table_angle_floats(plan) : nullptr;
+        if ((st = run_back(plan, proj, 0, 0, mu, att, tb, L, static_cast<char *>(ws), ws_bytes, nullptr, mode,
+                           f_out, nullptr, vec, T_BACK, s)))
             return st;
     }
     return ok();
 }
 
-int spect_sensitivity(const spect_plan *plan, const float *mu, float *sens, const int32_t *angle_idx,
-                      int32_t n_idx, void *ws, size_t ws_bytes, void *stream)
+int do_sens(const spect_plan *plan, const float *mu, float *sens, float *table, const int32_t *angle_idx,
+            int32_t n_idx, void *ws, size_t ws_bytes, void *stream)
 {
     int st;
     if ((st = check_plan(plan))) return st;
-    if ((st = check_ptr(mu, "mu", true)) || (st = check_ptr(sens, "sens", false))) return st;
+    if ((st = check_ptr(sens, "sens", false))) return st;
     std::vector<int> list;
     if ((st = make_list(plan, angle_idx, n_idx, &list))) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (list.empty()) {
-        return (st = clear(sens, (size_t)plan->N * plan->N * plan->Nz, s)) ? st : ok();
-    }
-    if ((st = check_ws(ws, ws_bytes, back_ws(plan, (int)list.size(), mu != nullptr)))) return st;
+    if (list.empty()) return (st = clear(sens, (size_t)plan->N * plan->N * plan->Nz, s)) ? st : ok();
+    const int att = table ? ATT_WRITE : att_of(mu != nullptr);
+    if ((st = check_ws(ws, ws_bytes, back_ws(plan, (int)list.size(), att)))) return st;
     const bool vec = want_vec(plan, {mu});
     const int G = back_group(plan, (int)list.size());
     for (size_t b = 0; b < list.size(); b += G) {
         const int n = (int)std::min<size_t>(G, list.size() - b);
         const AngleList L = to_list(list.data() + b, n);
-        if ((st = run_back(plan, nullptr, 0, 1, mu, att_of(mu), nullptr, L, static_cast<char *>(ws), ws_bytes, nullptr, b == 0 ? 0 : 1, sens,
-                           nullptr, vec, T_BACK, s)))
+        float *tb = table ? table + b * table_angle_floats(plan) : nullptr;
+        if ((st = run_back(plan, nullptr, 0, 1, mu, att, tb, L, static_cast<char *>(ws), ws_bytes, nullptr,
+                           b == 0 ? 0 : 1, sens, nullptr, vec, T_BACK, s)))
             return st;
     }
     return ok();
+}
+
+int check_table(const float *table)
+{
+    if (!table) return fail(SPECT_EINVAL, "table is NULL");
+    if ((uintptr_t)table & 15) return fail(SPECT_EINVAL, "table is not 16-byte aligned");
+    return SPECT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int spect_fwd(const spect_plan *plan, const float *f, const float *mu, float *proj,
+              const int32_t *angle_idx, int32_t n_idx, void *ws, size_t ws_bytes, void *stream)
+{
+    const int st = check_ptr(mu, "mu", true);
+    return st ? st : do_fwd(plan, f, mu, nullptr, proj, angle_idx, n_idx, ws, ws_bytes, stream);
+}
+
+int spect_back(const spect_plan *plan, const float *proj, const float *mu, float *f_out,
+               const int32_t *angle_idx, int32_t n_idx, int accumulate, void *ws, size_t ws_bytes,
+               void *stream)
+{
+    const int st = check_ptr(mu, "mu", true);
+    return st ? st : do_back(plan, proj, mu, nullptr, f_out, angle_idx, n_idx, accumulate, ws, ws_bytes, stream);
+}
+
+int spect_sensitivity(const spect_plan *plan, const float *mu, float *sens, const int32_t *angle_idx,
+                      int32_t n_idx, void *ws, size_t ws_bytes, void *stream)
+{
+    const int st = check_ptr(mu, "mu", true);
+    return st ? st : do_sens(plan, mu, sens, nullptr, angle_idx, n_idx, ws, ws_bytes, stream);
+}
+
+int spect_table_size(const spect_plan *plan, int32_t n_idx, size_t *bytes)
+{
+    if (!plan) return fail(SPECT_EINVAL, "plan is NULL");
+    if (!bytes) return fail(SPECT_EINVAL, "bytes is NULL");
+    if (n_idx < 0) return fail(SPECT_EINVAL, "n_idx = %d is negative", n_idx);
+    *bytes = sizeof(float) * (size_t)n_idx * table_angle_floats(plan);
+    return ok();
+}
+
+int spect_sensitivity_table(const spect_plan *plan, const float *mu, float *sens, float *table,
+                            const int32_t *angle_idx, int32_t n_idx, void *ws, size_t ws_bytes, void *stream)
+{
+    int st;
+    if ((st = check_ptr(mu, "mu", false)) || (st = check_table(table))) return st;
+    return do_sens(plan, mu, sens, table, angle_idx, n_idx, ws, ws_bytes, stream);
+}
+
+int spect_fwd_table(const spect_plan *plan, const float *f, const float *table, float *proj,
+                    const int32_t *angle_idx, int32_t n_idx, void *ws, size_t ws_bytes, void *stream)
+{
+    const int st = check_table(table);
+    return st ? st : do_fwd(plan, f, nullptr, table, proj, angle_idx, n_idx, ws, ws_bytes, stream);
+}
+
+int spect_back_table(const spect_plan *plan, const float *proj, const float *table, float *f_out,
+                     const int32_t *angle_idx, int32_t n_idx, int accumulate, void *ws, size_t ws_bytes,
+                     void *stream)
+{
+    const int st = check_table(table);
+    return st ? st : do_back(plan, proj, nullptr, table, f_out, angle_idx, n_idx, accumulate, ws, ws_bytes, stream);
 }
 
 int osem_subset_step(const spect_plan *plan, float *f, const float *mu, const float *g, const float *s_add,

@@ -103,3 +103,13 @@ def test_profile_query_rejects_bad_arguments():
     assert n.value == 0 and ms.value == 0.0
     assert lib.spect_profile_enable(0) == B.SPECT_OK
     assert lib.spect_profile_reset() == B.SPECT_OK
+
+
+def test_table_calls_reject_null_plan_and_bad_sizes():
+    lib = S.load_library()
+    nbytes = ctypes.c_size_t()
+    assert lib.spect_table_size(None, 4, ctypes.byref(nbytes)) == B.SPECT_EINVAL
+    assert lib.spect_sensitivity_table(None, None, None, None, None, 0, None, 0, None) == B.SPECT_EINVAL
+    assert lib.spect_fwd_table(None, None, None, None, None, 0, None, 0, None) == B.SPECT_EINVAL
+    assert lib.spect_back_table(None, None, None, None, None, 0, 0, None, 0, None) == B.SPECT_EINVAL
+    assert lib.spect_last_error().decode() != ""

@@ -106,6 +106,26 @@ def test_unrolled_osem_gradient_matches_the_oracle(with_s):
     assert el <= GRAD_TOL and eg <= GRAD_TOL
 
 
+def test_attenuation_tables_give_the_same_gradient():
+    """Unrolled OSEM reading per-subset attenuation tables (written by the
+    sensitivity pass) against the oracle, and against the map-based run."""
+    og, plan, f_true, mu, g, _ = small_problem(47)
+    K, M = 10, 4
+    mud = dev(mu)
+    sens, tables = S.autograd.subset_sensitivities(plan, M, mud, tables=True)
+    grads = []
+    for tabs in (tables, None):
+        f = torch.ones(og.object_shape, device="cuda", requires_grad=True)
+        fk = S.unrolled_osem(plan, dev(g), f, K, M, mud, sens=sens, tables=tabs)
+        ((fk.double() - dev(f_true).double()) ** 2).mean().backward()
+        grads.append(host(f.grad))
+    _, grad_ref = O.unrolled_osem_grad(og, g.astype(np.float64), np.ones(og.object_shape),
+                                       f_true.astype(np.float64), K, M, mu.astype(np.float64))
+    e_ref, e_map = rel_l2(grads[0], grad_ref), rel_l2(grads[0], grads[1])
+    say(f"  tables: gradient rel L2 {e_ref:.2e} vs oracle, {e_map:.2e} vs map-based run")
+    assert e_ref <= GRAD_TOL and e_map <= 1e-5
+
+
 def test_unrolled_osem_gradient_matches_central_differences():
     og, plan, f_true, mu, g, _ = small_problem(43)
     K, M = 10, 4
@@ -153,10 +173,11 @@ def test_checkpointing_and_batching_do_not_change_the_gradient():
 
 @pytest.mark.timeout(900)
 def test_batch_of_eight_at_128cube_matches_the_oracle():
-    """The differentiable workload at full size: 8 torso phantoms at 128^3
-    with 120 angles, 10 unrolled subiterations (8 subsets) with
-    checkpointing, loss = mean squared error to the phantoms; member 0's
-    loss and gradient against the FP64 oracle."""
+    """The differentiable workload at full size, as bench.py runs it: 8 torso
+    phantoms at 128^3 with 120 angles, 10 unrolled subiterations (8 subsets)
+    with checkpointing and per-subset attenuation tables, loss = mean squared
+    error to the phantoms; member 0's loss and gradient against the FP64
+    oracle."""
     w, B, K = P.C4, P.C4_BATCH, P.C4_STEPS
     og = O.Geometry(w.n, w.nz, w.n_angles, w.voxel_cm, w.psf_a, w.psf_b, w.psf_nsigma)
     plan = S.Plan.for_workload(w)
@@ -166,7 +187,9 @@ def test_batch_of_eight_at_128cube_matches_the_oracle():
                                    w.total_counts, noise) for b in range(B)])
     say("  oracle data ready")
     f = torch.ones((B,) + w.object_shape, device="cuda", requires_grad=True)
-    fk = S.unrolled_osem(plan, dev(g), f, K, w.n_subsets, dev(mu))
+    mud = dev(mu)
+    sens, tables = S.autograd.subset_sensitivities(plan, w.n_subsets, mud, tables=True)
+    fk = S.unrolled_osem(plan, dev(g), f, K, w.n_subsets, mud, sens=sens, tables=tables)
     loss = ((fk.double() - dev(f_true).double()) ** 2).mean(dim=(1, 2, 3))
     loss.sum().backward()
     got_loss, got_grad = loss[0].item(), host(f.grad[0])

@@ -307,3 +307,37 @@ def test_whole_reconstruction_matches_stepwise_driver():
     say(f"  uneven subsets (60 angles / 8): OSEM rel L2 {e2:.2e}")
     assert e2 <= OSEM_TOL
     assert w.n_subsets == 6
+
+
+@pytest.mark.parametrize("n,nz,A,idx", [(37, 20, 12, [0, 3, 4, 11]), (16, 8, 130, None),
+                                        (128, 128, 120, list(range(2, 120, 8)))])
+def test_attenuation_table_calls_match_the_oracle(n, nz, A, idx):
+    """spect_sensitivity_table writes the factors of the listed angles while it
+    computes H^T 1; spect_fwd_table / spect_back_table read them.  All three
+    against the oracle with the attenuation map (lists longer than one launch
+    included: 130 angles), and against the map-based calls."""
+    og, plan = both(n, nz, A)
+    r = np.random.default_rng(50 + n)
+    mu = P.random_mu(og.object_shape, r, 0.15)
+    f = P.random_object(og.object_shape, r)
+    y = P.random_object(og.proj_shape, r)
+    mud = dev(mu)
+    rows = list(range(A)) if idx is None else idx
+    sens_t, table = plan.sensitivity_table(mud, idx)
+    assert table.numel() * 4 == plan.table_size(len(rows))
+    ref_s = O.back(og, np.ones(og.proj_shape), mu.astype(np.float64), rows)
+    e_s = rel_l2(host(sens_t), ref_s)
+    e_s2 = rel_l2(host(sens_t), host(plan.sensitivity(mud, idx)))
+    fp = host(plan.forward_table(dev(f), table, idx))
+    ref_f = O.forward(og, f.astype(np.float64), mu.astype(np.float64), rows)
+    worst = max(rel_l2(fp[i], ref_f[i]) for i in rows)
+    bp = host(plan.back_table(dev(y), table, idx))
+    ref_b = O.back(og, y.astype(np.float64), mu.astype(np.float64), rows)
+    e_b = rel_l2(bp, ref_b)
+    say(f"  {n}x{n}x{nz}, {len(rows)} angles: sens {e_s:.2e} (vs map call {e_s2:.2e}), "
+        f"forward worst {worst:.2e}, back {e_b:.2e}")
+    assert e_s <= BACK_TOL and e_s2 <= 1e-6 and worst <= FWD_TOL and e_b <= BACK_TOL
+    others = np.setdiff1d(np.arange(A), rows)
+    assert not fp[others].any()
+    with pytest.raises(S.SpectError):
+        plan.workspace_size(S.OP_OSEM, 2, 2)
