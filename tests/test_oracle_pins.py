@@ -443,3 +443,100 @@ def test_p16_unrolled_osem_gradient_matches_central_differences():
         fd = (lp - lm) / (2 * eps)
         an = float(np.sum(grad * v))
         assert abs(fd - an) <= 1e-7 * abs(an) + 1e-12, (fd, an)
+
+
+# ----------------------------------------- P17-P20: RDP prior and BSREM ----
+
+def test_p17_rdp_gradient_matches_central_differences_of_the_prior():
+    """The closed-form RDP gradient against central differences of V(f) as
+    Table 1 defines it (FP64, eps 1e-6), at gamma 2 and 0."""
+    r = rng(30)
+    f = r.random((5, 4, 3)) + 0.1
+    for gamma in (2.0, 0.0):
+        grad = O.rdp_gradient(f, gamma)
+        eps = 1e-6
+        for q in r.choice(f.size, 12, replace=False):
+            e = np.zeros(f.size)
+            e[q] = eps
+            e = e.reshape(f.shape)
+            fd = (O.rdp_value(f + e, gamma) - O.rdp_value(f - e, gamma)) / (2 * eps)
+            assert abs(fd - grad.ravel()[q]) <= 1e-7 * max(1.0, abs(fd)), (gamma, q)
+
+
+def test_p18_rdp_hand_values_homogeneity_and_euler_identity():
+    """Two voxels a = 1, b = 3, gamma = 2: V = 2 phi(1, 3) = 1 and dV/da =
+    -0.875 (by hand).  phi is 1-homogeneous, so V(k f) = k V(f), the gradient
+    is 0-homogeneous and <f, grad V(f)> = V(f) (Euler); a uniform image has
+    zero gradient."""
+    f2 = np.array([1.0, 3.0]).reshape(2, 1, 1)
+    assert abs(O.rdp_value(f2, 2.0) - 1.0) < 1e-15
+    assert abs(O.rdp_gradient(f2, 2.0)[0, 0, 0] + 0.875) < 1e-15
+    r = rng(31)
+    f = r.random((6, 5, 4)) + 0.05
+    V, G = O.rdp_value(f, 2.0), O.rdp_gradient(f, 2.0)
+    assert abs(np.sum(f * G) - V) <= 1e-12 * V
+    assert abs(O.rdp_value(3.7 * f, 2.0) - 3.7 * V) <= 1e-12 * V
+    np.testing.assert_allclose(O.rdp_gradient(3.7 * f, 2.0), G, rtol=1e-12, atol=1e-15)
+    assert not O.rdp_gradient(np.full((4, 4, 4), 2.5), 2.0).any()
+
+
+def test_p19_bsrem_without_prior_or_subsets_is_mlem():
+    """One subset, beta = 0 and alpha = 1: the BSREM preconditioner f / H^T 1
+    makes the update the MLEM (multiplicative EM) update of ``osem``."""
+    g, _, mu, data = _small_problem()
+    a = O.bsrem(g, data, mu, n_iters=3, n_subsets=1, beta=0.0, relaxation=lambda k: 1.0)
+    b = O.osem(g, data, mu, n_iters=3, n_subsets=1)
+    np.testing.assert_allclose(a, b, rtol=1e-12)
+
+
+def test_p20_bsrem_fixed_point_of_consistent_uniform_data():
+    """Noise-free data of a uniform object: the object is a fixed point of
+    BSREM-RDP with one subset (the likelihood gradient and the prior gradient
+    both vanish there)."""
+    g = O.Geometry(8, 4, 6, 0.6, 0.05, 0.3)
+    fstar = np.full(g.object_shape, 2.0)
+    data = O.forward(g, fstar)
+    f = O.bsrem(g, data, None, n_iters=2, n_subsets=1, beta=0.3, gamma=2.0, f0=fstar)
+    sens = O.back(g, np.ones(g.proj_shape), None)
+    np.testing.assert_allclose(f[sens > 0], 2.0, rtol=1e-12)
+
+
+def test_p18b_rdp_hot_voxel_closed_form():
+    """One voxel of 1 in a zero 3x3x3 grid, gamma = 2: every pair with the
+    centre has phi = 1/3 in both orders and all other pairs are 0, so
+    V = 2 (6 + 12/sqrt 2 + 8/sqrt 3) / 3, and dV/df_centre = 2 sum w_s (1 * 3)/9."""
+    f = np.zeros((3, 3, 3))
+    f[1, 1, 1] = 1.0
+    wsum = 6 + 12 / np.sqrt(2) + 8 / np.sqrt(3)
+    assert abs(O.rdp_value(f, 2.0) - 2 * wsum / 3) < 1e-13
+    assert abs(O.rdp_gradient(f, 2.0)[1, 1, 1] - 2 * wsum / 3) < 1e-13
+    # a face neighbour b = 0 next to a = 1: dphi/db (b first) = (0 - 1)(0 + 3 + 2)/9, times 2 w = 2
+    assert abs(O.rdp_gradient(f, 2.0)[0, 1, 1] - 2 * (-5 / 9)) < 1e-13
+
+
+def test_p19b_bsrem_subset_scaling_on_a_symmetric_geometry():
+    """Angles 0, 90, 180, 270 without attenuation or blur and two subsets
+    {0, 180}, {90, 270}: every voxel's subset sensitivity is exactly half the
+    total, so BSREM with beta = 0, alpha = 1 equals OSEM with two subsets, and
+    one BSREM subiteration with the prior is that OSEM step minus
+    f alpha beta grad V / H^T 1 (c cancels), clipped at 0."""
+    g = O.Geometry(8, 3, 4, 0.6, angles_deg=[0.0, 90.0, 180.0, 270.0])
+    r = rng(32)
+    data = P.poisson_counts(O.forward(g, r.random(g.object_shape) + 0.5), 1e4, r).astype(np.float64)
+    a = O.bsrem(g, data, None, n_iters=2, n_subsets=2, beta=0.0, relaxation=lambda k: 1.0)
+    b = O.osem(g, data, None, n_iters=2, n_subsets=2)
+    np.testing.assert_allclose(a, b, rtol=1e-12)
+    f0 = r.random(g.object_shape) + 0.5
+    beta, gamma, alpha = 0.3, 2.0, 0.7
+    got = O.bsrem(g, data, None, n_iters=1, n_subsets=2, beta=beta, gamma=gamma, f0=f0,
+                  relaxation=lambda k: alpha)
+    S = O.back(g, np.ones(g.proj_shape), None)
+    f = f0
+    for ix in O.subsets(4, 2):
+        Sm = O.back(g, np.ones(g.proj_shape), None, ix)
+        gb = O.forward(g, f, None, ix)
+        q = np.zeros(g.proj_shape)
+        q[ix] = data[ix] / gb[ix]
+        osem_step = f * O.back(g, q, None, ix) / Sm
+        f = np.maximum(0.0, f + alpha * (osem_step - f) - f * alpha * beta * O.rdp_gradient(f, gamma) / S)
+    np.testing.assert_allclose(got, f, rtol=1e-12)
