@@ -72,6 +72,8 @@ extern "C" {
 #define SPECT_OP_SENS 2
 #define SPECT_OP_OSEM 3
 #define SPECT_OP_RECON 4
+#define SPECT_OP_BSREM_STEP 5
+#define SPECT_OP_BSREM 6
 
 /* with_mu value of spect_workspace_size for the attenuation-table calls. */
 #define SPECT_ATT_TABLE 2
@@ -206,11 +208,54 @@ int osem_reconstruct(const spect_plan *plan, float *f, const float *mu, const fl
                      const float *s_add, int32_t n_iters, int32_t n_subsets, void *ws,
                      size_t ws_bytes, void *stream);
 
+/* BSREM with the relative difference prior (Section 2.1.3: Eq. 4 with the
+ * Table 1 BSREM preconditioner C = f alpha^(n) / (c^(n) H^T 1), prior
+ * weight beta^(n) = c^(n) beta, and the Table 1 RelativeDifferencePrior
+ * phi(a, b) = (a - b)^2 / (a + b + gamma |a - b|)).
+ *
+ * Prior V(f) = sum_r sum_{s in N(r)} w_rs phi(f_r, f_s) over the 26 neighbours
+ * s of voxel r inside the grid, w_rs = 1 / (distance in voxels) (the paper:
+ * "typically inverse Euclidean distance"); its gradient is
+ *     dV/df_r = 2 sum_s w_rs (f_r - f_s)(f_r + 3 f_s + gamma |f_r - f_s|)
+ *               / (f_r + f_s + gamma |f_r - f_s|)^2,
+ * a pair with a zero denominator contributing 0.
+ *
+ * spect_rdp_gradient: grad = dV/df.  f, grad: device (N, N, Nz), distinct;
+ * gamma >= 0. */
+int spect_rdp_gradient(const spect_plan *plan, const float *f, float *grad, float gamma,
+                       void *stream);
+
+/* One BSREM subiteration on the interleaved subset S_m:
+ *     f <- max(0, f + f alpha / (c S) (H_m^T(g / (H_m f + s)) - H_m^T 1 - c beta dV/df))
+ * where S = sens_all = H^T 1 over all angles (spect_sensitivity with all
+ * angles), sens_m = H_m^T 1, c = |S_m| / A (the subset's share of the data);
+ * voxels with S = 0 keep their value; the clip at 0 keeps the image
+ * non-negative (the paper does not state it; BSREM is defined on the
+ * non-negative orthant).  alpha > 0, beta >= 0, gamma >= 0.  Workspace:
+ * SPECT_OP_BSREM_STEP with n_idx = n_subsets.  Other arguments as in
+ * osem_subset_step. */
+int bsrem_subset_step(const spect_plan *plan, float *f, const float *mu, const float *g,
+                      const float *s_add, const float *sens_m, const float *sens_all, int32_t m,
+                      int32_t n_subsets, float alpha, float beta, float gamma, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/* A whole BSREM-RDP reconstruction: the subset sensitivities (and, with an
+ * attenuation map, the attenuation-factor tables, as in osem_reconstruct),
+ * S = their sum, then n_iters iterations of bsrem_subset_step over
+ * m = 0 .. n_subsets-1 with alpha = relaxation[k] in iteration k (relaxation:
+ * host array of n_iters values > 0, or NULL for 1 / (1 + k), a reading: the
+ * paper leaves the sequence open).  The paper's SPECT examples use beta = 0.3,
+ * gamma = 2.  Workspace: SPECT_OP_BSREM with n_idx = n_subsets. */
+int bsrem_reconstruct(const spect_plan *plan, float *f, const float *mu, const float *g,
+                      const float *s_add, int32_t n_iters, int32_t n_subsets, float beta,
+                      float gamma, const float *relaxation, void *ws, size_t ws_bytes,
+                      void *stream);
+
 /* Kernel timing, a tracing aid.  While enabled (process-wide), every kernel
  * the library launches is bracketed by two HIP events recorded on the
  * launch's own stream.  spect_profile_query waits for the recorded launches of
  * the named kernel ("tau_prepass", "fwd_main", "fwd_reduce", "back_rot",
- * "back_gather", "fill_zero") and returns their count and summed duration in
+ * "back_gather", "fill_zero", "rdp_grad", "vol_sum") and returns their count and summed duration in
  * milliseconds; spect_profile_reset waits for and frees all records.
  * Errors: SPECT_EINVAL (NULL argument, unknown name), SPECT_EHIP. */
 int spect_profile_enable(int enable);

@@ -21,15 +21,16 @@ SPECT_EINVAL = -1
 SPECT_ENOMEM = -2
 SPECT_EHIP = -3
 SPECT_EUNSUPPORTED = -4
-OP_FWD, OP_BACK, OP_SENS, OP_OSEM, OP_RECON = 0, 1, 2, 3, 4
+OP_FWD, OP_BACK, OP_SENS, OP_OSEM, OP_RECON, OP_BSREM_STEP, OP_BSREM = 0, 1, 2, 3, 4, 5, 6
 ATT_TABLE = 2   # with_mu code of the attenuation-table calls
 
 EXPORTS = ("spect_plan_create", "spect_plan_destroy", "spect_workspace_size", "spect_fwd",
            "spect_back", "spect_sensitivity", "spect_table_size", "spect_sensitivity_table",
            "spect_fwd_table", "spect_back_table", "osem_subset_step", "osem_reconstruct",
-           "spect_profile_enable",
+           "spect_rdp_gradient", "bsrem_subset_step", "bsrem_reconstruct", "spect_profile_enable",
            "spect_profile_reset", "spect_profile_query", "spect_last_error")
-KERNELS = ("tau_prepass", "fwd_main", "fwd_reduce", "back_rot", "back_gather", "fill_zero")
+KERNELS = ("tau_prepass", "fwd_main", "fwd_reduce", "back_rot", "back_gather", "fill_zero", "rdp_grad",
+           "vol_sum")
 
 
 class SpectError(RuntimeError):
@@ -73,6 +74,10 @@ def load_library(path: Optional[str] = None):
     lib.spect_back_table.argtypes = [vp, vp, vp, vp, i32p, i32, ctypes.c_int, vp, sz, vp]
     lib.osem_subset_step.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, vp, sz, vp]
     lib.osem_reconstruct.argtypes = [vp, vp, vp, vp, vp, i32, i32, vp, sz, vp]
+    f32 = ctypes.c_float
+    lib.spect_rdp_gradient.argtypes = [vp, vp, vp, f32, vp]
+    lib.bsrem_subset_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, i32, f32, f32, f32, vp, sz, vp]
+    lib.bsrem_reconstruct.argtypes = [vp, vp, vp, vp, vp, i32, i32, f32, f32, ctypes.POINTER(f32), vp, sz, vp]
     lib.spect_profile_enable.argtypes = [ctypes.c_int]
     lib.spect_profile_reset.argtypes = []
     lib.spect_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
@@ -342,3 +347,51 @@ Plan.reconstruct = _recon_method
 def subset_angles(n_angles: int, n_subsets: int, m: int):
     """Interleaved subset m = {n : n mod M = m}."""
     return list(range(m, n_angles, n_subsets))
+
+
+def _rdp_gradient(self, f: torch.Tensor, gamma: float = 2.0, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Gradient of the relative difference prior at f (spect_rdp_gradient)."""
+    if out is None:
+        out = torch.empty(self.object_shape, dtype=torch.float32, device=f.device)
+    _check(load_library().spect_rdp_gradient(self._h, _ptr(f, self.object_shape, "f"),
+                                             _ptr(out, self.object_shape, "grad"), float(gamma), _stream()))
+    return out
+
+
+def _bsrem_step(self, f: torch.Tensor, g: torch.Tensor, sens_m: torch.Tensor, sens_all: torch.Tensor, m: int,
+                n_subsets: int, alpha: float, beta: float = 0.3, gamma: float = 2.0,
+                mu: Optional[torch.Tensor] = None, s_add: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """One BSREM-RDP subiteration on subset m, f updated in place (bsrem_subset_step)."""
+    ws = self.workspace(OP_BSREM_STEP, n_subsets, mu is not None)
+    _check(load_library().bsrem_subset_step(
+        self._h, _ptr(f, self.object_shape, "f"), _ptr(mu, self.object_shape, "mu"),
+        _ptr(g, self.proj_shape, "g"), _ptr(s_add, self.proj_shape, "s_add"),
+        _ptr(sens_m, self.object_shape, "sens_m"), _ptr(sens_all, self.object_shape, "sens_all"), int(m),
+        int(n_subsets), float(alpha), float(beta), float(gamma), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+        _stream()))
+    return f
+
+
+def _bsrem_method(self, g: torch.Tensor, n_iters: int, n_subsets: int, mu: Optional[torch.Tensor] = None,
+                  s_add: Optional[torch.Tensor] = None, f: Optional[torch.Tensor] = None, beta: float = 0.3,
+                  gamma: float = 2.0, relaxation: Optional[Sequence[float]] = None) -> torch.Tensor:
+    """Whole BSREM-RDP reconstruction (bsrem_reconstruct); f holds the initial
+    image (1 everywhere if None) and receives the result."""
+    if f is None:
+        f = torch.ones(self.object_shape, dtype=torch.float32, device=g.device)
+    rel = None
+    if relaxation is not None:
+        if len(relaxation) < n_iters:
+            raise ValueError("relaxation needs one value per iteration")
+        rel = (ctypes.c_float * len(relaxation))(*[float(a) for a in relaxation])
+    ws = self.workspace(OP_BSREM, n_subsets, mu is not None)
+    _check(load_library().bsrem_reconstruct(
+        self._h, _ptr(f, self.object_shape, "f"), _ptr(mu, self.object_shape, "mu"),
+        _ptr(g, self.proj_shape, "g"), _ptr(s_add, self.proj_shape, "s_add"), int(n_iters), int(n_subsets),
+        float(beta), float(gamma), rel, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return f
+
+
+Plan.rdp_gradient = _rdp_gradient
+Plan.bsrem_subset_step = _bsrem_step
+Plan.bsrem = _bsrem_method

@@ -38,9 +38,9 @@ namespace {
 // Optional per-kernel timing: while enabled, every launch is bracketed by two
 // HIP events recorded on the launch's own stream.
 
-enum KernelId { K_TAU = 0, K_FWD, K_REDUCE, K_BACK_ROT, K_GATHER, K_FILL, K_COUNT };
+enum KernelId { K_TAU = 0, K_FWD, K_REDUCE, K_BACK_ROT, K_GATHER, K_FILL, K_RDP, K_SUM, K_COUNT };
 const char *const kKernelNames[K_COUNT] = {"tau_prepass", "fwd_main", "fwd_reduce", "back_rot",
-                                           "back_gather", "fill_zero"};
+                                           "back_gather", "fill_zero", "rdp_grad", "vol_sum"};
 
 struct ProfRec {
     int kernel;
@@ -507,7 +507,7 @@ int run_forward(const spect_plan *p, const float *f, const float *mu, int att, c
 // ATT_READ (from table).  ws holds [tau][z]; tau_given as in run_forward.
 int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const float *mu, int att,
              float *table, const AngleList &L, char *ws, size_t ws_avail, const float *tau_given, int mode,
-             float *out, const float *sens, bool vec, int which, hipStream_t st)
+             float *out, const float *sens, bool vec, int which, hipStream_t st, const BsremTerms *bt = nullptr)
 {
     const Tuning t = tune(p, L.n, att, which);
     if (back_need(p, L.n, att, which) > ws_avail)
@@ -553,6 +553,7 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
     gg.mode = mode;
     gg.out = out;
     gg.sens = sens;
+    gg.bt = bt ? *bt : BsremTerms{nullptr, nullptr, 0.f, 0.f};
     const int tiles = (p->N + GT - 1) / GT;
     {
         ProfScope ps(K_GATHER, st);
@@ -561,6 +562,32 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "back projection launch");
     return SPECT_OK;
+}
+
+// grad = gradient of the relative difference prior at f (weight gamma).
+int launch_rdp(const spect_plan *p, const float *f, float *grad, float gamma, hipStream_t st)
+{
+    RdpArgs a{f, grad, p->N, p->Nz, gamma};
+    const size_t n = (size_t)p->N * p->N * p->Nz;
+    {
+        ProfScope ps(K_RDP, st);
+        hipLaunchKernelGGL(rdp_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+    }
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SPECT_OK : hip_fail(e, "prior gradient launch");
+}
+
+// out = sum of n volumes of the plan's size spaced `stride` floats apart.
+int launch_sum(const spect_plan *p, const float *first, size_t stride, int n, float *out, hipStream_t st)
+{
+    const size_t count = (size_t)p->N * p->N * p->Nz;
+    {
+        ProfScope ps(K_SUM, st);
+        hipLaunchKernelGGL(vol_sum, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, first, stride, n, out,
+                           count);
+    }
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SPECT_OK : hip_fail(e, "volume sum launch");
 }
 
 int clear(float *p, size_t n, hipStream_t st)
@@ -771,6 +798,14 @@ int spect_workspace_size(const spect_plan *plan, int op, int32_t n_idx, int with
         if (n_idx > plan->A) return fail(SPECT_EINVAL, "n_subsets %d exceeds n_angles %d", n_idx, plan->A);
         *bytes = recon_ws(plan, n_idx, mu);
         break;
+    case SPECT_OP_BSREM_STEP:
+        if (n_idx > plan->A) return fail(SPECT_EINVAL, "n_subsets %d exceeds n_angles %d", n_idx, plan->A);
+        *bytes = vol_bytes(plan) + osem_ws(plan, n_idx, mu);
+        break;
+    case SPECT_OP_BSREM:
+        if (n_idx > plan->A) return fail(SPECT_EINVAL, "n_subsets %d exceeds n_angles %d", n_idx, plan->A);
+        *bytes = recon_ws(plan, n_idx, mu) + 2 * vol_bytes(plan);
+        break;
     default: return fail(SPECT_EINVAL, "unknown op %d", op);
     }
     return ok();
@@ -961,8 +996,25 @@ int osem_subset_step(const spect_plan *plan, float *f, const float *mu, const fl
     return ok();
 }
 
-int osem_reconstruct(const spect_plan *plan, float *f, const float *mu, const float *g, const float *s_add,
-                     int32_t n_iters, int32_t n_subsets, void *ws, size_t ws_bytes, void *stream)
+}  // extern "C"
+
+namespace {
+
+// BSREM parameters of a whole reconstruction (nullptr: OSEM).
+struct BsremSpec {
+    float beta, gamma;
+    const float *relax;  // host, one relaxation per iteration; nullptr: 1 / (1 + k)
+};
+
+bool finite_nonneg(float x) { return std::isfinite(x) && x >= 0.f; }
+
+// Whole reconstruction: subset sensitivities (and attenuation tables), then
+// n_iters x M subiterations, each an OSEM update or, with bs, the BSREM
+// update with the relative difference prior.  Workspace as recon_ws, plus
+// two volumes (all-angle sensitivity, prior gradient) for BSREM right after
+// the M sensitivities.
+int reconstruct(const spect_plan *plan, float *f, const float *mu, const float *g, const float *s_add,
+                int32_t n_iters, int32_t n_subsets, void *ws, size_t ws_bytes, void *stream, const BsremSpec *bs)
 {
     int st;
     if ((st = check_plan(plan))) return st;
@@ -972,19 +1024,29 @@ int osem_reconstruct(const spect_plan *plan, float *f, const float *mu, const fl
     if (n_subsets < 1 || n_subsets > plan->A)
         return fail(SPECT_EINVAL, "n_subsets = %d outside [1, %d]", n_subsets, plan->A);
     if (n_iters < 0) return fail(SPECT_EINVAL, "n_iters = %d is negative", n_iters);
+    if (bs) {
+        if (!finite_nonneg(bs->beta) || !finite_nonneg(bs->gamma))
+            return fail(SPECT_EINVAL, "beta and gamma must be finite and >= 0");
+        for (int k = 0; bs->relax && k < n_iters; ++k)
+            if (!(std::isfinite(bs->relax[k]) && bs->relax[k] > 0.f))
+                return fail(SPECT_EINVAL, "relaxation[%d] must be finite and > 0", k);
+    }
     const int M = n_subsets;
     const int nl_max = (plan->A + M - 1) / M;
     if (nl_max > MAXL) return fail(SPECT_EUNSUPPORTED, "subsets of more than %d angles", MAXL);
-    if ((st = check_ws(ws, ws_bytes, recon_ws(plan, M, mu != nullptr)))) return st;
+    const size_t vb = vol_bytes(plan);
+    const size_t extra = bs ? 2 * vb : 0;
+    if ((st = check_ws(ws, ws_bytes, recon_ws(plan, M, mu != nullptr) + extra))) return st;
     const bool vec = want_vec(plan, {f, mu});
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *w = static_cast<char *>(ws);
-    const size_t vb = vol_bytes(plan);
     const bool table = use_table(plan, M, mu != nullptr);
     const int att = table ? ATT_READ : att_of(mu != nullptr);
     std::vector<float *> sens(M), per(M, nullptr);  // per subset: attenuation table or chunk offsets
-    size_t off = (size_t)M * vb;
     for (int m = 0; m < M; ++m) sens[m] = reinterpret_cast<float *>(w + (size_t)m * vb);
+    float *sens_all = bs ? reinterpret_cast<float *>(w + (size_t)M * vb) : nullptr;
+    float *prior = bs ? reinterpret_cast<float *>(w + (size_t)M * vb + vb) : nullptr;
+    size_t off = (size_t)M * vb + extra;
     std::vector<AngleList> lists(M);
     for (int m = 0; m < M; ++m) {
         std::vector<int> list;
@@ -1009,17 +1071,99 @@ int osem_reconstruct(const spect_plan *plan, float *f, const float *mu, const fl
                           vec, T_BOTH, s);
         if (st) return st;
     }
+    if (bs && (st = launch_sum(plan, sens[0], vb / sizeof(float), M, sens_all, s))) return st;
     for (int it = 0; it < n_iters; ++it)
         for (int m = 0; m < M; ++m) {
             float *tab = table ? per[m] : nullptr;
             const float *tau = table ? nullptr : per[m];
+            BsremTerms bt{sens_all, prior, 0.f, 0.f};
+            if (bs) {
+                const float c = (float)lists[m].n / (float)plan->A;
+                const float alpha = bs->relax ? bs->relax[it] : 1.f / (1.f + (float)it);
+                bt.a_over_c = alpha / c;
+                bt.c_beta = c * bs->beta;
+                if ((st = launch_rdp(plan, f, prior, bs->gamma, s))) return st;
+            }
             if ((st = run_forward(plan, f, mu, att, tab, lists[m], rest, avail, tau, 1, nullptr, g, s_add, q, vec,
                                   T_BOTH, s)))
                 return st;
-            if ((st = run_back(plan, q, 1, 0, mu, att, tab, lists[m], rest, avail, tau, 2, f, sens[m], vec, T_BOTH,
-                               s)))
+            if ((st = run_back(plan, q, 1, 0, mu, att, tab, lists[m], rest, avail, tau, bs ? 3 : 2, f, sens[m], vec,
+                               T_BOTH, s, bs ? &bt : nullptr)))
                 return st;
         }
+    return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+int osem_reconstruct(const spect_plan *plan, float *f, const float *mu, const float *g, const float *s_add,
+                     int32_t n_iters, int32_t n_subsets, void *ws, size_t ws_bytes, void *stream)
+{
+    return reconstruct(plan, f, mu, g, s_add, n_iters, n_subsets, ws, ws_bytes, stream, nullptr);
+}
+
+int bsrem_reconstruct(const spect_plan *plan, float *f, const float *mu, const float *g, const float *s_add,
+                      int32_t n_iters, int32_t n_subsets, float beta, float gamma, const float *relaxation,
+                      void *ws, size_t ws_bytes, void *stream)
+{
+    const BsremSpec bs{beta, gamma, relaxation};
+    return reconstruct(plan, f, mu, g, s_add, n_iters, n_subsets, ws, ws_bytes, stream, &bs);
+}
+
+int spect_rdp_gradient(const spect_plan *plan, const float *f, float *grad, float gamma, void *stream)
+{
+    int st;
+    if ((st = check_plan(plan))) return st;
+    if ((st = check_ptr(f, "f", false)) || (st = check_ptr(grad, "grad", false))) return st;
+    if (f == grad) return fail(SPECT_EINVAL, "f and grad must not overlap");
+    if (!finite_nonneg(gamma)) return fail(SPECT_EINVAL, "gamma must be finite and >= 0");
+    if ((st = launch_rdp(plan, f, grad, gamma, static_cast<hipStream_t>(stream)))) return st;
+    return ok();
+}
+
+int bsrem_subset_step(const spect_plan *plan, float *f, const float *mu, const float *g, const float *s_add,
+                      const float *sens_m, const float *sens_all, int32_t m, int32_t n_subsets, float alpha,
+                      float beta, float gamma, void *ws, size_t ws_bytes, void *stream)
+{
+    int st;
+    if ((st = check_plan(plan))) return st;
+    if ((st = check_ptr(f, "f", false)) || (st = check_ptr(mu, "mu", true)) || (st = check_ptr(g, "g", false)) ||
+        (st = check_ptr(s_add, "s_add", true)) || (st = check_ptr(sens_m, "sens_m", false)) ||
+        (st = check_ptr(sens_all, "sens_all", false)))
+        return st;
+    if (n_subsets < 1 || n_subsets > plan->A)
+        return fail(SPECT_EINVAL, "n_subsets = %d outside [1, %d]", n_subsets, plan->A);
+    if (m < 0 || m >= n_subsets) return fail(SPECT_EINVAL, "m = %d outside [0, %d)", m, n_subsets);
+    if (!(std::isfinite(alpha) && alpha > 0.f)) return fail(SPECT_EINVAL, "alpha must be finite and > 0");
+    if (!finite_nonneg(beta) || !finite_nonneg(gamma))
+        return fail(SPECT_EINVAL, "beta and gamma must be finite and >= 0");
+    const int nl_max = (plan->A + n_subsets - 1) / n_subsets;
+    if (nl_max > MAXL) return fail(SPECT_EUNSUPPORTED, "subsets of more than %d angles", MAXL);
+    const size_t vb = vol_bytes(plan);
+    if ((st = check_ws(ws, ws_bytes, vb + osem_ws(plan, n_subsets, mu != nullptr)))) return st;
+    std::vector<int> list;
+    for (int n = m; n < plan->A; n += n_subsets) list.push_back(n);
+    const AngleList L = to_list(list.data(), (int)list.size());
+    const bool vec = want_vec(plan, {f, mu});
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // workspace [prior][q][tau][partial | z]
+    char *w = static_cast<char *>(ws);
+    float *prior = reinterpret_cast<float *>(w);
+    float *q = reinterpret_cast<float *>(w + vb);
+    const size_t qb = osem_q_bytes(plan, n_subsets);
+    char *rest = w + vb + qb;
+    const size_t avail = ws_bytes - vb - qb;
+    const float c = (float)L.n / (float)plan->A;
+    const BsremTerms bt{sens_all, prior, alpha / c, c * beta};
+    if ((st = launch_rdp(plan, f, prior, gamma, s))) return st;
+    if ((st = run_forward(plan, f, mu, att_of(mu), nullptr, L, rest, avail, nullptr, 1, nullptr, g, s_add, q, vec,
+                          T_BOTH, s)))
+        return st;
+    if ((st = run_back(plan, q, 1, 0, mu, att_of(mu), nullptr, L, rest, avail, reinterpret_cast<const float *>(rest),
+                       3, f, sens_m, vec, T_BOTH, s, &bt)))
+        return st;
     return ok();
 }
 

@@ -692,14 +692,24 @@ __global__ __launch_bounds__(512) void back_rot(BackRotArgs a)
     }
 }
 
+// Terms of the BSREM update (gather mode 3): where sens_all > 0,
+// out <- max(0, out + out * a_over_c / sens_all * (sum - sens - c_beta * prior)).
+struct BsremTerms {
+    const float *sens_all;  // H^T 1 over all angles
+    const float *prior;     // gradient of the prior at out
+    float a_over_c;         // relaxation / subset share
+    float c_beta;           // subset share * prior weight
+};
+
 struct GatherArgs {
     DevGeom g;
     AngleList L;
     const float *z;
     int nslab;
-    int mode;            // 0: out = sum; 1: out += sum; 2: OSEM update of out with sens
+    int mode;            // 0: out = sum; 1: out += sum; 2: OSEM update of out with sens; 3: BSREM update
     float *out;
-    const float *sens;
+    const float *sens;   // modes 2, 3: subset sensitivity H_m^T 1
+    BsremTerms bt;       // mode 3
 };
 
 // Transpose of the bilinear rotation, as a gather.  Workgroup = 8 x 8 object
@@ -770,9 +780,16 @@ __global__ __launch_bounds__(256) void back_gather(GatherArgs a)
             *p = acc[r];
         } else if (a.mode == 1) {
             *p += acc[r];
-        } else {
+        } else if (a.mode == 2) {
             const float sv = a.sens[base + k];
             if (sv > 0.f) *p = *p * acc[r] / sv;
+        } else {
+            const float sa = a.bt.sens_all[base + k];
+            if (sa > 0.f) {
+                const float fv = *p;
+                const float step = acc[r] - a.sens[base + k] - a.bt.c_beta * a.bt.prior[base + k];
+                *p = fmaxf(0.f, fv + fv * a.bt.a_over_c / sa * step);
+            }
         }
     }
 }
@@ -784,6 +801,72 @@ __global__ __launch_bounds__(256) void fill_zero(float *p, size_t n)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.f;
+}
+
+// out = sum of n volumes spaced `stride` floats apart from `first`.
+__global__ __launch_bounds__(256) void vol_sum(const float *first, size_t stride, int n, float *out, size_t count)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float acc = 0.f;
+    for (int m = 0; m < n; ++m) acc += first[m * stride + i];
+    out[i] = acc;
+}
+
+// ------------------------------------------------ relative difference prior --
+//
+// Gradient of V(f) = sum_r sum_{s in N(r)} w_rs phi(f_r, f_s) with the
+// relative difference weighting phi(a, b) = (a - b)^2 / (a + b + gamma |a - b|)
+// (Table 1): dV/df_r = 2 sum_s w_rs (f_r - f_s)(f_r + 3 f_s + gamma |f_r - f_s|)
+// / (f_r + f_s + gamma |f_r - f_s|)^2 over the 26 neighbours inside the grid,
+// w = 1 / distance; a pair with a zero denominator contributes 0.  One thread
+// per voxel, z fastest so that a wave reads contiguous z-runs of each of the
+// 27 columns it touches.
+__device__ __forceinline__ float rdp_pair(float a, float b, float gamma)
+{
+    const float d = a - b, ad = fabsf(d);
+    const float den = fmaf(gamma, ad, a + b);
+    const float num = d * fmaf(gamma, ad, fmaf(3.f, b, a));
+    return den > 0.f ? num * __builtin_amdgcn_rcpf(den * den) : 0.f;
+}
+
+struct RdpArgs {
+    const float *f;
+    float *grad;
+    int N, Nz;
+    float gamma;
+};
+
+__global__ __launch_bounds__(256) void rdp_grad(RdpArgs a)
+{
+    const int N = a.N, Nz = a.Nz;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)N * N * Nz) return;
+    const int k = (int)(i % Nz);
+    const int y = (int)((i / Nz) % N);
+    const int x = (int)(i / ((size_t)Nz * N));
+    const float fr = a.f[i];
+    const float w2 = 1.41421356237309515f / 2.f, w3 = 1.73205080756887719f / 3.f;
+    float acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;  // face, edge and corner neighbours
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+        if ((unsigned)(x + dx) >= (unsigned)N) continue;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+            if ((unsigned)(y + dy) >= (unsigned)N) continue;
+            const float *col = a.f + ((size_t)(x + dx) * N + (y + dy)) * Nz;
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz) {
+                const int nd = (dx != 0) + (dy != 0) + (dz != 0);
+                if (nd == 0 || (unsigned)(k + dz) >= (unsigned)Nz) continue;
+                const float t = rdp_pair(fr, col[k + dz], a.gamma);
+                if (nd == 1) acc1 += t;
+                else if (nd == 2) acc2 += t;
+                else acc3 += t;
+            }
+        }
+    }
+    a.grad[i] = 2.f * (acc1 + w2 * acc2 + w3 * acc3);
 }
 
 #endif  // SPECT_HOST_TU

@@ -63,6 +63,15 @@ C2 = Workload("osem_128cube_120ang_att", n=128, nz=128, n_angles=120, with_mu=Tr
               n_subsets=8, total_counts=5e6, seed_index=1)
 
 
+# BSREM with the relative difference prior on the 128^3 data (the paper's
+# examples run 40 iterations of 6 subsets with beta = 0.3, gamma = 2; here
+# 40 iterations of the 8 subsets of the 120-angle acquisition).
+C6 = Workload("bsrem_rdp_128cube_120ang_att", n=128, nz=128, n_angles=120, with_mu=True, n_iters=40,
+              n_subsets=8, total_counts=5e6, seed_index=1)
+RDP_BETA = 0.3
+RDP_GAMMA = 2.0
+
+
 # The differentiable-projector workload: a batch of 8 torso phantoms at the
 # 128^3, 120-angle geometry; 10 unrolled OSEM subiterations (8 subsets) from
 # a uniform image, loss = mean squared error to each phantom.

@@ -113,3 +113,12 @@ def test_table_calls_reject_null_plan_and_bad_sizes():
     assert lib.spect_fwd_table(None, None, None, None, None, 0, None, 0, None) == B.SPECT_EINVAL
     assert lib.spect_back_table(None, None, None, None, None, 0, 0, None, 0, None) == B.SPECT_EINVAL
     assert lib.spect_last_error().decode() != ""
+
+
+def test_bsrem_calls_reject_null_plan():
+    lib = S.load_library()
+    assert lib.spect_rdp_gradient(None, None, None, 2.0, None) == B.SPECT_EINVAL
+    assert lib.bsrem_subset_step(None, None, None, None, None, None, None, 0, 1, 1.0, 0.3, 2.0,
+                                 None, 0, None) == B.SPECT_EINVAL
+    assert lib.bsrem_reconstruct(None, None, None, None, None, 1, 1, 0.3, 2.0, None, None, 0,
+                                 None) == B.SPECT_EINVAL
