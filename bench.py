@@ -1,11 +1,12 @@
 """Benchmark of the SPECT OSEM hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--recon-only]
-                    [--workload osem|unrolled]
+                    [--workload osem|unrolled|bsrem]
 
 The default workload (osem) is the headline measurement below;
 --workload unrolled measures the differentiable projector pair instead
-(bench_unrolled).  --recon-only runs the data generation and the timed reconstructions only
+(bench_unrolled), --workload bsrem BSREM with the relative difference prior
+(bench_bsrem).  --recon-only runs the data generation and the timed reconstructions only
 (no per-kernel timing, context passes or CPU baseline); hardware-counter
 runs use it so that every kernel they see after the data generation belongs
 to a reconstruction.
@@ -161,7 +162,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--recon-only", action="store_true")
-    ap.add_argument("--workload", choices=("osem", "unrolled"), default="osem")
+    ap.add_argument("--workload", choices=("osem", "unrolled", "bsrem"), default="osem")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -180,6 +181,8 @@ def main():
     del src, dst
     if args.workload == "unrolled":
         bench_unrolled(args)
+    elif args.workload == "bsrem":
+        bench_bsrem(args)
     else:
         bench_osem(args)
 
@@ -384,6 +387,90 @@ def bench_unrolled(args):
                                "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
                                "kind": "oracle",
                                "sample": f"one member's FP64 loss and gradient (sensitivities included): {dt:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
+def bench_bsrem(args):
+    """BSREM-RDP (beta 0.3, gamma 2) on the 128^3, 120-angle data: one step =
+    one whole reconstruction of 40 iterations x 8 subsets through
+    bsrem_reconstruct (sensitivities and attenuation tables included)."""
+    w = P.C6
+    args.steps = 3 if args.steps is None else args.steps
+    args.warmup = 1 if args.warmup is None else args.warmup
+    plan = S.Plan.for_workload(w)
+    f_true, mu_np = P.make_phantom(w)
+    mu = torch.from_numpy(mu_np).cuda()
+    _, noise = P.rngs(w.seed_index)
+    g = torch.from_numpy(P.poisson_counts(plan.forward(torch.from_numpy(f_true).cuda(), mu).cpu().numpy(),
+                                          w.total_counts, noise)).cuda()
+    f = torch.empty(w.object_shape, device="cuda")
+    log(f"workload {w.name}: data ready")
+
+    def step():
+        f.fill_(1.0)
+        plan.bsrem(g, w.n_iters, w.n_subsets, mu, f=f, beta=P.RDP_BETA, gamma=P.RDP_GAMMA)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    t0 = time.perf_counter()
+    evs[0].record(st)
+    for i in range(args.steps):
+        step()
+        evs[i + 1].record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+    ms = float(per.mean())
+    log(f"BSREM-RDP reconstruction: mean {ms:.2f} ms (events), {wall * 1e3 / args.steps:.2f} ms (wall)")
+    kernels = kernel_stats(step, 1)
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    flop_r, bytes_r = recon_work(w, dom, uses_att_table(w))
+    per_recon = kernels[dom]["launches"]
+    dur = kernels[dom]["avg_ms"] * 1e-3
+    tflops = flop_r / per_recon / dur / 1e12
+    gbs = bytes_r / per_recon / dur / 1e9
+    # the prior stencil: reads the image and writes its gradient, 8 B per voxel
+    rdp = kernels.get("rdp_grad")
+    rdp_gbs = 8.0 * w.n * w.n * w.nz / (rdp["avg_ms"] * 1e-3) / 1e9 if rdp else None
+    out = {
+        "metric": "BSREM-RDP reconstruction latency at 128^3x120 (40 it x 8 subsets)",
+        "value": ms,
+        "unit": "ms",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "nz": w.nz, "n_angles": w.n_angles,
+                   "iterations": w.n_iters, "subsets": w.n_subsets, "beta": P.RDP_BETA,
+                   "gamma": P.RDP_GAMMA, "relaxation": "1/(1+k)"},
+        "voxel_angle_projections_per_s": w.voxel_angles * (w.n_iters + 0.5) / (ms * 1e-3),
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": tflops,
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": None},
+        "roofline_hbm": {"kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS},
+        "prior_kernel": None if rdp is None else {
+            "kernel": "rdp_grad", "avg_ms": rdp["avg_ms"], "bound": "hbm", "achieved": rdp_gbs,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": rdp_gbs / HBM_PEAK_GBS},
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        log("timing one FP64 oracle BSREM iteration on the host")
+        O = _oracle()
+        og = O.Geometry(w.n, w.nz, w.n_angles, w.voxel_cm, w.psf_a, w.psf_b, w.psf_nsigma)
+        _, noise = P.rngs(w.seed_index)
+        g0 = P.poisson_counts(O.forward(og, f_true.astype(np.float64), mu_np.astype(np.float64)),
+                              w.total_counts, noise).astype(np.float64)
+        t0 = time.perf_counter()
+        O.bsrem(og, g0, mu_np.astype(np.float64), 1, w.n_subsets, P.RDP_BETA, P.RDP_GAMMA)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": dt * w.n_iters * 1e3, "unit": "ms",
+                               "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                               "kind": "oracle",
+                               "sample": f"one FP64 iteration (8 subiterations, sensitivities included): {dt:.1f} s, "
+                                         f"scaled to {w.n_iters} iterations"}
     print(json.dumps(out), flush=True)
 
 
