@@ -83,6 +83,7 @@ extern "C" {
 #define SPECT_MAX_K 32         /* collimator blur radius in pixels */
 
 typedef struct spect_plan spect_plan;
+typedef struct spect_batch spect_batch;
 
 /* Acquisition geometry (Section 2.1.1: projection space V of 2D images, one
  * per angle; object space U of voxelised activity). */
@@ -145,6 +146,58 @@ int spect_back(const spect_plan *plan, const float *proj, const float *mu, float
 int spect_sensitivity(const spect_plan *plan, const float *mu, float *sens,
                       const int32_t *angle_idx, int32_t n_idx, void *ws, size_t ws_bytes,
                       void *stream);
+
+/* Batched OSEM: many reconstructions of different geometries at once (studies
+ * over many patients, noise realisations and algorithms, Section 4; the OSEM
+ * of Section 2.1.3, Eq. 5 with the Table 1 preconditioner, as in
+ * osem_reconstruct).
+ *
+ * A batch holds R member geometries (plans, which must outlive it) and a
+ * common subset count M.  osem_batch_reconstruct runs, for every member, the
+ * computation of osem_reconstruct with the same subsets; subiteration m of all
+ * members is one batched launch per stage (forward projection with the ratio,
+ * rotated-frame adjoint, gather with the multiplicative update) over a
+ * work-list of (member, angle, axial slab, depth chunk) tasks.  Each member's
+ * state lives in its own region of one workspace (spect_batch_workspace_size
+ * bytes, 256-byte aligned, caller-owned; it also holds copies of the images
+ * for osem_batch_autotune).  Results equal osem_reconstruct per member.
+ *
+ * Arrays f, mu, g, s_add are host arrays of R device pointers, laid out as in
+ * osem_reconstruct; mu must be given for every member if the batch was created
+ * with_mu != 0 (attenuation-factor tables are then kept per member and
+ * subset) and must be NULL (or hold NULLs) otherwise; s_add may be NULL.
+ *
+ * Schedules (spect_batch_set_schedule, osem_batch_autotune): bit 0 set = one
+ * launch per stage for each group of members with equal block size and blur
+ * class, clear = one launch for all members; bit 1 set = persistent grids
+ * (workgroups loop over tasks), clear = one task per workgroup.
+ *
+ * By default one iteration (the M subiterations) is captured once as a HIP
+ * graph on an internal stream and replayed on `stream` n_iters times;
+ * SPECT_BATCH_EAGER launches the kernels directly instead.  A batch is not
+ * reentrant: calls on it must not overlap. */
+#define SPECT_BATCH_EAGER 1
+
+int spect_batch_create(const spect_plan *const *plans, int32_t n_members, int32_t n_subsets,
+                       int with_mu, spect_batch **out);
+int spect_batch_destroy(spect_batch *batch);
+int spect_batch_workspace_size(const spect_batch *batch, size_t *bytes);
+int osem_batch_reconstruct(spect_batch *batch, float *const *f, const float *const *mu,
+                           const float *const *g, const float *const *s_add, int32_t n_iters,
+                           int32_t flags, void *ws, size_t ws_bytes, void *stream);
+
+/* Autotuner: times one graph-replayed iteration of every schedule on copies
+ * of the images (the sensitivities are computed first; f is not changed),
+ * keeps the fastest as the batch's schedule and records the times.
+ * Synchronises the stream. */
+int osem_batch_autotune(spect_batch *batch, float *const *f, const float *const *mu,
+                        const float *const *g, const float *const *s_add, void *ws,
+                        size_t ws_bytes, void *stream);
+
+/* The current schedule and, in candidate_ms[0..3] (may be NULL), the
+ * autotuner's per-iteration times (-1 where not measured). */
+int spect_batch_schedule(const spect_batch *batch, int32_t *schedule, double *candidate_ms);
+int spect_batch_set_schedule(spect_batch *batch, int32_t schedule);
 
 /* Attenuation-factor tables (T_att of Eq. 1 evaluated once).  For a fixed
  * attenuation map and angle list the factors exp(-tau) do not change between

@@ -27,10 +27,12 @@ ATT_TABLE = 2   # with_mu code of the attenuation-table calls
 EXPORTS = ("spect_plan_create", "spect_plan_destroy", "spect_workspace_size", "spect_fwd",
            "spect_back", "spect_sensitivity", "spect_table_size", "spect_sensitivity_table",
            "spect_fwd_table", "spect_back_table", "osem_subset_step", "osem_reconstruct",
-           "spect_rdp_gradient", "bsrem_subset_step", "bsrem_reconstruct", "spect_profile_enable",
+           "spect_rdp_gradient", "bsrem_subset_step", "bsrem_reconstruct", "spect_batch_create",
+           "spect_batch_destroy", "spect_batch_workspace_size", "osem_batch_reconstruct", "osem_batch_autotune",
+           "spect_batch_schedule", "spect_batch_set_schedule", "spect_profile_enable",
            "spect_profile_reset", "spect_profile_query", "spect_last_error")
 KERNELS = ("tau_prepass", "fwd_main", "fwd_reduce", "back_rot", "back_gather", "fill_zero", "rdp_grad",
-           "vol_sum")
+           "vol_sum", "fwd_batch", "reduce_batch", "back_batch", "gather_batch")
 
 
 class SpectError(RuntimeError):
@@ -78,6 +80,14 @@ def load_library(path: Optional[str] = None):
     lib.spect_rdp_gradient.argtypes = [vp, vp, vp, f32, vp]
     lib.bsrem_subset_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, i32, f32, f32, f32, vp, sz, vp]
     lib.bsrem_reconstruct.argtypes = [vp, vp, vp, vp, vp, i32, i32, f32, f32, ctypes.POINTER(f32), vp, sz, vp]
+    vpp = ctypes.POINTER(vp)
+    lib.spect_batch_create.argtypes = [vpp, i32, i32, ctypes.c_int, vpp]
+    lib.spect_batch_destroy.argtypes = [vp]
+    lib.spect_batch_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.osem_batch_reconstruct.argtypes = [vp, vpp, vpp, vpp, vpp, i32, i32, vp, sz, vp]
+    lib.osem_batch_autotune.argtypes = [vp, vpp, vpp, vpp, vpp, vp, sz, vp]
+    lib.spect_batch_schedule.argtypes = [vp, i32p, ctypes.POINTER(ctypes.c_double)]
+    lib.spect_batch_set_schedule.argtypes = [vp, i32]
     lib.spect_profile_enable.argtypes = [ctypes.c_int]
     lib.spect_profile_reset.argtypes = []
     lib.spect_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
@@ -395,3 +405,78 @@ def _bsrem_method(self, g: torch.Tensor, n_iters: int, n_subsets: int, mu: Optio
 Plan.rdp_gradient = _rdp_gradient
 Plan.bsrem_subset_step = _bsrem_step
 Plan.bsrem = _bsrem_method
+
+
+BATCH_EAGER = 1
+
+
+class Batch:
+    """Batched OSEM over several geometries (spect_batch_*).
+
+    batch = Batch([plan_a, plan_b, ...], n_subsets=8, with_mu=True)
+    batch.autotune(fs, mus, gs)               # optional: pick the fastest schedule
+    batch.reconstruct(fs, mus, gs, n_iters)   # fs updated in place
+    """
+
+    def __init__(self, plans: Sequence[Plan], n_subsets: int, with_mu: bool):
+        lib = load_library()
+        self.plans = list(plans)
+        self.n_subsets = int(n_subsets)
+        self.with_mu = bool(with_mu)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib.spect_batch_create(arr, len(self.plans), self.n_subsets, int(self.with_mu), ctypes.byref(h)))
+        self._h = h
+        b = ctypes.c_size_t()
+        _check(lib.spect_batch_workspace_size(self._h, ctypes.byref(b)))
+        self.workspace_bytes = b.value
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().spect_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _arrays(self, fs, mus, gs, ss):
+        R = len(self.plans)
+        if len(fs) != R or len(gs) != R:
+            raise ValueError(f"need {R} images and {R} data sets")
+        fa = (ctypes.c_void_p * R)(*[_ptr(f, p.object_shape, "f").value for f, p in zip(fs, self.plans)])
+        ga = (ctypes.c_void_p * R)(*[_ptr(g, p.proj_shape, "g").value for g, p in zip(gs, self.plans)])
+        ma = None if mus is None else (ctypes.c_void_p * R)(
+            *[_ptr(m, p.object_shape, "mu").value for m, p in zip(mus, self.plans)])
+        sa = None if ss is None else (ctypes.c_void_p * R)(
+            *[None if s is None else _ptr(s, p.proj_shape, "s_add").value for s, p in zip(ss, self.plans)])
+        if self._ws is None:
+            self._ws = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device="cuda")
+        return fa, ma, ga, sa
+
+    def reconstruct(self, fs, mus, gs, n_iters: int, s_adds=None, eager: bool = False):
+        fa, ma, ga, sa = self._arrays(fs, mus, gs, s_adds)
+        _check(load_library().osem_batch_reconstruct(self._h, fa, ma, ga, sa, int(n_iters),
+                                                      BATCH_EAGER if eager else 0,
+                                                      ctypes.c_void_p(self._ws.data_ptr()), self._ws.numel(),
+                                                      _stream()))
+        return fs
+
+    def autotune(self, fs, mus, gs, s_adds=None):
+        fa, ma, ga, sa = self._arrays(fs, mus, gs, s_adds)
+        _check(load_library().osem_batch_autotune(self._h, fa, ma, ga, sa, ctypes.c_void_p(self._ws.data_ptr()),
+                                                   self._ws.numel(), _stream()))
+        return self.schedule()
+
+    def schedule(self):
+        """(schedule, [ms per iteration of each candidate, -1 if not timed])."""
+        s = ctypes.c_int32()
+        ms = (ctypes.c_double * 4)()
+        _check(load_library().spect_batch_schedule(self._h, ctypes.byref(s), ms))
+        return s.value, list(ms)
+
+    def set_schedule(self, schedule: int):
+        _check(load_library().spect_batch_set_schedule(self._h, int(schedule)))

@@ -38,9 +38,13 @@ namespace {
 // Optional per-kernel timing: while enabled, every launch is bracketed by two
 // HIP events recorded on the launch's own stream.
 
-enum KernelId { K_TAU = 0, K_FWD, K_REDUCE, K_BACK_ROT, K_GATHER, K_FILL, K_RDP, K_SUM, K_COUNT };
+enum KernelId {
+    K_TAU = 0, K_FWD, K_REDUCE, K_BACK_ROT, K_GATHER, K_FILL, K_RDP, K_SUM,
+    K_FWD_B, K_REDUCE_B, K_BACK_B, K_GATHER_B, K_COUNT
+};
 const char *const kKernelNames[K_COUNT] = {"tau_prepass", "fwd_main", "fwd_reduce", "back_rot",
-                                           "back_gather", "fill_zero", "rdp_grad", "vol_sum"};
+                                           "back_gather", "fill_zero", "rdp_grad", "vol_sum",
+                                           "fwd_batch", "reduce_batch", "back_batch", "gather_batch"};
 
 struct ProfRec {
     int kernel;
@@ -56,10 +60,11 @@ struct ProfScope {
     hipStream_t st;
     hipEvent_t a = nullptr, b = nullptr;
     bool on;
-    ProfScope(int k, hipStream_t s) : kernel(k), st(s)
+    // allowed = false while a stream is being captured into a graph
+    ProfScope(int k, hipStream_t s, bool allowed = true) : kernel(k), st(s)
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
-        on = g_prof_on;
+        on = g_prof_on && allowed;
         if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
             (void)hipEventRecord(a, st);
         else
@@ -347,20 +352,51 @@ BackFn back_kernel(int att, int kmc, bool vec)
     }
 }
 
+FwdBatchFn fwd_batch_kernel(int att, int kmc, bool vec, bool persist)
+{
+    switch (kmc) {
+    case 0: return fwd_batch_kmc0(att, vec, persist);
+    case 4: return fwd_batch_kmc4(att, vec, persist);
+    case 8: return fwd_batch_kmc8(att, vec, persist);
+    case 12: return fwd_batch_kmc12(att, vec, persist);
+    case 16: return fwd_batch_kmc16(att, vec, persist);
+    case 20: return fwd_batch_kmc20(att, vec, persist);
+    case 24: return fwd_batch_kmc24(att, vec, persist);
+    case 28: return fwd_batch_kmc28(att, vec, persist);
+    default: return fwd_batch_kmc32(att, vec, persist);
+    }
+}
+
+BackBatchFn back_batch_kernel(int att, int kmc, bool vec, bool persist)
+{
+    switch (kmc) {
+    case 0: return back_batch_kmc0(att, vec, persist);
+    case 4: return back_batch_kmc4(att, vec, persist);
+    case 8: return back_batch_kmc8(att, vec, persist);
+    case 12: return back_batch_kmc12(att, vec, persist);
+    case 16: return back_batch_kmc16(att, vec, persist);
+    case 20: return back_batch_kmc20(att, vec, persist);
+    case 24: return back_batch_kmc24(att, vec, persist);
+    case 28: return back_batch_kmc28(att, vec, persist);
+    default: return back_batch_kmc32(att, vec, persist);
+    }
+}
+
 int block_threads(int N) { return std::min(512, ((2 * N + 63) / 64) * 64); }
 
-size_t wb_bytes(const spect_plan *p) { return sizeof(float4) * 2 * 2 * 2 * (size_t)(p->N + 2 * p->kmc); }
+size_t wb_bytes(int N, int kmc) { return sizeof(float4) * 2 * 2 * 2 * (size_t)(N + 2 * kmc); }
 
-size_t fwd_smem(const spect_plan *p)
+size_t fwd_smem(int N, int kmc)
 {
-    const size_t merge = sizeof(float) * (size_t)p->N * (ROWS + 2 * p->kmc + 1);
-    return std::max(wb_bytes(p), merge);
+    const size_t merge = sizeof(float) * (size_t)N * (ROWS + 2 * kmc + 1);
+    return std::max(wb_bytes(N, kmc), merge);
 }
 
-size_t back_smem(const spect_plan *p)
-{
-    return wb_bytes(p) + sizeof(float) * (size_t)p->N * (SLAB + 2 * p->kmc + 1);
-}
+size_t back_smem(int N, int kmc) { return wb_bytes(N, kmc) + sizeof(float) * (size_t)N * (SLAB + 2 * kmc + 1); }
+
+size_t wb_bytes(const spect_plan *p) { return wb_bytes(p->N, p->kmc); }
+size_t fwd_smem(const spect_plan *p) { return fwd_smem(p->N, p->kmc); }
+size_t back_smem(const spect_plan *p) { return back_smem(p->N, p->kmc); }
 
 // Kernels that need more than 64 KiB of dynamic LDS must say so first.
 void allow_smem(const void *fn, size_t bytes)
@@ -1165,6 +1201,600 @@ int bsrem_subset_step(const spect_plan *plan, float *f, const float *mu, const f
                        3, f, sens_m, vec, T_BOTH, s, &bt)))
         return st;
     return ok();
+}
+
+}  // extern "C"
+
+// ==================================================== batched OSEM ====
+//
+// Many reconstructions of different geometries advance together: subiteration
+// m of every member runs as one batched launch per stage (forward, ratio,
+// rotated-frame adjoint, gather with the OSEM update) over a work-list of
+// (member, angle, slab, depth-chunk) tasks.  Each member keeps its whole OSEM
+// state (sensitivities, attenuation tables, ratio, scratch) in its own region
+// of one workspace.  One iteration (M subiterations) is recorded once as a
+// HIP graph and replayed.  The schedule (members in one launch per stage or
+// one launch per size class; persistent or one-task-per-workgroup grids) is
+// chosen by timing the candidates (osem_batch_autotune).
+
+struct BatchLaunch {
+    int threads = 0;
+    size_t fsmem = 0, bsmem = 0;
+    FwdBatchFn fk = nullptr;
+    BackBatchFn bk = nullptr;
+    BatchList<FwdArgs> fwd{};
+    BatchList<ReduceArgs> red{};
+    BatchList<BackRotArgs> back{};
+    BatchList<GatherArgs> gat{};
+    int gf = 0, gr = 0, gb = 0, gg = 0;  // grid sizes
+};
+
+struct spect_batch {
+    int R = 0, M = 0, device = 0, cus = 256;
+    bool mu = false;
+    std::vector<const spect_plan *> plans;
+    std::vector<std::vector<AngleList>> lists;  // [r][m]
+    std::vector<std::vector<Tuning>> tun;       // [r][m], passes of the iterations
+    int kmc_max = 0;
+    std::vector<size_t> base, q_off, scr_off, scr_bytes;
+    std::vector<std::vector<size_t>> tab_off;   // [r][m], relative to base[r]
+    size_t regions = 0, ws_total = 0;
+    int sched = 0;                              // bit 0: one launch per size class; bit 1: persistent
+    double cand_ms[4] = {-1.0, -1.0, -1.0, -1.0};
+    std::vector<std::vector<BatchLaunch>> steps;  // [m][group]
+    void *dmem = nullptr;
+    size_t dmem_bytes = 0;
+    std::vector<const void *> key;
+    int key_sched = -1;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_sched = -1;
+};
+
+namespace {
+
+int batch_att(const spect_batch *b) { return b->mu ? ATT_READ : ATT_NONE; }
+
+size_t batch_part_bytes(const spect_plan *p, const Tuning &t, int nl, int kmc)
+{
+    return align256(sizeof(float) * (size_t)nl * t.nslab * t.nchunk * p->N * (SLAB + 2 * kmc));
+}
+
+void drop_graph(spect_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_sched = -1;
+}
+
+struct Ptrs {
+    float *const *f;
+    const float *const *mu;
+    const float *const *g;
+    const float *const *s;
+    char *ws;
+};
+
+template <class T>
+size_t put(std::vector<char> &blob, const std::vector<T> &v)
+{
+    const size_t off = (blob.size() + 255) & ~size_t(255);
+    blob.resize(off + sizeof(T) * v.size());
+    if (!v.empty()) std::memcpy(blob.data() + off, v.data(), sizeof(T) * v.size());
+    return off;
+}
+
+// Build the launch tables of schedule `sched` for the given arrays and upload
+// them.  Waits for the device first: replays of an earlier build may still
+// read the tables.
+int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
+{
+    const int att = batch_att(b);
+    const bool grouped = sched & 1, persist = sched & 2;
+    // groups: members sharing block size and blur class, or all members
+    std::vector<std::vector<int>> groups;
+    std::vector<int> gkmc, gthreads;
+    if (grouped) {
+        std::vector<std::pair<std::pair<int, int>, int>> keys;
+        for (int r = 0; r < b->R; ++r) keys.push_back({{block_threads(b->plans[r]->N), b->plans[r]->kmc}, r});
+        std::stable_sort(keys.begin(), keys.end(),
+                         [](const auto &x, const auto &y) { return x.first < y.first; });
+        for (size_t i = 0; i < keys.size(); ++i) {
+            if (i == 0 || keys[i].first != keys[i - 1].first) {
+                groups.emplace_back();
+                gthreads.push_back(keys[i].first.first);
+                gkmc.push_back(keys[i].first.second);
+            }
+            groups.back().push_back(keys[i].second);
+        }
+    } else {
+        groups.emplace_back();
+        int th = 64;
+        for (int r = 0; r < b->R; ++r) {
+            groups.back().push_back(r);
+            th = std::max(th, block_threads(b->plans[r]->N));
+        }
+        gthreads.push_back(th);
+        gkmc.push_back(b->kmc_max);
+    }
+    struct Offs {
+        size_t fa, ft, ra, rt, ba, bt, ga, gt;
+        int nf, nr, nb, ng;
+    };
+    std::vector<char> blob;
+    std::vector<std::vector<Offs>> offs(b->M);
+    for (int m = 0; m < b->M; ++m) {
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            const int kmc = gkmc[gi];
+            std::vector<FwdArgs> fa;
+            std::vector<ReduceArgs> ra;
+            std::vector<BackRotArgs> ba;
+            std::vector<GatherArgs> ga;
+            std::vector<std::pair<long, Task>> ft, bt;
+            std::vector<Task> rt, gt;
+            for (size_t li = 0; li < groups[gi].size(); ++li) {
+                const int r = groups[gi][li];
+                const spect_plan *p = b->plans[r];
+                const AngleList &L = b->lists[r][m];
+                const Tuning &t = b->tun[r][m];
+                char *base = P.ws + b->base[r];
+                float *tab = b->mu ? reinterpret_cast<float *>(base + b->tab_off[r][m]) : nullptr;
+                float *q = reinterpret_cast<float *>(base + b->q_off[r]);
+                float *scr = reinterpret_cast<float *>(base + b->scr_off[r]);
+                float *sens = reinterpret_cast<float *>(base + (size_t)m * vol_bytes(p));
+                FwdArgs a{};
+                a.g = p->g;
+                a.L = L;
+                a.f = P.f[r];
+                a.att = tab;
+                a.part = scr;
+                a.nslab = t.nslab;
+                a.nchunk = t.nchunk;
+                a.dchunk = t.dchunk;
+                a.vec = vec;
+                fa.push_back(a);
+                ReduceArgs rr{};
+                rr.L = L;
+                rr.part = scr;
+                rr.N = p->N;
+                rr.Nz = p->Nz;
+                rr.nslab = t.nslab;
+                rr.nchunk = t.nchunk;
+                rr.kmc = kmc;
+                rr.mode = 1;
+                rr.g = P.g[r];
+                rr.s_add = P.s ? P.s[r] : nullptr;
+                rr.q = q;
+                ra.push_back(rr);
+                BackRotArgs bb{};
+                bb.g = p->g;
+                bb.L = L;
+                bb.y = q;
+                bb.y_compact = 1;
+                bb.att = tab;
+                bb.z = scr;
+                bb.nslab = t.nslab;
+                bb.nchunk = t.nchunk;
+                bb.dchunk = t.dchunk;
+                bb.vec = vec;
+                ba.push_back(bb);
+                GatherArgs gg{};
+                gg.g = p->g;
+                gg.L = L;
+                gg.z = scr;
+                gg.nslab = t.nslab;
+                gg.mode = 2;
+                gg.out = P.f[r];
+                gg.sens = sens;
+                ga.push_back(gg);
+                const int li_ = (int)li;
+                const long cost = (long)t.dchunk * p->N;  // depths x bins of one task
+                for (int al = 0; al < L.n; ++al)
+                    for (int sl = 0; sl < t.nslab; ++sl)
+                        for (int c = 0; c < t.nchunk; ++c) {
+                            const int d = std::min(t.dchunk, p->N - c * t.dchunk);
+                            ft.push_back({(long)d * p->N, Task{li_, sl, c, al}});
+                            bt.push_back({(long)d * p->N, Task{li_, sl, c, al}});
+                        }
+                (void)cost;
+                const int blocks = (p->N * p->Nz + 255) / 256;
+                for (int al = 0; al < L.n; ++al)
+                    for (int k = 0; k < blocks; ++k) rt.push_back(Task{li_, k, 0, al});
+                const int tiles = (p->N + GT - 1) / GT;
+                for (int sl = 0; sl < t.nslab; ++sl)
+                    for (int k = 0; k < tiles * tiles; ++k) gt.push_back(Task{li_, k, sl, 0});
+            }
+            // longest tasks first, so that the tail of the launch is short
+            auto by_cost = [](const std::pair<long, Task> &x, const std::pair<long, Task> &y) {
+                return x.first > y.first;
+            };
+            std::stable_sort(ft.begin(), ft.end(), by_cost);
+            std::stable_sort(bt.begin(), bt.end(), by_cost);
+            std::vector<Task> ftv, btv;
+            for (auto &x : ft) ftv.push_back(x.second);
+            for (auto &x : bt) btv.push_back(x.second);
+            Offs o;
+            o.fa = put(blob, fa);
+            o.ft = put(blob, ftv);
+            o.ra = put(blob, ra);
+            o.rt = put(blob, rt);
+            o.ba = put(blob, ba);
+            o.bt = put(blob, btv);
+            o.ga = put(blob, ga);
+            o.gt = put(blob, gt);
+            o.nf = (int)ftv.size();
+            o.nr = (int)rt.size();
+            o.nb = (int)btv.size();
+            o.ng = (int)gt.size();
+            offs[m].push_back(o);
+        }
+    }
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "batch table update");
+    if (blob.size() > b->dmem_bytes) {
+        if (b->dmem) (void)hipFree(b->dmem);
+        b->dmem = nullptr;
+        b->dmem_bytes = 0;
+        if ((e = hipMalloc(&b->dmem, blob.size())) != hipSuccess)
+            return fail(SPECT_ENOMEM, "hipMalloc of %zu bytes of batch tables failed", blob.size());
+        b->dmem_bytes = blob.size();
+        drop_graph(b);  // the graph's kernel arguments point at the old tables
+    }
+    if ((e = hipMemcpy(b->dmem, blob.data(), blob.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "batch table upload");
+    char *d = static_cast<char *>(b->dmem);
+    b->steps.assign(b->M, {});
+    for (int m = 0; m < b->M; ++m)
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            const Offs &o = offs[m][gi];
+            BatchLaunch l;
+            l.threads = gthreads[gi];
+            int Nmax = 0;
+            for (int r : groups[gi]) Nmax = std::max(Nmax, b->plans[r]->N);
+            l.fsmem = fwd_smem(Nmax, gkmc[gi]);
+            l.bsmem = back_smem(Nmax, gkmc[gi]);
+            l.fk = fwd_batch_kernel(att, gkmc[gi], vec, persist);
+            l.bk = back_batch_kernel(att, gkmc[gi], vec, persist);
+            allow_smem(reinterpret_cast<const void *>(l.fk), l.fsmem);
+            allow_smem(reinterpret_cast<const void *>(l.bk), l.bsmem);
+            l.fwd = {reinterpret_cast<const FwdArgs *>(d + o.fa), reinterpret_cast<const Task *>(d + o.ft), o.nf};
+            l.red = {reinterpret_cast<const ReduceArgs *>(d + o.ra), reinterpret_cast<const Task *>(d + o.rt), o.nr};
+            l.back = {reinterpret_cast<const BackRotArgs *>(d + o.ba), reinterpret_cast<const Task *>(d + o.bt),
+                      o.nb};
+            l.gat = {reinterpret_cast<const GatherArgs *>(d + o.ga), reinterpret_cast<const Task *>(d + o.gt), o.ng};
+            if (persist) {
+                int nb = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(l.fk),
+                                                                  l.threads, l.fsmem) != hipSuccess || nb < 1)
+                    nb = 1;
+                l.gf = std::max(1, std::min(o.nf, nb * b->cus));
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(l.bk),
+                                                                  l.threads, l.bsmem) != hipSuccess || nb < 1)
+                    nb = 1;
+                l.gb = std::max(1, std::min(o.nb, nb * b->cus));
+                l.gr = std::max(1, std::min(o.nr, 8 * b->cus));
+                l.gg = std::max(1, std::min(o.ng, 8 * b->cus));
+            } else {
+                l.gf = std::max(1, o.nf);
+                l.gb = std::max(1, o.nb);
+                l.gr = std::max(1, o.nr);
+                l.gg = std::max(1, o.ng);
+            }
+            b->steps[m].push_back(l);
+        }
+    (void)hipGetLastError();
+    return SPECT_OK;
+}
+
+// Subiteration m of every member, on stream st (capturing: no event timing).
+int launch_step(const spect_batch *b, int m, hipStream_t st, bool capturing)
+{
+    for (const BatchLaunch &l : b->steps[m]) {
+        {
+            ProfScope ps(K_FWD_B, st, !capturing);
+            hipLaunchKernelGGL(l.fk, dim3(l.gf), dim3(l.threads), l.fsmem, st, l.fwd);
+        }
+        {
+            ProfScope ps(K_REDUCE_B, st, !capturing);
+            hipLaunchKernelGGL(reduce_batch, dim3(l.gr), dim3(256), 0, st, l.red);
+        }
+    }
+    for (const BatchLaunch &l : b->steps[m]) {
+        {
+            ProfScope ps(K_BACK_B, st, !capturing);
+            hipLaunchKernelGGL(l.bk, dim3(l.gb), dim3(l.threads), l.bsmem, st, l.back);
+        }
+        {
+            ProfScope ps(K_GATHER_B, st, !capturing);
+            hipLaunchKernelGGL(gather_batch, dim3(l.gg), dim3(256), 0, st, l.gat);
+        }
+    }
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SPECT_OK : hip_fail(e, "batched launch");
+}
+
+// Record one iteration (M subiterations) as a graph.
+int capture_iteration(spect_batch *b)
+{
+    drop_graph(b);
+    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "graph capture begin");
+    int st = SPECT_OK;
+    for (int m = 0; m < b->M && st == SPECT_OK; ++m) st = launch_step(b, m, b->cap, true);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->cap, &g);
+    if (st != SPECT_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "graph capture end");
+    b->graph = g;
+    if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+        drop_graph(b);
+        return hip_fail(e, "graph instantiation");
+    }
+    b->graph_sched = b->sched;
+    return SPECT_OK;
+}
+
+// Sensitivities (and attenuation tables) of every member and subset, with
+// the single-reconstruction kernels.
+int batch_sensitivities(const spect_batch *b, const Ptrs &P, bool vec, hipStream_t st)
+{
+    for (int r = 0; r < b->R; ++r) {
+        const spect_plan *p = b->plans[r];
+        char *base = P.ws + b->base[r];
+        for (int m = 0; m < b->M; ++m) {
+            float *tab = b->mu ? reinterpret_cast<float *>(base + b->tab_off[r][m]) : nullptr;
+            float *sens = reinterpret_cast<float *>(base + (size_t)m * vol_bytes(p));
+            const int st_ = run_back(p, nullptr, 0, 1, b->mu ? P.mu[r] : nullptr, b->mu ? ATT_WRITE : ATT_NONE, tab,
+                                     b->lists[r][m], base + b->scr_off[r], b->scr_bytes[r], nullptr, 0, sens, nullptr,
+                                     vec, T_BACK, st);
+            if (st_) return st_;
+        }
+    }
+    return SPECT_OK;
+}
+
+int check_batch_args(const spect_batch *b, const Ptrs &P, size_t ws_bytes, bool *vec)
+{
+    int st;
+    if (!b) return fail(SPECT_EINVAL, "batch is NULL");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
+        return fail(SPECT_EINVAL, "current HIP device %d is not the batch's device %d", dev, b->device);
+    if (!P.f || !P.g) return fail(SPECT_EINVAL, "f and g arrays must not be NULL");
+    if (b->mu && !P.mu) return fail(SPECT_EINVAL, "the batch was created with attenuation: mu array is NULL");
+    *vec = true;
+    for (int r = 0; r < b->R; ++r) {
+        if ((st = check_ptr(P.f[r], "f[r]", false)) || (st = check_ptr(P.g[r], "g[r]", false))) return st;
+        if (b->mu && (st = check_ptr(P.mu[r], "mu[r]", false))) return st;
+        if (!b->mu && P.mu && P.mu[r]) return fail(SPECT_EINVAL, "the batch was created without attenuation");
+        if (P.s && (st = check_ptr(P.s[r], "s_add[r]", true))) return st;
+        if (b->plans[r]->Nz % 4 || !aligned16(P.f[r]) || (b->mu && !aligned16(P.mu[r]))) *vec = false;
+    }
+    return check_ws(P.ws, ws_bytes, b->ws_total);
+}
+
+// (Re)build the tables when the arrays or the schedule changed.
+int prepare(spect_batch *b, const Ptrs &P, bool vec)
+{
+    std::vector<const void *> key;
+    for (int r = 0; r < b->R; ++r) {
+        key.push_back(P.f[r]);
+        key.push_back(P.g[r]);
+        key.push_back(b->mu ? P.mu[r] : nullptr);
+        key.push_back(P.s ? P.s[r] : nullptr);
+    }
+    key.push_back(P.ws);
+    key.push_back(reinterpret_cast<const void *>((uintptr_t)vec));
+    if (key == b->key && b->key_sched == b->sched) return SPECT_OK;
+    const int st = build_tables(b, P, vec, b->sched);
+    if (st) return st;
+    b->key = key;
+    b->key_sched = b->sched;
+    return SPECT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int spect_batch_create(const spect_plan *const *plans, int32_t n_members, int32_t n_subsets, int with_mu,
+                       spect_batch **out)
+{
+    if (!out) return fail(SPECT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!plans) return fail(SPECT_EINVAL, "plans is NULL");
+    if (n_members < 1) return fail(SPECT_EINVAL, "n_members = %d must be >= 1", n_members);
+    if (n_subsets < 1) return fail(SPECT_EINVAL, "n_subsets = %d must be >= 1", n_subsets);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(SPECT_EHIP, "no HIP device");
+    for (int r = 0; r < n_members; ++r) {
+        if (!plans[r]) return fail(SPECT_EINVAL, "plans[%d] is NULL", r);
+        if (plans[r]->device != dev) return fail(SPECT_EINVAL, "plans[%d] belongs to another device", r);
+        if (n_subsets > plans[r]->A)
+            return fail(SPECT_EINVAL, "n_subsets %d exceeds n_angles %d of member %d", n_subsets, plans[r]->A, r);
+        if ((plans[r]->A + n_subsets - 1) / n_subsets > MAXL)
+            return fail(SPECT_EUNSUPPORTED, "member %d has subsets of more than %d angles", r, MAXL);
+    }
+    spect_batch *b = new spect_batch();
+    b->R = n_members;
+    b->M = n_subsets;
+    b->device = dev;
+    b->mu = with_mu != 0;
+    if (hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || b->cus < 1)
+        b->cus = 256;
+    const int att = batch_att(b);
+    size_t off = 0;
+    for (int r = 0; r < n_members; ++r) {
+        const spect_plan *p = plans[r];
+        b->plans.push_back(p);
+        b->kmc_max = std::max(b->kmc_max, p->kmc);
+    }
+    for (int r = 0; r < n_members; ++r) {
+        const spect_plan *p = b->plans[r];
+        std::vector<AngleList> ls;
+        std::vector<Tuning> ts;
+        std::vector<size_t> tabs;
+        size_t rel = (size_t)n_subsets * vol_bytes(p), scr = 0;
+        for (int m = 0; m < n_subsets; ++m) {
+            std::vector<int> list;
+            for (int n = m; n < p->A; n += n_subsets) list.push_back(n);
+            ls.push_back(to_list(list.data(), (int)list.size()));
+            const int nl = (int)list.size();
+            const Tuning t = tune(p, nl, att, T_BOTH);
+            ts.push_back(t);
+            tabs.push_back(rel);
+            if (b->mu) rel += table_bytes(p, nl);
+            scr = std::max(scr, batch_part_bytes(p, t, nl, b->kmc_max));
+            scr = std::max(scr, z_bytes(p, t, nl));
+            scr = std::max(scr, back_need(p, nl, b->mu ? ATT_WRITE : ATT_NONE, T_BACK));
+        }
+        b->lists.push_back(ls);
+        b->tun.push_back(ts);
+        b->tab_off.push_back(tabs);
+        b->q_off.push_back(rel);
+        rel += osem_q_bytes(p, n_subsets);
+        b->scr_off.push_back(rel);
+        b->scr_bytes.push_back(scr);
+        rel += scr;
+        b->base.push_back(off);
+        off += align256(rel);
+    }
+    b->regions = off;
+    b->ws_total = off;
+    for (int r = 0; r < n_members; ++r) b->ws_total += vol_bytes(b->plans[r]);  // image copies for tuning
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+        delete b;
+        return fail(SPECT_EHIP, "stream creation failed");
+    }
+    *out = b;
+    return ok();
+}
+
+int spect_batch_destroy(spect_batch *b)
+{
+    if (!b) return ok();
+    (void)hipDeviceSynchronize();
+    drop_graph(b);
+    if (b->dmem) (void)hipFree(b->dmem);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+    return ok();
+}
+
+int spect_batch_workspace_size(const spect_batch *b, size_t *bytes)
+{
+    if (!b) return fail(SPECT_EINVAL, "batch is NULL");
+    if (!bytes) return fail(SPECT_EINVAL, "bytes is NULL");
+    *bytes = b->ws_total;
+    return ok();
+}
+
+int spect_batch_schedule(const spect_batch *b, int32_t *schedule, double *candidate_ms)
+{
+    if (!b) return fail(SPECT_EINVAL, "batch is NULL");
+    if (schedule) *schedule = b->sched;
+    if (candidate_ms)
+        for (int c = 0; c < 4; ++c) candidate_ms[c] = b->cand_ms[c];
+    return ok();
+}
+
+int spect_batch_set_schedule(spect_batch *b, int32_t schedule)
+{
+    if (!b) return fail(SPECT_EINVAL, "batch is NULL");
+    if (schedule < 0 || schedule > 3) return fail(SPECT_EINVAL, "schedule = %d outside [0, 3]", schedule);
+    b->sched = schedule;
+    return ok();
+}
+
+int osem_batch_reconstruct(spect_batch *b, float *const *f, const float *const *mu, const float *const *g,
+                           const float *const *s_add, int32_t n_iters, int32_t flags, void *ws, size_t ws_bytes,
+                           void *stream)
+{
+    int st;
+    const Ptrs P{f, mu, g, s_add, static_cast<char *>(ws)};
+    bool vec = true;
+    if ((st = check_batch_args(b, P, ws_bytes, &vec))) return st;
+    if (n_iters < 0) return fail(SPECT_EINVAL, "n_iters = %d is negative", n_iters);
+    if (flags & ~SPECT_BATCH_EAGER) return fail(SPECT_EINVAL, "unknown flags 0x%x", (unsigned)flags);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = batch_sensitivities(b, P, vec, s))) return st;
+    if (n_iters == 0) return ok();
+    if ((st = prepare(b, P, vec))) return st;
+    if (flags & SPECT_BATCH_EAGER) {
+        for (int it = 0; it < n_iters; ++it)
+            for (int m = 0; m < b->M; ++m)
+                if ((st = launch_step(b, m, s, false))) return st;
+        return ok();
+    }
+    if (!b->exec || b->graph_sched != b->sched)
+        if ((st = capture_iteration(b))) return st;
+    for (int it = 0; it < n_iters; ++it) {
+        const hipError_t e = hipGraphLaunch(b->exec, s);
+        if (e != hipSuccess) return hip_fail(e, "graph launch");
+    }
+    return ok();
+}
+
+int osem_batch_autotune(spect_batch *b, float *const *f, const float *const *mu, const float *const *g,
+                        const float *const *s_add, void *ws, size_t ws_bytes, void *stream)
+{
+    int st;
+    const Ptrs P0{f, mu, g, s_add, static_cast<char *>(ws)};
+    bool vec = true;
+    if ((st = check_batch_args(b, P0, ws_bytes, &vec))) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // work on copies of the images, kept after the member regions
+    std::vector<float *> fc(b->R);
+    size_t off = b->regions;
+    for (int r = 0; r < b->R; ++r) {
+        fc[r] = reinterpret_cast<float *>(static_cast<char *>(ws) + off);
+        const size_t n = sizeof(float) * (size_t)b->plans[r]->N * b->plans[r]->N * b->plans[r]->Nz;
+        const hipError_t e = hipMemcpyAsync(fc[r], f[r], n, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "image copy for tuning");
+        off += vol_bytes(b->plans[r]);
+    }
+    const Ptrs P{fc.data(), mu, g, s_add, static_cast<char *>(ws)};
+    bool vec_c = vec;
+    for (int r = 0; r < b->R; ++r)
+        if (!aligned16(fc[r])) vec_c = false;
+    if ((st = batch_sensitivities(b, P, vec_c, s))) return st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(SPECT_EHIP, "event creation failed");
+    int best = 0;
+    double best_ms = 1e300;
+    for (int c = 0; c < 4 && st == SPECT_OK; ++c) {
+        b->sched = c;
+        if ((st = prepare(b, P, vec_c)) || (st = capture_iteration(b))) break;
+        hipError_t e = hipGraphLaunch(b->exec, s);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipGraphLaunch(b->exec, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "autotune timing");
+            break;
+        }
+        b->cand_ms[c] = ms / 2.0;
+        if (ms / 2.0 < best_ms) {
+            best_ms = ms / 2.0;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->sched = best;
+    b->key.clear();  // the next reconstruction rebuilds for its own arrays
+    drop_graph(b);
+    return st ? st : ok();
 }
 
 }  // extern "C"

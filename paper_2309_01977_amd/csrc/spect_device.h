@@ -48,6 +48,35 @@ constexpr int MAXL = 128;  // angles per launch
 
 enum AttMode { ATT_NONE = 0, ATT_SAMPLE = 1, ATT_WRITE = 2, ATT_READ = 3 };
 
+// Work-list of a batched launch: task = (reconstruction r, x, y, z), where
+// (x, y, z) are the block coordinates the single-reconstruction launch would
+// use; args[r] are reconstruction r's launch arguments.  A persistent batched
+// kernel (PERSIST) has workgroup b take tasks b, b + gridDim.x, ...; the
+// other form runs one task per workgroup (grid = task count), which keeps
+// the register count of the single-reconstruction kernel.
+struct Task {
+    int r, x, y, z;
+};
+
+template <class Args>
+struct BatchList {
+    const Args *args;
+    const Task *tasks;
+    int ntasks;
+};
+
+// The argument and task arrays of a batched launch are written by the host
+// before the launch and only read by it, so the kernels read them through
+// the constant address space: uniform fields then come in with scalar loads.
+template <class T>
+using ConstMem = const __attribute__((address_space(4))) T;
+
+template <class T>
+__device__ __forceinline__ ConstMem<T> *as_const(const T *p)
+{
+    return (ConstMem<T> *)p;
+}
+
 // Element offset of the 16 axial rows of (angle al, slab, depth i', bin j')
 // in a rotated-frame brick volume [L][nslab][N][N][16] (the back-projection
 // workspace and the attenuation table share this layout).
@@ -422,14 +451,13 @@ struct FwdArgs {
     int vec;
 };
 
-template <int ATT, int KMC, bool VEC>
-__global__ __launch_bounds__(512) void fwd_main(FwdArgs a)
+template <int ATT, int KMC, bool VEC, class Args>
+__device__ __forceinline__ void fwd_body(const Args &a, int slab, int chunk, int al)
 {
     static_assert(ATT != ATT_WRITE, "the forward kernel does not write the table");
     constexpr bool MU = ATT == ATT_SAMPLE;
     extern __shared__ float4 smem[];
     const int N = a.g.N, Nz = a.g.Nz;
-    const int slab = blockIdx.x, chunk = blockIdx.y, al = blockIdx.z;
     const int ang = a.L.idx[al];
     const int jp = threadIdx.x >> 1, h = threadIdx.x & 1;
     const bool active = jp < N;
@@ -530,6 +558,29 @@ __global__ __launch_bounds__(512) void fwd_main(FwdArgs a)
     }
 }
 
+template <int ATT, int KMC, bool VEC>
+__global__ __launch_bounds__(512) void fwd_main(FwdArgs a)
+{
+    fwd_body<ATT, KMC, VEC>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <int ATT, int KMC, bool VEC, bool PERSIST>
+__global__ __launch_bounds__(512) void fwd_batch(BatchList<FwdArgs> b)
+{
+    ConstMem<FwdArgs> *args = as_const(b.args);
+    ConstMem<Task> *tasks = as_const(b.tasks);
+    if (!PERSIST) {
+        const int t = blockIdx.x;
+        if (t < b.ntasks) fwd_body<ATT, KMC, VEC>(args[tasks[t].r], tasks[t].x, tasks[t].y, tasks[t].z);
+        return;
+    }
+    for (int t = blockIdx.x; t < b.ntasks; t += gridDim.x) {
+        const int r = tasks[t].r, x = tasks[t].x, y = tasks[t].y, z = tasks[t].z;
+        fwd_body<ATT, KMC, VEC>(args[r], x, y, z);
+        __syncthreads();  // the next task rewrites the row buffers
+    }
+}
+
 struct ReduceArgs {
     AngleList L;
     const float *part;
@@ -544,12 +595,12 @@ struct ReduceArgs {
 #ifdef SPECT_HOST_TU
 // Sum the partial rows of all chunks and overlapping slabs for one output
 // element (angle, bin, row).
-__global__ __launch_bounds__(256) void fwd_reduce(ReduceArgs a)
+template <class Args>
+__device__ __forceinline__ void reduce_body(const Args &a, int blk, int al)
 {
     const int N = a.N, Nz = a.Nz;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blk * blockDim.x + threadIdx.x;
     if (t >= N * Nz) return;
-    const int al = blockIdx.y;
     const int ang = a.L.idx[al];
     const int r = t / Nz, k = t % Nz;
     const int R = SLAB + 2 * a.kmc;
@@ -571,6 +622,18 @@ __global__ __launch_bounds__(256) void fwd_reduce(ReduceArgs a)
     }
 }
 
+__global__ __launch_bounds__(256) void fwd_reduce(ReduceArgs a) { reduce_body(a, blockIdx.x, blockIdx.y); }
+
+__global__ __launch_bounds__(256) void reduce_batch(BatchList<ReduceArgs> b)
+{
+    ConstMem<ReduceArgs> *args = as_const(b.args);
+    ConstMem<Task> *tasks = as_const(b.tasks);
+    for (int t = blockIdx.x; t < b.ntasks; t += gridDim.x) {
+        const int r = tasks[t].r, x = tasks[t].x, z = tasks[t].z;
+        reduce_body(args[r], x, z);
+    }
+}
+
 #endif  // SPECT_HOST_TU
 
 // ---------------------------------------------------------- back project --
@@ -589,13 +652,12 @@ struct BackRotArgs {
     int vec;
 };
 
-template <int ATT, int KMC, bool VEC>
-__global__ __launch_bounds__(512) void back_rot(BackRotArgs a)
+template <int ATT, int KMC, bool VEC, class Args>
+__device__ __forceinline__ void back_body(const Args &a, int slab, int chunk, int al)
 {
     constexpr bool MU = ATT == ATT_SAMPLE || ATT == ATT_WRITE;
     extern __shared__ float4 smem[];
     const int N = a.g.N, Nz = a.g.Nz;
-    const int slab = blockIdx.x, chunk = blockIdx.y, al = blockIdx.z;
     const int ang = a.L.idx[al];
     const int jp = threadIdx.x >> 1, h = threadIdx.x & 1;
     const bool active = jp < N;
@@ -692,6 +754,29 @@ __global__ __launch_bounds__(512) void back_rot(BackRotArgs a)
     }
 }
 
+template <int ATT, int KMC, bool VEC>
+__global__ __launch_bounds__(512) void back_rot(BackRotArgs a)
+{
+    back_body<ATT, KMC, VEC>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <int ATT, int KMC, bool VEC, bool PERSIST>
+__global__ __launch_bounds__(512) void back_batch(BatchList<BackRotArgs> b)
+{
+    ConstMem<BackRotArgs> *args = as_const(b.args);
+    ConstMem<Task> *tasks = as_const(b.tasks);
+    if (!PERSIST) {
+        const int t = blockIdx.x;
+        if (t < b.ntasks) back_body<ATT, KMC, VEC>(args[tasks[t].r], tasks[t].x, tasks[t].y, tasks[t].z);
+        return;
+    }
+    for (int t = blockIdx.x; t < b.ntasks; t += gridDim.x) {
+        const int r = tasks[t].r, x = tasks[t].x, y = tasks[t].y, z = tasks[t].z;
+        back_body<ATT, KMC, VEC>(args[r], x, y, z);
+        __syncthreads();  // the next task rewrites the row and projection buffers
+    }
+}
+
 // Terms of the BSREM update (gather mode 3): where sens_all > 0,
 // out <- max(0, out + out * a_over_c / sens_all * (sum - sens - c_beta * prior)).
 struct BsremTerms {
@@ -723,15 +808,15 @@ struct GatherArgs {
 constexpr int GT = 8;  // gather tile edge
 
 #ifdef SPECT_HOST_TU
-__global__ __launch_bounds__(256) void back_gather(GatherArgs a)
+template <class Args>
+__device__ __forceinline__ void gather_body(const Args &a, int tile, int slab)
 {
     const int N = a.g.N, Nz = a.g.Nz;
     const int tiles = (N + GT - 1) / GT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane >> 2, q = lane & 3;
-    const int x = (blockIdx.x / tiles) * GT + wave * 2 + (col >> 3);
-    const int y = (blockIdx.x % tiles) * GT + (col & 7);
-    const int slab = blockIdx.y;
+    const int x = (tile / tiles) * GT + wave * 2 + (col >> 3);
+    const int y = (tile % tiles) * GT + (col & 7);
     if (x >= N || y >= N) return;
     const float c = 0.5f * (float)(N - 1);
     const float xx = (float)x - c, yy = (float)y - c;
@@ -797,6 +882,18 @@ __global__ __launch_bounds__(256) void back_gather(GatherArgs a)
 #endif  // SPECT_HOST_TU
 
 #ifdef SPECT_HOST_TU
+__global__ __launch_bounds__(256) void back_gather(GatherArgs a) { gather_body(a, blockIdx.x, blockIdx.y); }
+
+__global__ __launch_bounds__(256) void gather_batch(BatchList<GatherArgs> b)
+{
+    ConstMem<GatherArgs> *args = as_const(b.args);
+    ConstMem<Task> *tasks = as_const(b.tasks);
+    for (int t = blockIdx.x; t < b.ntasks; t += gridDim.x) {
+        const int r = tasks[t].r, x = tasks[t].x, y = tasks[t].y;
+        gather_body(args[r], x, y);
+    }
+}
+
 __global__ __launch_bounds__(256) void fill_zero(float *p, size_t n)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -875,10 +972,15 @@ __global__ __launch_bounds__(256) void rdp_grad(RdpArgs a)
 // own translation unit (spect_kmc.hip compiled with -DSPECT_KMC=<class>).
 typedef void (*KernelFn)(FwdArgs);
 typedef void (*BackFn)(BackRotArgs);
-// att is an AttMode (the forward kernel has no ATT_WRITE variant).
-#define SPECT_DECLARE_CLASS(K)                       \
-    KernelFn fwd_kernel_kmc##K(int att, bool vec); \
-    BackFn back_kernel_kmc##K(int att, bool vec);
+typedef void (*FwdBatchFn)(BatchList<FwdArgs>);
+typedef void (*BackBatchFn)(BatchList<BackRotArgs>);
+// att is an AttMode (the forward kernel has no ATT_WRITE variant; the batched
+// kernels exist for ATT_NONE and ATT_READ).
+#define SPECT_DECLARE_CLASS(K)                                 \
+    KernelFn fwd_kernel_kmc##K(int att, bool vec);           \
+    BackFn back_kernel_kmc##K(int att, bool vec);            \
+    FwdBatchFn fwd_batch_kmc##K(int att, bool vec, bool persist); \
+    BackBatchFn back_batch_kmc##K(int att, bool vec, bool persist);
 SPECT_DECLARE_CLASS(0)
 SPECT_DECLARE_CLASS(4)
 SPECT_DECLARE_CLASS(8)

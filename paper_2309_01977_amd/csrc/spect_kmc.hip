@@ -33,4 +33,32 @@ BackFn SPECT_PASTE(back_kernel_kmc, SPECT_KMC)(int att, bool vec)
     }
 }
 
+template <int ATT>
+FwdBatchFn fwd_batch_of(bool vec, bool persist)
+{
+    if (persist) return vec ? fwd_batch<ATT, SPECT_KMC, true, true> : fwd_batch<ATT, SPECT_KMC, false, true>;
+    return vec ? fwd_batch<ATT, SPECT_KMC, true, false> : fwd_batch<ATT, SPECT_KMC, false, false>;
+}
+
+template <int ATT>
+BackBatchFn back_batch_of(bool vec, bool persist)
+{
+    if (persist) return vec ? back_batch<ATT, SPECT_KMC, true, true> : back_batch<ATT, SPECT_KMC, false, true>;
+    return vec ? back_batch<ATT, SPECT_KMC, true, false> : back_batch<ATT, SPECT_KMC, false, false>;
+}
+
+FwdBatchFn SPECT_PASTE(fwd_batch_kmc, SPECT_KMC)(int att, bool vec, bool persist)
+{
+    if (att == ATT_NONE) return fwd_batch_of<ATT_NONE>(vec, persist);
+    if (att == ATT_READ) return fwd_batch_of<ATT_READ>(vec, persist);
+    return nullptr;
+}
+
+BackBatchFn SPECT_PASTE(back_batch_kmc, SPECT_KMC)(int att, bool vec, bool persist)
+{
+    if (att == ATT_NONE) return back_batch_of<ATT_NONE>(vec, persist);
+    if (att == ATT_READ) return back_batch_of<ATT_READ>(vec, persist);
+    return nullptr;
+}
+
 }  // namespace spectk

@@ -81,6 +81,42 @@ C4_BATCH = 8
 C4_STEPS = 10
 
 
+# The batched workload: 32 reconstructions of uneven sizes (transverse 64 to
+# 192 voxels, 64 to 160 axial slices, 60 to 128 angles), each a torso phantom
+# with its attenuation map, 4 iterations x 8 subsets.
+C3_COUNT = 32
+
+
+def c3_workloads(count: int = C3_COUNT) -> List[Workload]:
+    """Seeded geometries of the batched workload (member i uses phantom and
+    noise streams of its own, see member_rngs)."""
+    rng, _ = rngs(2)
+    out = []
+    for i in range(count):
+        n = int(rng.choice([64, 96, 128, 160, 192]))
+        nz = 160 if n == 192 else int(rng.choice(np.arange(64, min(n, 160) + 1, 16)))
+        a = int(rng.choice(np.arange(60, 129, 4)))
+        out.append(Workload(f"batch_member_{i}_{n}x{n}x{nz}x{a}", n=n, nz=nz, n_angles=a, with_mu=True,
+                            n_iters=4, n_subsets=8, total_counts=float(rng.uniform(1e6, 5e6)), seed_index=2))
+    return out
+
+
+def member_rngs(i: int) -> Tuple[np.random.Generator, np.random.Generator]:
+    """(phantom rng, noise rng) of batched member i."""
+    child = np.random.SeedSequence(MASTER_SEED).spawn(5)[2].spawn(C3_COUNT + 1)[i + 1]
+    a, b = child.spawn(2)
+    return np.random.default_rng(a), np.random.default_rng(b)
+
+
+def make_member_phantom(w: Workload, i: int, ss: int = 2):
+    """(f_true, mu) float32 torso phantom of batched member i, scaled to its grid."""
+    rng, _ = member_rngs(i)
+    act, mu_shapes = _torso(rng, (w.n * w.voxel_cm) / 61.44, n_spheres=10)
+    f = voxelise(act, w.n, w.nz, w.voxel_cm, ss).astype(np.float32)
+    mu = voxelise(mu_shapes, w.n, w.nz, w.voxel_cm, ss).astype(np.float32)
+    return f, mu
+
+
 def rngs(seed_index: int) -> Tuple[np.random.Generator, np.random.Generator]:
     """(phantom rng, noise rng) for workload ``seed_index``."""
     child = np.random.SeedSequence(MASTER_SEED).spawn(5)[seed_index]

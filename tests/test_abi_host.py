@@ -122,3 +122,18 @@ def test_bsrem_calls_reject_null_plan():
                                  None, 0, None) == B.SPECT_EINVAL
     assert lib.bsrem_reconstruct(None, None, None, None, None, 1, 1, 0.3, 2.0, None, None, 0,
                                  None) == B.SPECT_EINVAL
+
+
+def test_batch_calls_reject_bad_arguments_before_any_device_call():
+    lib = S.load_library()
+    h = ctypes.c_void_p(5)
+    assert lib.spect_batch_create(None, 1, 1, 0, ctypes.byref(h)) == B.SPECT_EINVAL
+    assert h.value is None
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.spect_batch_create(arr, 0, 1, 0, ctypes.byref(h)) == B.SPECT_EINVAL
+    nbytes = ctypes.c_size_t()
+    assert lib.spect_batch_workspace_size(None, ctypes.byref(nbytes)) == B.SPECT_EINVAL
+    assert lib.osem_batch_reconstruct(None, None, None, None, None, 1, 0, None, 0, None) == B.SPECT_EINVAL
+    assert lib.osem_batch_autotune(None, None, None, None, None, None, 0, None) == B.SPECT_EINVAL
+    assert lib.spect_batch_set_schedule(None, 0) == B.SPECT_EINVAL
+    assert lib.spect_batch_destroy(None) == B.SPECT_OK
