@@ -160,17 +160,22 @@ int spect_sensitivity(const spect_plan *plan, const float *mu, float *sens,
  * work-list of (member, angle, axial slab, depth chunk) tasks.  Each member's
  * state lives in its own region of one workspace (spect_batch_workspace_size
  * bytes, 256-byte aligned, caller-owned; it also holds copies of the images
- * for osem_batch_autotune).  Results equal osem_reconstruct per member.
+ * for osem_batch_autotune).  Results equal osem_reconstruct per member up to
+ * FP32 rounding: the batch's sensitivity pass sums each ray's attenuation
+ * over all depths at once, and schedules 4-7 do the same for the forward
+ * depth sums (without attenuation, schedules 0-3 are bitwise equal).
  *
  * Arrays f, mu, g, s_add are host arrays of R device pointers, laid out as in
  * osem_reconstruct; mu must be given for every member if the batch was created
  * with_mu != 0 (attenuation-factor tables are then kept per member and
  * subset) and must be NULL (or hold NULLs) otherwise; s_add may be NULL.
  *
- * Schedules (spect_batch_set_schedule, osem_batch_autotune): bit 0 set = one
- * launch per stage for each group of members with equal block size and blur
- * class, clear = one launch for all members; bit 1 set = persistent grids
- * (workgroups loop over tasks), clear = one task per workgroup.
+ * Schedules 0..7 (spect_batch_set_schedule, osem_batch_autotune): bit 0 set =
+ * one launch per stage for each group of members with equal block size and
+ * blur class, clear = one launch for all members; bit 1 set = persistent
+ * grids (workgroups loop over tasks), clear = one task per workgroup; bit 2
+ * set = every task walks all depths of its rays, clear = depths split into
+ * the chunks a single reconstruction would use.
  *
  * By default one iteration (the M subiterations) is captured once as a HIP
  * graph on an internal stream and replayed on `stream` n_iters times;
@@ -194,7 +199,7 @@ int osem_batch_autotune(spect_batch *batch, float *const *f, const float *const 
                         const float *const *g, const float *const *s_add, void *ws,
                         size_t ws_bytes, void *stream);
 
-/* The current schedule and, in candidate_ms[0..3] (may be NULL), the
+/* The current schedule and, in candidate_ms[0..7] (may be NULL), the
  * autotuner's per-iteration times (-1 where not measured). */
 int spect_batch_schedule(const spect_batch *batch, int32_t *schedule, double *candidate_ms);
 int spect_batch_set_schedule(spect_batch *batch, int32_t schedule);

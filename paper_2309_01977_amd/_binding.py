@@ -474,7 +474,7 @@ class Batch:
     def schedule(self):
         """(schedule, [ms per iteration of each candidate, -1 if not timed])."""
         s = ctypes.c_int32()
-        ms = (ctypes.c_double * 4)()
+        ms = (ctypes.c_double * 8)()
         _check(load_library().spect_batch_schedule(self._h, ctypes.byref(s), ms))
         return s.value, list(ms)
 

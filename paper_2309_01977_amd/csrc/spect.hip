@@ -1227,6 +1227,11 @@ struct BatchLaunch {
     BatchList<BackRotArgs> back{};
     BatchList<GatherArgs> gat{};
     int gf = 0, gr = 0, gb = 0, gg = 0;  // grid sizes
+    // sensitivity pass (ones back-projected, attenuation tables written), single depth chunk
+    BackBatchFn sk = nullptr;
+    BatchList<BackRotArgs> sback{};
+    BatchList<GatherArgs> sgat{};
+    int gsb = 0, gsg = 0;
 };
 
 struct spect_batch {
@@ -1234,13 +1239,14 @@ struct spect_batch {
     bool mu = false;
     std::vector<const spect_plan *> plans;
     std::vector<std::vector<AngleList>> lists;  // [r][m]
-    std::vector<std::vector<Tuning>> tun;       // [r][m], passes of the iterations
+    std::vector<std::vector<Tuning>> tun;       // [r][m], passes of the iterations (depth-chunked)
+    std::vector<std::vector<Tuning>> tun1;      // [r][m], the same without depth chunks
     int kmc_max = 0;
     std::vector<size_t> base, q_off, scr_off, scr_bytes;
     std::vector<std::vector<size_t>> tab_off;   // [r][m], relative to base[r]
     size_t regions = 0, ws_total = 0;
-    int sched = 0;                              // bit 0: one launch per size class; bit 1: persistent
-    double cand_ms[4] = {-1.0, -1.0, -1.0, -1.0};
+    int sched = 0;  // bit 0: one launch per size class; bit 1: persistent; bit 2: no depth chunks
+    double cand_ms[8] = {-1.0, -1.0, -1.0, -1.0, -1.0, -1.0, -1.0, -1.0};
     std::vector<std::vector<BatchLaunch>> steps;  // [m][group]
     void *dmem = nullptr;
     size_t dmem_bytes = 0;
@@ -1294,6 +1300,7 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
 {
     const int att = batch_att(b);
     const bool grouped = sched & 1, persist = sched & 2;
+    const std::vector<std::vector<Tuning>> &tuning = (sched & 4) ? b->tun1 : b->tun;
     // groups: members sharing block size and blur class, or all members
     std::vector<std::vector<int>> groups;
     std::vector<int> gkmc, gthreads;
@@ -1321,8 +1328,8 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
         gkmc.push_back(b->kmc_max);
     }
     struct Offs {
-        size_t fa, ft, ra, rt, ba, bt, ga, gt;
-        int nf, nr, nb, ng;
+        size_t fa, ft, ra, rt, ba, bt, ga, gt, sa, st, sg;
+        int nf, nr, nb, ng, ns;
     };
     std::vector<char> blob;
     std::vector<std::vector<Offs>> offs(b->M);
@@ -1333,13 +1340,15 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
             std::vector<ReduceArgs> ra;
             std::vector<BackRotArgs> ba;
             std::vector<GatherArgs> ga;
-            std::vector<std::pair<long, Task>> ft, bt;
+            std::vector<std::pair<long, Task>> ft, bt, stk;
             std::vector<Task> rt, gt;
+            std::vector<BackRotArgs> sa;
+            std::vector<GatherArgs> sg;
             for (size_t li = 0; li < groups[gi].size(); ++li) {
                 const int r = groups[gi][li];
                 const spect_plan *p = b->plans[r];
                 const AngleList &L = b->lists[r][m];
-                const Tuning &t = b->tun[r][m];
+                const Tuning &t = tuning[r][m];
                 char *base = P.ws + b->base[r];
                 float *tab = b->mu ? reinterpret_cast<float *>(base + b->tab_off[r][m]) : nullptr;
                 float *q = reinterpret_cast<float *>(base + b->q_off[r]);
@@ -1390,6 +1399,22 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
                 gg.out = P.f[r];
                 gg.sens = sens;
                 ga.push_back(gg);
+                BackRotArgs sb = bb;  // sensitivity: ones, mu sampled, table written, one depth chunk
+                sb.y = nullptr;
+                sb.y_compact = 0;
+                sb.ones = 1;
+                sb.mu = b->mu ? P.mu[r] : nullptr;
+                sb.nchunk = 1;
+                sb.dchunk = p->N;
+                sa.push_back(sb);
+                GatherArgs sgg = gg;
+                sgg.mode = 0;
+                sgg.out = sens;
+                sgg.sens = nullptr;
+                sg.push_back(sgg);
+                for (int al = 0; al < L.n; ++al)
+                    for (int sl = 0; sl < t.nslab; ++sl)
+                        stk.push_back({(long)p->N * p->N, Task{(int)li, sl, 0, al}});
                 const int li_ = (int)li;
                 const long cost = (long)t.dchunk * p->N;  // depths x bins of one task
                 for (int al = 0; al < L.n; ++al)
@@ -1413,9 +1438,11 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
             };
             std::stable_sort(ft.begin(), ft.end(), by_cost);
             std::stable_sort(bt.begin(), bt.end(), by_cost);
-            std::vector<Task> ftv, btv;
+            std::stable_sort(stk.begin(), stk.end(), by_cost);
+            std::vector<Task> ftv, btv, stv;
             for (auto &x : ft) ftv.push_back(x.second);
             for (auto &x : bt) btv.push_back(x.second);
+            for (auto &x : stk) stv.push_back(x.second);
             Offs o;
             o.fa = put(blob, fa);
             o.ft = put(blob, ftv);
@@ -1425,6 +1452,10 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
             o.bt = put(blob, btv);
             o.ga = put(blob, ga);
             o.gt = put(blob, gt);
+            o.sa = put(blob, sa);
+            o.st = put(blob, stv);
+            o.sg = put(blob, sg);
+            o.ns = (int)stv.size();
             o.nf = (int)ftv.size();
             o.nr = (int)rt.size();
             o.nb = (int)btv.size();
@@ -1465,6 +1496,11 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
             l.back = {reinterpret_cast<const BackRotArgs *>(d + o.ba), reinterpret_cast<const Task *>(d + o.bt),
                       o.nb};
             l.gat = {reinterpret_cast<const GatherArgs *>(d + o.ga), reinterpret_cast<const Task *>(d + o.gt), o.ng};
+            l.sk = back_batch_kernel(b->mu ? ATT_WRITE : ATT_NONE, gkmc[gi], vec, persist);
+            allow_smem(reinterpret_cast<const void *>(l.sk), l.bsmem);
+            l.sback = {reinterpret_cast<const BackRotArgs *>(d + o.sa), reinterpret_cast<const Task *>(d + o.st),
+                       o.ns};
+            l.sgat = {reinterpret_cast<const GatherArgs *>(d + o.sg), reinterpret_cast<const Task *>(d + o.gt), o.ng};
             if (persist) {
                 int nb = 0;
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(l.fk),
@@ -1477,12 +1513,18 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
                 l.gb = std::max(1, std::min(o.nb, nb * b->cus));
                 l.gr = std::max(1, std::min(o.nr, 8 * b->cus));
                 l.gg = std::max(1, std::min(o.ng, 8 * b->cus));
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(l.sk),
+                                                                  l.threads, l.bsmem) != hipSuccess || nb < 1)
+                    nb = 1;
+                l.gsb = std::max(1, std::min(o.ns, nb * b->cus));
             } else {
                 l.gf = std::max(1, o.nf);
                 l.gb = std::max(1, o.nb);
                 l.gr = std::max(1, o.nr);
                 l.gg = std::max(1, o.ng);
+                l.gsb = std::max(1, o.ns);
             }
+            l.gsg = l.gg;
             b->steps[m].push_back(l);
         }
     (void)hipGetLastError();
@@ -1540,23 +1582,24 @@ int capture_iteration(spect_batch *b)
     return SPECT_OK;
 }
 
-// Sensitivities (and attenuation tables) of every member and subset, with
-// the single-reconstruction kernels.
-int batch_sensitivities(const spect_batch *b, const Ptrs &P, bool vec, hipStream_t st)
+// Sensitivities (and attenuation tables) of every member and subset: per
+// subset one batched adjoint launch per group (ones back-projected, mu
+// sampled along whole rays, factors stored) and one gather.
+int batch_sensitivities(const spect_batch *b, hipStream_t st)
 {
-    for (int r = 0; r < b->R; ++r) {
-        const spect_plan *p = b->plans[r];
-        char *base = P.ws + b->base[r];
-        for (int m = 0; m < b->M; ++m) {
-            float *tab = b->mu ? reinterpret_cast<float *>(base + b->tab_off[r][m]) : nullptr;
-            float *sens = reinterpret_cast<float *>(base + (size_t)m * vol_bytes(p));
-            const int st_ = run_back(p, nullptr, 0, 1, b->mu ? P.mu[r] : nullptr, b->mu ? ATT_WRITE : ATT_NONE, tab,
-                                     b->lists[r][m], base + b->scr_off[r], b->scr_bytes[r], nullptr, 0, sens, nullptr,
-                                     vec, T_BACK, st);
-            if (st_) return st_;
+    for (int m = 0; m < b->M; ++m)
+        for (const BatchLaunch &l : b->steps[m]) {
+            {
+                ProfScope ps(K_BACK_B, st);
+                hipLaunchKernelGGL(l.sk, dim3(l.gsb), dim3(l.threads), l.bsmem, st, l.sback);
+            }
+            {
+                ProfScope ps(K_GATHER_B, st);
+                hipLaunchKernelGGL(gather_batch, dim3(l.gsg), dim3(256), 0, st, l.sgat);
+            }
         }
-    }
-    return SPECT_OK;
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SPECT_OK : hip_fail(e, "batched sensitivity launch");
 }
 
 int check_batch_args(const spect_batch *b, const Ptrs &P, size_t ws_bytes, bool *vec)
@@ -1638,7 +1681,7 @@ int spect_batch_create(const spect_plan *const *plans, int32_t n_members, int32_
     for (int r = 0; r < n_members; ++r) {
         const spect_plan *p = b->plans[r];
         std::vector<AngleList> ls;
-        std::vector<Tuning> ts;
+        std::vector<Tuning> ts, t1;
         std::vector<size_t> tabs;
         size_t rel = (size_t)n_subsets * vol_bytes(p), scr = 0;
         for (int m = 0; m < n_subsets; ++m) {
@@ -1648,6 +1691,7 @@ int spect_batch_create(const spect_plan *const *plans, int32_t n_members, int32_
             const int nl = (int)list.size();
             const Tuning t = tune(p, nl, att, T_BOTH);
             ts.push_back(t);
+            t1.push_back(Tuning{t.nslab, 1, p->N});
             tabs.push_back(rel);
             if (b->mu) rel += table_bytes(p, nl);
             scr = std::max(scr, batch_part_bytes(p, t, nl, b->kmc_max));
@@ -1656,6 +1700,7 @@ int spect_batch_create(const spect_plan *const *plans, int32_t n_members, int32_
         }
         b->lists.push_back(ls);
         b->tun.push_back(ts);
+        b->tun1.push_back(t1);
         b->tab_off.push_back(tabs);
         b->q_off.push_back(rel);
         rel += osem_q_bytes(p, n_subsets);
@@ -1700,14 +1745,14 @@ int spect_batch_schedule(const spect_batch *b, int32_t *schedule, double *candid
     if (!b) return fail(SPECT_EINVAL, "batch is NULL");
     if (schedule) *schedule = b->sched;
     if (candidate_ms)
-        for (int c = 0; c < 4; ++c) candidate_ms[c] = b->cand_ms[c];
+        for (int c = 0; c < 8; ++c) candidate_ms[c] = b->cand_ms[c];
     return ok();
 }
 
 int spect_batch_set_schedule(spect_batch *b, int32_t schedule)
 {
     if (!b) return fail(SPECT_EINVAL, "batch is NULL");
-    if (schedule < 0 || schedule > 3) return fail(SPECT_EINVAL, "schedule = %d outside [0, 3]", schedule);
+    if (schedule < 0 || schedule > 7) return fail(SPECT_EINVAL, "schedule = %d outside [0, 7]", schedule);
     b->sched = schedule;
     return ok();
 }
@@ -1723,9 +1768,9 @@ int osem_batch_reconstruct(spect_batch *b, float *const *f, const float *const *
     if (n_iters < 0) return fail(SPECT_EINVAL, "n_iters = %d is negative", n_iters);
     if (flags & ~SPECT_BATCH_EAGER) return fail(SPECT_EINVAL, "unknown flags 0x%x", (unsigned)flags);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((st = batch_sensitivities(b, P, vec, s))) return st;
-    if (n_iters == 0) return ok();
     if ((st = prepare(b, P, vec))) return st;
+    if ((st = batch_sensitivities(b, s))) return st;
+    if (n_iters == 0) return ok();
     if (flags & SPECT_BATCH_EAGER) {
         for (int it = 0; it < n_iters; ++it)
             for (int m = 0; m < b->M; ++m)
@@ -1763,15 +1808,16 @@ int osem_batch_autotune(spect_batch *b, float *const *f, const float *const *mu,
     bool vec_c = vec;
     for (int r = 0; r < b->R; ++r)
         if (!aligned16(fc[r])) vec_c = false;
-    if ((st = batch_sensitivities(b, P, vec_c, s))) return st;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(SPECT_EHIP, "event creation failed");
     int best = 0;
     double best_ms = 1e300;
-    for (int c = 0; c < 4 && st == SPECT_OK; ++c) {
+    for (int c = 0; c < 8 && st == SPECT_OK; ++c) {
         b->sched = c;
-        if ((st = prepare(b, P, vec_c)) || (st = capture_iteration(b))) break;
+        if ((st = prepare(b, P, vec_c))) break;
+        if (c == 0 && (st = batch_sensitivities(b, s))) break;
+        if ((st = capture_iteration(b))) break;
         hipError_t e = hipGraphLaunch(b->exec, s);  // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, s);
         for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipGraphLaunch(b->exec, s);

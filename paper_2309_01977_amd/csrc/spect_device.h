@@ -975,7 +975,8 @@ typedef void (*BackFn)(BackRotArgs);
 typedef void (*FwdBatchFn)(BatchList<FwdArgs>);
 typedef void (*BackBatchFn)(BatchList<BackRotArgs>);
 // att is an AttMode (the forward kernel has no ATT_WRITE variant; the batched
-// kernels exist for ATT_NONE and ATT_READ).
+// kernels exist for ATT_NONE and ATT_READ, the batched adjoint also for
+// ATT_WRITE, the sensitivity pass of a batch).
 #define SPECT_DECLARE_CLASS(K)                                 \
     KernelFn fwd_kernel_kmc##K(int att, bool vec);           \
     BackFn back_kernel_kmc##K(int att, bool vec);            \

@@ -1,10 +1,13 @@
 """Batched OSEM (spect_batch_*, osem_batch_reconstruct) on the GPU.
 
 Every member of a batch must come out as its own osem_reconstruct does (the
-same kernels on the same tasks: bitwise, checked to 1e-6), and within the
-OSEM bar (1e-4 relative L2) of the FP64 oracle.  All schedules, the eager
-path and repeated graph replays (with other device work and synchronisation
-in between, and with new arrays) give the same images.
+same kernels on the same tasks; only the attenuation sums of the batch's
+sensitivity pass run over whole rays: checked to 1e-6), and within the OSEM
+bar (1e-4 relative L2) of the FP64 oracle.  Schedules 0-3, the eager path
+and repeated graph replays (with other device work and synchronisation in
+between, and with new arrays) give the same images bitwise; schedules 4-7
+sum each ray over all depths at once instead of per depth chunk, which
+changes only the FP32 rounding (checked to 1e-5, and against the oracle).
 """
 import sys
 
@@ -95,12 +98,21 @@ def test_every_schedule_and_the_eager_path_give_the_same_images():
     M, I = 4, 2
     mem = members(SHAPES, True, 71)
     ref, batch = run_batch(mem, M, I, True, eager=True)
-    for sched in range(4):
+    for sched in range(8):
+        runs = []
         for eager in (False, True):
             got, _ = run_batch(mem, M, I, True, schedule=sched, eager=eager, batch=batch)
-            for a, b in zip(got, ref):
-                np.testing.assert_array_equal(a, b)
-        say(f"  schedule {sched}: graph and eager equal the reference")
+            runs.append(got)
+            for a, b, (og, _, mu, g) in zip(got, ref, mem):
+                if sched & 4:
+                    # one running depth sum instead of per-chunk partials: FP32 rounding only
+                    assert rel_l2(a, b) <= 1e-5
+                    assert rel_l2(a, O.osem(og, g.astype(np.float64), mu.astype(np.float64), I, M)) <= OSEM_TOL
+                else:
+                    np.testing.assert_array_equal(a, b)
+        for a, b in zip(*runs):
+            np.testing.assert_array_equal(a, b)   # graph = eager within a schedule
+        say(f"  schedule {sched}: graph and eager agree with the reference")
 
 
 def test_graph_replays_between_other_work_and_with_new_arrays():
@@ -141,7 +153,7 @@ def test_autotune_picks_a_timed_schedule_and_keeps_the_images():
     gs = [dev(m[3]) for m in mem]
     sched, ms = batch.autotune(fs, mus, gs)
     say(f"  autotune: schedule {sched}, ms per iteration {['%.3f' % x for x in ms]}")
-    assert 0 <= sched <= 3 and all(x > 0 for x in ms)
+    assert 0 <= sched <= 7 and all(x > 0 for x in ms)
     assert ms[sched] == min(ms)
     for f in fs:
         assert torch.all(f == 1.0)
