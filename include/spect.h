@@ -204,6 +204,48 @@ int osem_batch_autotune(spect_batch *batch, float *const *f, const float *const 
 int spect_batch_schedule(const spect_batch *batch, int32_t *schedule, double *candidate_ms);
 int spect_batch_set_schedule(spect_batch *batch, int32_t schedule);
 
+/* Reconstruction server: continuous admission of whole OSEM reconstructions
+ * (osem_reconstruct) as they arrive, for serving many studies (Section 4).
+ *
+ * The server owns pool_bytes of device memory and n_slots HIP streams
+ * (default priority).  spect_server_submit queues a request in arrival order;
+ * the head of the queue is admitted as soon as a slot is idle and the pool
+ * holds a free block of the request's workspace (spect_workspace_size with
+ * SPECT_OP_RECON), so requests arriving while others run start at once and
+ * their kernels overlap on the device; a request that does not fit waits (and
+ * so do the ones behind it) until running requests free their memory.
+ * Finished requests are retired by spect_server_progress (non-blocking: it
+ * polls completion events, then admits) or spect_server_wait (blocks).  The
+ * caller owns f (the initial image on submission, the reconstruction once the
+ * request is SPECT_REQ_DONE), mu, g, s_add, and keeps them alive and
+ * untouched until then.  Results equal osem_reconstruct alone.  Not
+ * thread-safe: one host thread drives a server.
+ *
+ * spect_server_submit fails with SPECT_EINVAL if the request's workspace can
+ * never fit in the pool.  spect_server_status: *state = SPECT_REQ_*; a failed
+ * request returns its error code and message.  spect_server_forget drops the
+ * record of a finished request.  spect_server_destroy waits for all running
+ * requests; queued ones are dropped. */
+#define SPECT_REQ_QUEUED 0
+#define SPECT_REQ_RUNNING 1
+#define SPECT_REQ_DONE 2
+#define SPECT_REQ_FAILED 3
+
+typedef struct spect_server spect_server;
+int spect_server_create(int32_t n_slots, size_t pool_bytes, spect_server **out);
+int spect_server_destroy(spect_server *server);
+int spect_server_submit(spect_server *server, const spect_plan *plan, float *f, const float *mu,
+                        const float *g, const float *s_add, int32_t n_iters, int32_t n_subsets,
+                        int64_t *request_id);
+int spect_server_progress(spect_server *server, int32_t *n_running, int32_t *n_queued);
+int spect_server_status(spect_server *server, int64_t request_id, int32_t *state);
+int spect_server_wait(spect_server *server, int64_t request_id);
+int spect_server_forget(spect_server *server, int64_t request_id);
+/* Running and queued counts, the largest number of requests ever running at
+ * once, and the pool bytes in use. */
+int spect_server_stats(const spect_server *server, int32_t *n_running, int32_t *n_queued,
+                       int32_t *peak_running, size_t *pool_in_use);
+
 /* Attenuation-factor tables (T_att of Eq. 1 evaluated once).  For a fixed
  * attenuation map and angle list the factors exp(-tau) do not change between
  * projections, so repeated projections of the same list (OSEM iterations,

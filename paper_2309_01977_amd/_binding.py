@@ -29,7 +29,9 @@ EXPORTS = ("spect_plan_create", "spect_plan_destroy", "spect_workspace_size", "s
            "spect_fwd_table", "spect_back_table", "osem_subset_step", "osem_reconstruct",
            "spect_rdp_gradient", "bsrem_subset_step", "bsrem_reconstruct", "spect_batch_create",
            "spect_batch_destroy", "spect_batch_workspace_size", "osem_batch_reconstruct", "osem_batch_autotune",
-           "spect_batch_schedule", "spect_batch_set_schedule", "spect_profile_enable",
+           "spect_batch_schedule", "spect_batch_set_schedule", "spect_server_create", "spect_server_destroy",
+           "spect_server_submit", "spect_server_progress", "spect_server_status", "spect_server_wait",
+           "spect_server_forget", "spect_server_stats", "spect_profile_enable",
            "spect_profile_reset", "spect_profile_query", "spect_last_error")
 KERNELS = ("tau_prepass", "fwd_main", "fwd_reduce", "back_rot", "back_gather", "fill_zero", "rdp_grad",
            "vol_sum", "fwd_batch", "reduce_batch", "back_batch", "gather_batch")
@@ -88,6 +90,15 @@ def load_library(path: Optional[str] = None):
     lib.osem_batch_autotune.argtypes = [vp, vpp, vpp, vpp, vpp, vp, sz, vp]
     lib.spect_batch_schedule.argtypes = [vp, i32p, ctypes.POINTER(ctypes.c_double)]
     lib.spect_batch_set_schedule.argtypes = [vp, i32]
+    i64 = ctypes.c_int64
+    lib.spect_server_create.argtypes = [i32, sz, vpp]
+    lib.spect_server_destroy.argtypes = [vp]
+    lib.spect_server_submit.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, ctypes.POINTER(i64)]
+    lib.spect_server_progress.argtypes = [vp, i32p, i32p]
+    lib.spect_server_status.argtypes = [vp, i64, i32p]
+    lib.spect_server_wait.argtypes = [vp, i64]
+    lib.spect_server_forget.argtypes = [vp, i64]
+    lib.spect_server_stats.argtypes = [vp, i32p, i32p, i32p, ctypes.POINTER(sz)]
     lib.spect_profile_enable.argtypes = [ctypes.c_int]
     lib.spect_profile_reset.argtypes = []
     lib.spect_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
@@ -480,3 +491,67 @@ class Batch:
 
     def set_schedule(self, schedule: int):
         _check(load_library().spect_batch_set_schedule(self._h, int(schedule)))
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+
+
+class Server:
+    """Reconstruction server (spect_server_*): whole OSEM reconstructions
+    admitted as slots and pool memory free up, overlapping on the device."""
+
+    def __init__(self, n_slots: int, pool_bytes: int):
+        h = ctypes.c_void_p()
+        _check(load_library().spect_server_create(int(n_slots), int(pool_bytes), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}   # request id -> tensors that must stay alive until it finishes
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().spect_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, plan: Plan, f: torch.Tensor, g: torch.Tensor, n_iters: int, n_subsets: int,
+               mu: Optional[torch.Tensor] = None, s_add: Optional[torch.Tensor] = None) -> int:
+        rid = ctypes.c_int64()
+        _check(load_library().spect_server_submit(
+            self._h, plan._h, _ptr(f, plan.object_shape, "f"), _ptr(mu, plan.object_shape, "mu"),
+            _ptr(g, plan.proj_shape, "g"), _ptr(s_add, plan.proj_shape, "s_add"), int(n_iters), int(n_subsets),
+            ctypes.byref(rid)))
+        self._keep[rid.value] = (plan, f, g, mu, s_add)
+        return rid.value
+
+    def progress(self):
+        """(running, queued) after retiring finished requests and admitting."""
+        nr, nq = ctypes.c_int32(), ctypes.c_int32()
+        _check(load_library().spect_server_progress(self._h, ctypes.byref(nr), ctypes.byref(nq)))
+        return nr.value, nq.value
+
+    def status(self, rid: int) -> int:
+        st = ctypes.c_int32()
+        _check(load_library().spect_server_status(self._h, int(rid), ctypes.byref(st)))
+        if st.value == REQ_DONE:
+            self._keep.pop(rid, None)
+        return st.value
+
+    def wait(self, rid: int):
+        _check(load_library().spect_server_wait(self._h, int(rid)))
+        self._keep.pop(rid, None)
+
+    def forget(self, rid: int):
+        _check(load_library().spect_server_forget(self._h, int(rid)))
+
+    def stats(self):
+        """(running, queued, peak running, pool bytes in use)."""
+        nr, nq, pk = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        used = ctypes.c_size_t()
+        _check(load_library().spect_server_stats(self._h, ctypes.byref(nr), ctypes.byref(nq), ctypes.byref(pk),
+                                                  ctypes.byref(used)))
+        return nr.value, nq.value, pk.value, used.value

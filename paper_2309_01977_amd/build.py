@@ -2,8 +2,8 @@
 
     python -m paper_2309_01977_amd.build [-v]
 
-Compiles the host/C-ABI translation unit and one translation unit per
-blur-radius class (spect_kmc.hip with -DSPECT_KMC=0,4,...,32) in parallel,
+Compiles the host/C-ABI translation units (projector library, server) and
+one translation unit per blur-radius class (spect_kmc.hip with -DSPECT_KMC=0,4,...,32) in parallel,
 then links paper_2309_01977_amd/_lib/libspect_hip.so.
 """
 from __future__ import annotations
@@ -53,7 +53,8 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     os.makedirs(OBJ_DIR, exist_ok=True)
     cc, fl = hipcc(), common_flags()
-    units = [(os.path.join(CSRC, "spect.hip"), os.path.join(OBJ_DIR, "spect.o"), [])]
+    units = [(os.path.join(CSRC, "spect.hip"), os.path.join(OBJ_DIR, "spect.o"), []),
+             (os.path.join(CSRC, "spect_server.hip"), os.path.join(OBJ_DIR, "spect_server.o"), [])]
     for k in KMC_CLASSES:
         units.append((os.path.join(CSRC, "spect_kmc.hip"), os.path.join(OBJ_DIR, f"spect_kmc{k}.o"),
                       [f"-DSPECT_KMC={k}"]))

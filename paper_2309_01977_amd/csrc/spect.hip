@@ -644,6 +644,12 @@ bool want_vec(const spect_plan *p, std::initializer_list<const void *> ptrs)
 
 }  // namespace
 
+// Error reporting for the other host translation units (spect_internal.h).
+namespace spect_internal {
+int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+int clear_error() { return ok(); }
+}  // namespace spect_internal
+
 // ============================================================== C ABI ====
 
 extern "C" {

@@ -137,3 +137,18 @@ def test_batch_calls_reject_bad_arguments_before_any_device_call():
     assert lib.osem_batch_autotune(None, None, None, None, None, None, 0, None) == B.SPECT_EINVAL
     assert lib.spect_batch_set_schedule(None, 0) == B.SPECT_EINVAL
     assert lib.spect_batch_destroy(None) == B.SPECT_OK
+
+
+def test_server_calls_reject_bad_arguments_before_any_device_call():
+    lib = S.load_library()
+    h = ctypes.c_void_p(5)
+    assert lib.spect_server_create(0, 1 << 20, ctypes.byref(h)) == B.SPECT_EINVAL
+    assert h.value is None
+    assert lib.spect_server_create(2, 16, ctypes.byref(h)) == B.SPECT_EINVAL
+    rid = ctypes.c_int64()
+    assert lib.spect_server_submit(None, None, None, None, None, None, 1, 1, ctypes.byref(rid)) == B.SPECT_EINVAL
+    assert lib.spect_server_progress(None, None, None) == B.SPECT_EINVAL
+    st = ctypes.c_int32()
+    assert lib.spect_server_status(None, 1, ctypes.byref(st)) == B.SPECT_EINVAL
+    assert lib.spect_server_wait(None, 1) == B.SPECT_EINVAL
+    assert lib.spect_server_destroy(None) == B.SPECT_OK
