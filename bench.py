@@ -1,13 +1,14 @@
 """Benchmark of the SPECT OSEM hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--recon-only]
-                    [--workload osem|unrolled|bsrem|batched]
+                    [--workload osem|unrolled|bsrem|batched|serving] [--serve-seconds S]
 
 The default workload (osem) is the headline measurement below;
 --workload unrolled measures the differentiable projector pair instead
 (bench_unrolled), --workload bsrem BSREM with the relative difference prior
 (bench_bsrem), --workload batched 32 uneven reconstructions at once against
-the same reconstructions one at a time (bench_batched).  --recon-only runs the data generation and the timed reconstructions only
+the same reconstructions one at a time (bench_batched), --workload serving a
+Poisson stream of reconstruction requests through the server (bench_serving).  --recon-only runs the data generation and the timed reconstructions only
 (no per-kernel timing, context passes or CPU baseline); hardware-counter
 runs use it so that every kernel they see after the data generation belongs
 to a reconstruction.
@@ -163,7 +164,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--recon-only", action="store_true")
-    ap.add_argument("--workload", choices=("osem", "unrolled", "bsrem", "batched"), default="osem")
+    ap.add_argument("--workload", choices=("osem", "unrolled", "bsrem", "batched", "serving"), default="osem")
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -186,6 +188,8 @@ def main():
         bench_bsrem(args)
     elif args.workload == "batched":
         bench_batched(args)
+    elif args.workload == "serving":
+        bench_serving(args)
     else:
         bench_osem(args)
 
@@ -554,6 +558,74 @@ def bench_batched(args):
         "autotune_ms_per_iteration": cand,
         "batched_sensitivity_pass_ms": float(per_sens.mean()),
         "max_member_rel_l2_vs_one_at_a_time": worst,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args):
+    """A Poisson stream of 20 reconstruction requests per second for
+    --serve-seconds seconds, each drawn from the 64^3 x 60 (no attenuation,
+    2 x 6), 128^3 x 120 and 192 x 192 x 160 x 128 (attenuation, 4 x 8)
+    classes with Poisson data (three noise draws per class), served by the
+    reconstruction server with 8 slots and a 64 GiB pool; the same trace
+    served one request at a time (1 slot); and a burst of 60 requests at once
+    (throughput) with 8 slots and with 1."""
+    from paper_2309_01977_amd import serving
+    works = [P.C1, P.C2, P.C5_LARGE]
+    classes = []
+    for w in works:
+        plan = S.Plan.for_workload(w)
+        f_true, mu_np = P.make_phantom(w, ss=2)
+        mu = None if mu_np is None else torch.from_numpy(mu_np).cuda()
+        gbar = plan.forward(torch.from_numpy(f_true).cuda(), mu).cpu().numpy()
+        _, noise = P.rngs(w.seed_index)
+        data = [torch.from_numpy(P.poisson_counts(gbar, w.total_counts, noise)).cuda() for _ in range(3)]
+        classes.append(serving.RequestClass(w.name, plan, data, None if mu is None else [mu] * 3,
+                                            w.n_iters, w.n_subsets))
+    log("serving: request classes ready")
+    rng = np.random.default_rng(np.random.SeedSequence(P.MASTER_SEED).spawn(5)[4].spawn(2)[1])
+    trace = serving.poisson_trace(P.C5_RATE, args.serve_seconds, len(classes), rng)
+    # warm-up: one request of each class
+    warm = S.Server(len(classes), 64 << 30)
+    serving.replay(warm, classes, [(0.0, c) for c in range(len(classes))])
+    warm.close()
+    results = {}
+    for name, slots in (("server_8_slots", 8), ("one_at_a_time", 1)):
+        server = S.Server(slots, 64 << 30)
+        t0 = time.perf_counter()
+        served = serving.replay(server, classes, trace)
+        wall = time.perf_counter() - t0
+        st = serving.summary(served, wall)
+        st["peak_running"] = server.stats()[2]
+        st["per_class_p99_ms"] = {classes[c].name: float(np.percentile(
+            [s.latency * 1e3 for s in served if s.cls == c], 99)) for c in range(len(classes))
+            if any(s.cls == c for s in served)}
+        results[name] = st
+        server.close()
+        log(f"{name}: {st}")
+    burst = [(0.0, int(c)) for c in rng.choice(len(classes), 60)]
+    for name, slots in (("burst_8_slots", 8), ("burst_one_at_a_time", 1)):
+        server = S.Server(slots, 64 << 30)
+        t0 = time.perf_counter()
+        served = serving.replay(server, classes, burst)
+        wall = time.perf_counter() - t0
+        results[name] = serving.summary(served, wall)
+        results[name]["peak_running"] = server.stats()[2]
+        server.close()
+        log(f"{name}: {results[name]}")
+    s8 = results["server_8_slots"]
+    out = {
+        "metric": "served OSEM reconstructions/s and p50/p99 latency (Poisson 20 req/s, 3 acquisition classes)",
+        "value": s8["recon_per_s"],
+        "unit": "reconstructions/s",
+        "n_gpus": 1, "steps": len(trace), "warmup": len(classes), "ms_per_step": s8["latency_ms_mean"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serving_poisson20", "classes": [c.name for c in classes],
+                   "rate_per_s": P.C5_RATE, "seconds": args.serve_seconds, "slots": 8, "pool_gib": 64},
+        "latency_ms_p50": s8["latency_ms_p50"], "latency_ms_p99": s8["latency_ms_p99"],
+        "runs": results,
+        "burst_speedup": results["burst_one_at_a_time"]["latency_ms_max"] / results["burst_8_slots"]["latency_ms_max"],
     }
     print(json.dumps(out), flush=True)
 

@@ -81,6 +81,14 @@ C4_BATCH = 8
 C4_STEPS = 10
 
 
+# The serving workload: requests drawn from three acquisition classes (the
+# 64^3 and 128^3 workloads above and a 192 x 192 x 160 volume with 128
+# angles), arriving as a Poisson stream of 20 requests per second.
+C5_LARGE = Workload("osem_192x160_128ang_att", n=192, nz=160, n_angles=128, with_mu=True, n_iters=4,
+                    n_subsets=8, total_counts=8e6, seed_index=4)
+C5_RATE = 20.0
+
+
 # The batched workload: 32 reconstructions of uneven sizes (transverse 64 to
 # 192 voxels, 64 to 160 axial slices, 60 to 128 angles), each a torso phantom
 # with its attenuation map, 4 iterations x 8 subsets.
