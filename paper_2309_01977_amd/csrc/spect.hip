@@ -40,11 +40,12 @@ namespace {
 
 enum KernelId {
     K_TAU = 0, K_FWD, K_REDUCE, K_BACK_ROT, K_GATHER, K_FILL, K_RDP, K_SUM,
-    K_FWD_B, K_REDUCE_B, K_BACK_B, K_GATHER_B, K_COUNT
+    K_FWD_B, K_REDUCE_B, K_BACK_B, K_GATHER_B, K_SENS, K_COUNT
 };
 const char *const kKernelNames[K_COUNT] = {"tau_prepass", "fwd_main", "fwd_reduce", "back_rot",
                                            "back_gather", "fill_zero", "rdp_grad", "vol_sum",
-                                           "fwd_batch", "reduce_batch", "back_batch", "gather_batch"};
+                                           "fwd_batch", "reduce_batch", "back_batch", "gather_batch",
+                                           "sens_rot"};
 
 struct ProfRec {
     int kernel;
@@ -575,9 +576,18 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
     b.nchunk = t.nchunk;
     b.dchunk = t.dchunk;
     b.vec = vec;
-    BackFn bk = back_kernel(att, p->kmc, vec);
-    allow_smem(reinterpret_cast<const void *>(bk), back_smem(p));
-    {
+    if (ones) {
+        // constant projection: the blur reduces to in-range tap sums (sens_rot)
+        BackFn sk = nullptr;
+        if (att == ATT_WRITE) sk = vec ? sens_rot<ATT_WRITE, true> : sens_rot<ATT_WRITE, false>;
+        else if (att == ATT_SAMPLE) sk = vec ? sens_rot<ATT_SAMPLE, true> : sens_rot<ATT_SAMPLE, false>;
+        else if (att == ATT_NONE) sk = sens_rot<ATT_NONE, true>;
+        if (!sk) return fail(SPECT_EINVAL, "no sensitivity pass for attenuation mode %d", att);
+        ProfScope ps(K_SENS, st);
+        hipLaunchKernelGGL(sk, dim3(t.nslab, t.nchunk, L.n), dim3(block_threads(p->N)), 0, st, b);
+    } else {
+        BackFn bk = back_kernel(att, p->kmc, vec);
+        allow_smem(reinterpret_cast<const void *>(bk), back_smem(p));
         ProfScope ps(K_BACK_ROT, st);
         hipLaunchKernelGGL(bk, dim3(t.nslab, t.nchunk, L.n), dim3(block_threads(p->N)), back_smem(p), st, b);
     }
@@ -745,7 +755,7 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
     const int N = g.n, A = g.n_angles;
     std::vector<float2> cs(A), xy0((size_t)A * N);
     std::vector<int> kd((size_t)A * N);
-    std::vector<float> taps((size_t)A * N * p->TS, 0.f);
+    std::vector<float> taps((size_t)A * N * p->TS, 0.f), ctaps((size_t)A * N * p->TS, 0.f);
     const double c = 0.5 * (N - 1);
     std::vector<double> t;
     for (int i = 0; i < A; ++i) {
@@ -758,12 +768,19 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
         for (int ip = 0; ip < N; ++ip) {
             const int K = depth_kernel(g, rad[i], ip, &t);
             kd[(size_t)i * N + ip] = K;
-            for (int m = 0; m <= K; ++m) taps[((size_t)i * N + ip) * p->TS + m] = (float)t[m];
+            double run = 0.0;
+            for (int m = 0; m < p->TS; ++m) {
+                if (m <= K) {
+                    taps[((size_t)i * N + ip) * p->TS + m] = (float)t[m];
+                    run += t[m];
+                }
+                ctaps[((size_t)i * N + ip) * p->TS + m] = (float)run;
+            }
         }
     }
     const size_t b_cs = align256(sizeof(float2) * A), b_xy = align256(sizeof(float2) * (size_t)A * N);
     const size_t b_kd = align256(sizeof(int) * (size_t)A * N), b_tp = align256(sizeof(float) * taps.size());
-    hipError_t e = hipMalloc(&p->dmem, b_cs + b_xy + b_kd + b_tp);
+    hipError_t e = hipMalloc(&p->dmem, b_cs + b_xy + b_kd + 2 * b_tp);
     if (e != hipSuccess) {
         delete p;
         return fail(SPECT_ENOMEM, "hipMalloc of plan tables failed: %s", hipGetErrorString(e));
@@ -774,6 +791,9 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
     if (e == hipSuccess) e = hipMemcpy(base + b_cs + b_xy, kd.data(), sizeof(int) * kd.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(base + b_cs + b_xy + b_kd, taps.data(), sizeof(float) * taps.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(base + b_cs + b_xy + b_kd + b_tp, ctaps.data(), sizeof(float) * ctaps.size(),
+                      hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(p->dmem);
         delete p;
@@ -783,6 +803,7 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
     p->g.xy0 = reinterpret_cast<const float2 *>(base + b_cs);
     p->g.kdep = reinterpret_cast<const int *>(base + b_cs + b_xy);
     p->g.taps = reinterpret_cast<const float *>(base + b_cs + b_xy + b_kd);
+    p->g.ctaps = reinterpret_cast<const float *>(base + b_cs + b_xy + b_kd + b_tp);
     p->g.N = N;
     p->g.Nz = g.nz;
     p->g.A = A;
@@ -1502,8 +1523,10 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
             l.back = {reinterpret_cast<const BackRotArgs *>(d + o.ba), reinterpret_cast<const Task *>(d + o.bt),
                       o.nb};
             l.gat = {reinterpret_cast<const GatherArgs *>(d + o.ga), reinterpret_cast<const Task *>(d + o.gt), o.ng};
-            l.sk = back_batch_kernel(b->mu ? ATT_WRITE : ATT_NONE, gkmc[gi], vec, persist);
-            allow_smem(reinterpret_cast<const void *>(l.sk), l.bsmem);
+            if (b->mu)
+                l.sk = vec ? sens_batch<ATT_WRITE, true> : sens_batch<ATT_WRITE, false>;
+            else
+                l.sk = sens_batch<ATT_NONE, true>;
             l.sback = {reinterpret_cast<const BackRotArgs *>(d + o.sa), reinterpret_cast<const Task *>(d + o.st),
                        o.ns};
             l.sgat = {reinterpret_cast<const GatherArgs *>(d + o.sg), reinterpret_cast<const Task *>(d + o.gt), o.ng};
@@ -1520,7 +1543,7 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
                 l.gr = std::max(1, std::min(o.nr, 8 * b->cus));
                 l.gg = std::max(1, std::min(o.ng, 8 * b->cus));
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(l.sk),
-                                                                  l.threads, l.bsmem) != hipSuccess || nb < 1)
+                                                                  l.threads, 0) != hipSuccess || nb < 1)
                     nb = 1;
                 l.gsb = std::max(1, std::min(o.ns, nb * b->cus));
             } else {
@@ -1589,15 +1612,15 @@ int capture_iteration(spect_batch *b)
 }
 
 // Sensitivities (and attenuation tables) of every member and subset: per
-// subset one batched adjoint launch per group (ones back-projected, mu
-// sampled along whole rays, factors stored) and one gather.
+// subset one batched sensitivity launch per group (constant projection: tap
+// sums, mu sampled along whole rays, factors stored) and one gather.
 int batch_sensitivities(const spect_batch *b, hipStream_t st)
 {
     for (int m = 0; m < b->M; ++m)
         for (const BatchLaunch &l : b->steps[m]) {
             {
-                ProfScope ps(K_BACK_B, st);
-                hipLaunchKernelGGL(l.sk, dim3(l.gsb), dim3(l.threads), l.bsmem, st, l.sback);
+                ProfScope ps(K_SENS, st);
+                hipLaunchKernelGGL(l.sk, dim3(l.gsb), dim3(l.threads), 0, st, l.sback);
             }
             {
                 ProfScope ps(K_GATHER_B, st);

@@ -96,6 +96,7 @@ struct DevGeom {
     const float2 *xy0;  // [A][N] rotated-frame origin of ray j': X = X0 + i' cos, Y = Y0 + i' sin
     const int *kdep;    // [A][N] blur radius per depth
     const float *taps;  // [A][N][TS] one-sided taps g[0..K]
+    const float *ctaps; // [A][N][TS] their running sums C[m] = g[0] + ... + g[m]
     int N, Nz, A, TS;
     float tau_scale;    // dx * log2(e): exp(-tau) = exp2(-tau_scale * (sum mu))
 };
@@ -777,6 +778,96 @@ __global__ __launch_bounds__(512) void back_batch(BatchList<BackRotArgs> b)
     }
 }
 
+#ifdef SPECT_HOST_TU
+// Rotated-frame pass of the sensitivity H^T 1.  The projection is all ones,
+// so the separable blur of depth i' reduces to the product of the in-range
+// tap sums along the bin axis and the axial axis:
+//     (G_r G_z 1)(j', k) = e_r(j') e_z(k),  e_r(j') = sum_{|m|<=K, 0<=j'+m<N} g_|m|
+//                                                  = C[min(K, j')] + C[min(K, N-1-j')] - g_0
+// with the running tap sums C (e_z likewise over 0 <= k+l < Nz); the value is that product times the
+// attenuation factor, written to the rotated-frame bricks like back_rot
+// (ATT_WRITE also stores the factors).  Same grid and thread mapping as
+// back_rot; no LDS.
+template <int ATT, bool VEC, class Args>
+__device__ __forceinline__ void sens_body(const Args &a, int slab, int chunk, int al)
+{
+    constexpr bool MU = ATT == ATT_SAMPLE || ATT == ATT_WRITE;
+    const int N = a.g.N, Nz = a.g.Nz;
+    const int ang = a.L.idx[al];
+    const int jp = threadIdx.x >> 1, h = threadIdx.x & 1;
+    if (jp >= N) return;
+    const int k0 = slab * SLAB;
+    const int kb = k0 + h * ROWS;
+    const bool full = k0 + SLAB <= Nz;
+    const float2 cs = a.g.cs[ang];
+    const float2 o = a.g.xy0[(size_t)ang * N + jp];
+    float S[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) S[r] = 0.f;
+    if (MU && chunk > 0) chunk_start(a.tau, al, a.nchunk, chunk, N, Nz, jp, kb, S);
+    const int ihi = N - chunk * a.dchunk - 1;
+    const int ilo = max(0, N - (chunk + 1) * a.dchunk);
+    const int *kd = a.g.kdep + (size_t)ang * N;
+    const RowGeom rg = row_geom(kb, Nz);
+    const size_t wg0 = brick_offset(al, a.nslab, slab, N, 0, 0);
+    const uint32_t toff = 4u * (uint32_t)(jp * SLAB + h * ROWS);
+    for (int ip = ihi; ip >= ilo; --ip) {
+        const int K = kd[ip];
+        const float *ct = a.g.ctaps + ((size_t)ang * N + ip) * a.g.TS;
+        const float g0 = ct[0];
+        const float er = ct[min(K, jp)] + ct[min(K, N - 1 - jp)] - g0;
+        float u[ROWS];
+        if (k0 - K >= 0 && k0 + SLAB - 1 + K < Nz) {
+            const float ez = 2.f * ct[K] - g0;
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) u[r] = er * ez;
+        } else {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const int k = kb + r;  // rows past Nz get a value the gather never reads
+                const float ez = ct[min(K, max(k, 0))] + ct[max(0, min(K, Nz - 1 - k))] - g0;
+                u[r] = er * ez;
+            }
+        }
+        const size_t row0 = wg0 + (size_t)ip * N * SLAB;
+        if (MU) {
+            const Corners cn = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, rg.rowb);
+            Raw rm;
+            load_raw<VEC>(a.mu, cn, rg, kb, Nz, rm);
+            float m[ROWS], att[ROWS];
+            combine(rm, cn, kb, Nz, m, full);
+            attenuate(m, S, a.g.tau_scale, att);
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) u[r] *= att[r];
+            if (ATT == ATT_WRITE) {
+                float4 *tb = reinterpret_cast<float4 *>(reinterpret_cast<char *>(a.att + row0) + toff);
+                tb[0] = make_float4(att[0], att[1], att[2], att[3]);
+                tb[1] = make_float4(att[4], att[5], att[6], att[7]);
+            }
+        }
+        float4 *dst = reinterpret_cast<float4 *>(reinterpret_cast<char *>(a.z + row0) + toff);
+        dst[0] = make_float4(u[0], u[1], u[2], u[3]);
+        dst[1] = make_float4(u[4], u[5], u[6], u[7]);
+    }
+}
+
+template <int ATT, bool VEC>
+__global__ __launch_bounds__(512) void sens_rot(BackRotArgs a)
+{
+    sens_body<ATT, VEC>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// The same over a batch work-list, one task per workgroup.
+template <int ATT, bool VEC>
+__global__ __launch_bounds__(512) void sens_batch(BatchList<BackRotArgs> b)
+{
+    ConstMem<BackRotArgs> *args = as_const(b.args);
+    ConstMem<Task> *tasks = as_const(b.tasks);
+    for (int t = blockIdx.x; t < b.ntasks; t += gridDim.x)
+        sens_body<ATT, VEC>(args[tasks[t].r], tasks[t].x, tasks[t].y, tasks[t].z);
+}
+#endif  // SPECT_HOST_TU
+
 // Terms of the BSREM update (gather mode 3): where sens_all > 0,
 // out <- max(0, out + out * a_over_c / sens_all * (sum - sens - c_beta * prior)).
 struct BsremTerms {
@@ -824,35 +915,58 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int slab)
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
     const size_t zstride = (size_t)a.nslab * N * N * SLAB;
     const float *zq = a.z + (size_t)slab * N * N * SLAB + 4 * q;
-    for (int al = 0; al < a.L.n; ++al) {
+    // Candidate window and ray origins of angle al; fetched one angle ahead so
+    // that the weights are known before the brick loads are issued.
+    struct Win {
+        float2 cs, o[3];
+        int ilo, jlo;
+    };
+    auto window = [&](int al) {
+        Win w;
         const int ang = a.L.idx[al];
-        const float2 cs = a.g.cs[ang];
+        w.cs = a.g.cs[ang];
+        const float wdw = fabsf(w.cs.x) + fabsf(w.cs.y) + 1e-3f;
+        const float ic = c + w.cs.x * xx + w.cs.y * yy;
+        const float jc = c - w.cs.y * xx + w.cs.x * yy;
+        w.ilo = (int)ceilf(ic - wdw);
+        w.jlo = (int)ceilf(jc - wdw);
         const float2 *xy0 = a.g.xy0 + (size_t)ang * N;
-        const float wdw = fabsf(cs.x) + fabsf(cs.y) + 1e-3f;
-        const float ic = c + cs.x * xx + cs.y * yy;
-        const float jc = c - cs.y * xx + cs.x * yy;
-        const int ilo = (int)ceilf(ic - wdw), jlo = (int)ceilf(jc - wdw);
-        const float *zb = zq + (size_t)al * zstride;
-        float2 o[3];
-        float4 v[9];
 #pragma unroll
-        for (int dj = 0; dj < 3; ++dj) o[dj] = xy0[min(max(jlo + dj, 0), N - 1)];
+        for (int dj = 0; dj < 3; ++dj) w.o[dj] = xy0[min(max(w.jlo + dj, 0), N - 1)];
+        return w;
+    };
+    Win nxt;
+    if (a.L.n > 0) nxt = window(0);
+    for (int al = 0; al < a.L.n; ++al) {
+        const Win cur = nxt;
+        if (al + 1 < a.L.n) nxt = window(al + 1);
+        const float *zb = zq + (size_t)al * zstride;
+        float wt[9];
 #pragma unroll
         for (int d = 0; d < 9; ++d) {
-            const int ipc = min(max(ilo + d / 3, 0), N - 1), jpc = min(max(jlo + d % 3, 0), N - 1);
-            v[d] = *reinterpret_cast<const float4 *>(zb + ((size_t)ipc * N + jpc) * SLAB);
+            const int ip = cur.ilo + d / 3, jp = cur.jlo + d % 3;
+            const bool inr = (unsigned)ip < (unsigned)N && (unsigned)jp < (unsigned)N;
+            const float X = fmaf((float)ip, cur.cs.x, cur.o[d % 3].x), Y = fmaf((float)ip, cur.cs.y, cur.o[d % 3].y);
+            const float wx = fmaxf(0.f, 1.f - fabsf(X - fxv)), wy = fmaxf(0.f, 1.f - fabsf(Y - fyv));
+            wt[d] = inr ? wx * wy : 0.f;
+        }
+        // only candidates with a non-zero weight are read: the four lanes of a
+        // column share the weight, so whole quads drop out of the loads
+        float4 v[9];
+#pragma unroll
+        for (int d = 0; d < 9; ++d) {
+            v[d] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (wt[d] > 0.f) {
+                const int ipc = min(max(cur.ilo + d / 3, 0), N - 1), jpc = min(max(cur.jlo + d % 3, 0), N - 1);
+                v[d] = *reinterpret_cast<const float4 *>(zb + ((size_t)ipc * N + jpc) * SLAB);
+            }
         }
 #pragma unroll
         for (int d = 0; d < 9; ++d) {
-            const int ip = ilo + d / 3, jp = jlo + d % 3;
-            const bool inr = (unsigned)ip < (unsigned)N && (unsigned)jp < (unsigned)N;
-            const float X = fmaf((float)ip, cs.x, o[d % 3].x), Y = fmaf((float)ip, cs.y, o[d % 3].y);
-            const float wx = fmaxf(0.f, 1.f - fabsf(X - fxv)), wy = fmaxf(0.f, 1.f - fabsf(Y - fyv));
-            const float w = inr ? wx * wy : 0.f;
-            acc[0] = fmaf(w, v[d].x, acc[0]);
-            acc[1] = fmaf(w, v[d].y, acc[1]);
-            acc[2] = fmaf(w, v[d].z, acc[2]);
-            acc[3] = fmaf(w, v[d].w, acc[3]);
+            acc[0] = fmaf(wt[d], v[d].x, acc[0]);
+            acc[1] = fmaf(wt[d], v[d].y, acc[1]);
+            acc[2] = fmaf(wt[d], v[d].z, acc[2]);
+            acc[3] = fmaf(wt[d], v[d].w, acc[3]);
         }
     }
     const size_t base = ((size_t)x * N + y) * Nz;
@@ -975,8 +1089,7 @@ typedef void (*BackFn)(BackRotArgs);
 typedef void (*FwdBatchFn)(BatchList<FwdArgs>);
 typedef void (*BackBatchFn)(BatchList<BackRotArgs>);
 // att is an AttMode (the forward kernel has no ATT_WRITE variant; the batched
-// kernels exist for ATT_NONE and ATT_READ, the batched adjoint also for
-// ATT_WRITE, the sensitivity pass of a batch).
+// kernels exist for ATT_NONE and ATT_READ).
 #define SPECT_DECLARE_CLASS(K)                                 \
     KernelFn fwd_kernel_kmc##K(int att, bool vec);           \
     BackFn back_kernel_kmc##K(int att, bool vec);            \

@@ -57,7 +57,6 @@ FwdBatchFn SPECT_PASTE(fwd_batch_kmc, SPECT_KMC)(int att, bool vec, bool persist
 BackBatchFn SPECT_PASTE(back_batch_kmc, SPECT_KMC)(int att, bool vec, bool persist)
 {
     if (att == ATT_NONE) return back_batch_of<ATT_NONE>(vec, persist);
-    if (att == ATT_WRITE) return back_batch_of<ATT_WRITE>(vec, persist);
     if (att == ATT_READ) return back_batch_of<ATT_READ>(vec, persist);
     return nullptr;
 }
