@@ -66,10 +66,15 @@ struct ProfScope {
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
         on = g_prof_on && allowed;
-        if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
-            (void)hipEventRecord(a, st);
-        else
+        if (!on) return;
+        if (hipEventCreate(&a) != hipSuccess) {
             on = false;
+        } else if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            on = false;
+        } else {
+            (void)hipEventRecord(a, st);
+        }
     }
     ~ProfScope()
     {
