@@ -895,10 +895,31 @@ struct GatherArgs {
 // the <= 3 x 3 rotated samples around its rotated position; the weight of
 // sample P is the bilinear hat max(0, 1 - |X_P - x|) max(0, 1 - |Y_P - y|),
 // with X_P, Y_P computed by the forward's own FP32 expression, so the weights
-// equal the forward's to within one rounding.
+// equal the forward's to within one rounding.  Lane q of a column evaluates
+// the three candidates of window column q (lane 3 none) and the quad shares
+// weights and brick offsets through DPP quad permutes.
 constexpr int GT = 8;  // gather tile edge
 
 #ifdef SPECT_HOST_TU
+// Value of lane `src` of this lane's quad (all four lanes active).
+// Third descriptor word of a raw (unswizzled, unformatted) buffer resource on
+// gfx9-family GPUs; a byte offset of kPastEnd lies beyond every buffer built
+// here, so a load there returns zeros.
+constexpr int kBufferDword3 = 0x00020000;
+constexpr int kPastEnd = 0x40000000;
+
+template <int SRC>
+__device__ __forceinline__ int quad_bcast(int v)
+{
+    return __builtin_amdgcn_mov_dpp(v, SRC * 0x55, 0xF, 0xF, false);
+}
+
+template <int SRC>
+__device__ __forceinline__ float quad_bcast(float v)
+{
+    return __int_as_float(quad_bcast<SRC>(__float_as_int(v)));
+}
+
 template <class Args>
 __device__ __forceinline__ void gather_body(const Args &a, int tile, int slab)
 {
@@ -908,17 +929,20 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int slab)
     const int col = lane >> 2, q = lane & 3;
     const int x = (tile / tiles) * GT + wave * 2 + (col >> 3);
     const int y = (tile % tiles) * GT + (col & 7);
-    if (x >= N || y >= N) return;
+    if (x >= N || y >= N) return;  // whole quads leave together
     const float c = 0.5f * (float)(N - 1);
     const float xx = (float)x - c, yy = (float)y - c;
     const float fxv = (float)x, fyv = (float)y;
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
     const size_t zstride = (size_t)a.nslab * N * N * SLAB;
-    const float *zq = a.z + (size_t)slab * N * N * SLAB + 4 * q;
-    // Candidate window and ray origins of angle al; fetched one angle ahead so
-    // that the weights are known before the brick loads are issued.
+    const float *zs = a.z + (size_t)slab * N * N * SLAB;
+    const uint32_t qoff = 16u * (uint32_t)q;
+    const uint32_t rowb = (uint32_t)N * SLAB * 4;  // bytes per rotated row i' (N <= 256: < 2^22)
+    // Candidate window of angle al and the ray origin of this lane's window
+    // column; fetched one angle ahead so that the weights are known before
+    // the brick loads are issued.
     struct Win {
-        float2 cs, o[3];
+        float2 cs, o;
         int ilo, jlo;
     };
     auto window = [&](int al) {
@@ -930,9 +954,7 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int slab)
         const float jc = c - w.cs.y * xx + w.cs.x * yy;
         w.ilo = (int)ceilf(ic - wdw);
         w.jlo = (int)ceilf(jc - wdw);
-        const float2 *xy0 = a.g.xy0 + (size_t)ang * N;
-#pragma unroll
-        for (int dj = 0; dj < 3; ++dj) w.o[dj] = xy0[min(max(w.jlo + dj, 0), N - 1)];
+        w.o = a.g.xy0[(size_t)ang * N + min(max(w.jlo + q, 0), N - 1)];
         return w;
     };
     Win nxt;
@@ -940,34 +962,41 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int slab)
     for (int al = 0; al < a.L.n; ++al) {
         const Win cur = nxt;
         if (al + 1 < a.L.n) nxt = window(al + 1);
-        const float *zb = zq + (size_t)al * zstride;
-        float wt[9];
+        // raw buffer over the angle's slab plane: an offset past its end
+        // reads zeros, which is how candidates with a zero weight drop out
+        const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float *>(zs + (size_t)al * zstride), (short)0, (int)(N * rowb), kBufferDword3);
+        // this lane's window column jlo + q: weights and brick offsets of its
+        // three rows (lane 3 has none)
+        const int jp = cur.jlo + q;
+        const bool jin = q < 3 && (unsigned)jp < (unsigned)N;
+        const uint32_t jb = (uint32_t)jp * (SLAB * 4);
+        float wo[3];
+        int oo[3];
 #pragma unroll
-        for (int d = 0; d < 9; ++d) {
-            const int ip = cur.ilo + d / 3, jp = cur.jlo + d % 3;
-            const bool inr = (unsigned)ip < (unsigned)N && (unsigned)jp < (unsigned)N;
-            const float X = fmaf((float)ip, cur.cs.x, cur.o[d % 3].x), Y = fmaf((float)ip, cur.cs.y, cur.o[d % 3].y);
+        for (int di = 0; di < 3; ++di) {
+            const int ip = cur.ilo + di;
+            const bool inr = jin && (unsigned)ip < (unsigned)N;
+            const float X = fmaf((float)ip, cur.cs.x, cur.o.x), Y = fmaf((float)ip, cur.cs.y, cur.o.y);
             const float wx = fmaxf(0.f, 1.f - fabsf(X - fxv)), wy = fmaxf(0.f, 1.f - fabsf(Y - fyv));
-            wt[d] = inr ? wx * wy : 0.f;
+            wo[di] = inr ? wx * wy : 0.f;
+            oo[di] = wo[di] > 0.f ? (int)((uint32_t)ip * rowb + jb) : kPastEnd;
         }
-        // only candidates with a non-zero weight are read: the four lanes of a
-        // column share the weight, so whole quads drop out of the loads
-        float4 v[9];
-#pragma unroll
-        for (int d = 0; d < 9; ++d) {
-            v[d] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (wt[d] > 0.f) {
-                const int ipc = min(max(cur.ilo + d / 3, 0), N - 1), jpc = min(max(cur.jlo + d % 3, 0), N - 1);
-                v[d] = *reinterpret_cast<const float4 *>(zb + ((size_t)ipc * N + jpc) * SLAB);
-            }
-        }
-#pragma unroll
-        for (int d = 0; d < 9; ++d) {
-            acc[0] = fmaf(wt[d], v[d].x, acc[0]);
-            acc[1] = fmaf(wt[d], v[d].y, acc[1]);
-            acc[2] = fmaf(wt[d], v[d].z, acc[2]);
-            acc[3] = fmaf(wt[d], v[d].w, acc[3]);
-        }
+        // candidate d = 3 di + dj lives in lane dj of the quad
+#define SPECT_CAND(di, dj)                                                                  \
+    {                                                                                       \
+        const float wt = quad_bcast<dj>(wo[di]);                                            \
+        const int off = quad_bcast<dj>(oo[di]) + (int)qoff;                                 \
+        const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(zr, off, 0, 0)); \
+        acc[0] = fmaf(wt, v.x, acc[0]);                                                     \
+        acc[1] = fmaf(wt, v.y, acc[1]);                                                     \
+        acc[2] = fmaf(wt, v.z, acc[2]);                                                     \
+        acc[3] = fmaf(wt, v.w, acc[3]);                                                     \
+    }
+        SPECT_CAND(0, 0) SPECT_CAND(0, 1) SPECT_CAND(0, 2)
+        SPECT_CAND(1, 0) SPECT_CAND(1, 1) SPECT_CAND(1, 2)
+        SPECT_CAND(2, 0) SPECT_CAND(2, 1) SPECT_CAND(2, 2)
+#undef SPECT_CAND
     }
     const size_t base = ((size_t)x * N + y) * Nz;
 #pragma unroll
