@@ -400,7 +400,6 @@ size_t fwd_smem(int N, int kmc)
 
 size_t back_smem(int N, int kmc) { return wb_bytes(N, kmc) + sizeof(float) * (size_t)N * (SLAB + 2 * kmc + 1); }
 
-size_t wb_bytes(const spect_plan *p) { return wb_bytes(p->N, p->kmc); }
 size_t fwd_smem(const spect_plan *p) { return fwd_smem(p->N, p->kmc); }
 size_t back_smem(const spect_plan *p) { return back_smem(p->N, p->kmc); }
 

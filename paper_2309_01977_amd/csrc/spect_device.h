@@ -595,7 +595,12 @@ struct ReduceArgs {
 
 #ifdef SPECT_HOST_TU
 // Sum the partial rows of all chunks and overlapping slabs for one output
-// element (angle, bin, row).
+// element (angle, bin, row), chunks outer and slabs ascending.  The slabs
+// whose partial rows hold row k are s with k + kmc - R < 16 s <= k + kmc: at
+// most five for kmc <= 32, so their offsets are fixed before the chunk loop
+// and each chunk's loads are issued together.
+constexpr int RED_SLABS = 5;
+
 template <class Args>
 __device__ __forceinline__ void reduce_body(const Args &a, int blk, int al)
 {
@@ -605,15 +610,28 @@ __device__ __forceinline__ void reduce_body(const Args &a, int blk, int al)
     const int ang = a.L.idx[al];
     const int r = t / Nz, k = t % Nz;
     const int R = SLAB + 2 * a.kmc;
-    const int slo = max(0, (k + a.kmc - R) / SLAB);  // loose bound; rows are checked below
+    const int slo = max(0, (k + a.kmc - R + 4 * SLAB) / SLAB - 3);  // floor((k + kmc - R) / 16) + 1
     const int shi = min(a.nslab - 1, (k + a.kmc) / SLAB);
+    const size_t cstride = (size_t)N * R;  // one chunk
+    const float *pc = a.part + (size_t)al * a.nslab * a.nchunk * cstride + (size_t)r * R;
+    size_t off[RED_SLABS];
+    bool ok[RED_SLABS];
+#pragma unroll
+    for (int i = 0; i < RED_SLABS; ++i) {
+        const int s = slo + i;
+        ok[i] = s <= shi;
+        off[i] = ok[i] ? (size_t)s * a.nchunk * cstride + (size_t)(k - s * SLAB + a.kmc) : 0;
+    }
     float sum = 0.f;
-    for (int c = 0; c < a.nchunk; ++c)
-        for (int s = slo; s <= shi; ++s) {
-            const int row = k - s * SLAB + a.kmc;
-            if (row < 0 || row >= R) continue;
-            sum += a.part[((((size_t)al * a.nslab + s) * a.nchunk + c) * N + r) * R + row];
-        }
+    for (int c = 0; c < a.nchunk; ++c) {
+        const float *p = pc + (size_t)c * cstride;
+        float v[RED_SLABS];
+#pragma unroll
+        for (int i = 0; i < RED_SLABS; ++i) v[i] = p[off[i]];
+#pragma unroll
+        for (int i = 0; i < RED_SLABS; ++i)
+            if (ok[i]) sum += v[i];
+    }
     const size_t o = ((size_t)ang * N + r) * Nz + k;
     if (a.mode == 0) {
         a.proj[o] = sum;
