@@ -398,7 +398,9 @@ size_t fwd_smem(int N, int kmc)
     return std::max(wb_bytes(N, kmc), merge);
 }
 
-size_t back_smem(int N, int kmc) { return wb_bytes(N, kmc) + sizeof(float) * (size_t)N * (SLAB + 2 * kmc + 1); }
+// Row buffers plus the projection columns: N columns of SLAB + 2 kmc + 1
+// floats, skewed by 8 floats per group of 8 bins.
+size_t back_smem(int N, int kmc) { return wb_bytes(N, kmc) + sizeof(float) * (size_t)N * (SLAB + 2 * kmc + 2); }
 
 size_t fwd_smem(const spect_plan *p) { return fwd_smem(p->N, p->kmc); }
 size_t back_smem(const spect_plan *p) { return back_smem(p->N, p->kmc); }

@@ -689,14 +689,18 @@ __device__ __forceinline__ void back_body(const Args &a, int slab, int chunk, in
     float *ybuf = reinterpret_cast<float *>(smem + 2 * 2 * nrows * 2);
 
     zero_padding<KMC>(smem, N, nrows);
-    // axial rows k0 - KMC .. k0 + SLAB + KMC - 1 of the projection, per bin
+    // axial rows k0 - KMC .. k0 + SLAB + KMC - 1 of the projection, per bin;
+    // bin jp's column starts at jp * YP + 8 (jp / 8), which puts the 64 lanes
+    // of a column read (bins jp, halves h reading rows 8 h + c) in distinct
+    // banks of a 32- or 64-bank LDS
+    float *ycol = ybuf + jp * YP + 8 * (jp >> 3);
     if (active) {
         const float *yr = a.y + ((size_t)(a.y_compact ? al : ang) * N + jp) * Nz;
         for (int t = h; t < R; t += 2) {
             const int k = k0 - KMC + t;
             float v = 0.f;
             if (k >= 0 && k < Nz) v = a.ones ? 1.f : yr[k];
-            ybuf[jp * YP + t] = v;
+            ycol[t] = v;
         }
     }
 
@@ -733,7 +737,7 @@ __device__ __forceinline__ void back_body(const Args &a, int slab, int chunk, in
                 t0 = at_byte<float4>(a.att + row0, toff);
                 t1 = at_byte<float4>(a.att + row0, toff + 16);
             }
-            ZGather zg{ybuf + jp * YP, h * ROWS + KMC, gt, v};
+            ZGather zg{ycol, h * ROWS + KMC, gt, v};
             KSwitch<0, KMC>::run(K, zg);
             smem[wb_index(buf, 0, jp + KMC, h, nrows)] = make_float4(v[0], v[1], v[2], v[3]);
             smem[wb_index(buf, 1, jp + KMC, h, nrows)] = make_float4(v[4], v[5], v[6], v[7]);
