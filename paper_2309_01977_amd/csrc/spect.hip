@@ -609,7 +609,7 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
     const int tiles = (p->N + GT - 1) / GT;
     {
         ProfScope ps(K_GATHER, st);
-        hipLaunchKernelGGL(back_gather, dim3(tiles * tiles, t.nslab), dim3(256), 0, st, gg);
+        hipLaunchKernelGGL(back_gather, dim3(tiles * tiles, (t.nslab + GS - 1) / GS), dim3(256), 0, st, gg);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "back projection launch");
@@ -1462,8 +1462,8 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
                 for (int al = 0; al < L.n; ++al)
                     for (int k = 0; k < blocks; ++k) rt.push_back(Task{li_, k, 0, al});
                 const int tiles = (p->N + GT - 1) / GT;
-                for (int sl = 0; sl < t.nslab; ++sl)
-                    for (int k = 0; k < tiles * tiles; ++k) gt.push_back(Task{li_, k, sl, 0});
+                for (int sp = 0; sp < (t.nslab + GS - 1) / GS; ++sp)
+                    for (int k = 0; k < tiles * tiles; ++k) gt.push_back(Task{li_, k, sp, 0});
             }
             // longest tasks first, so that the tail of the launch is short
             auto by_cost = [](const std::pair<long, Task> &x, const std::pair<long, Task> &y) {

@@ -911,16 +911,18 @@ struct GatherArgs {
 };
 
 // Transpose of the bilinear rotation, as a gather.  Workgroup = 8 x 8 object
-// columns x one slab; a wave covers 16 columns and four lanes share a column,
-// one per 16-byte quad of its 16 axial rows, so that every candidate brick
-// (64 bytes) is read by four adjacent lanes.  For each angle a column takes
-// the <= 3 x 3 rotated samples around its rotated position; the weight of
-// sample P is the bilinear hat max(0, 1 - |X_P - x|) max(0, 1 - |Y_P - y|),
-// with X_P, Y_P computed by the forward's own FP32 expression, so the weights
-// equal the forward's to within one rounding.  Lane q of a column evaluates
-// the three candidates of window column q (lane 3 none) and the quad shares
-// weights and brick offsets through DPP quad permutes.
+// columns x two slabs; a wave covers 16 columns and four lanes share a
+// column, lane q taking the 16-byte quad q of the column's 16 axial rows in
+// both slabs, so that every candidate brick (64 bytes) is read by four
+// adjacent lanes.  For each angle a column takes the <= 3 x 3 rotated samples
+// around its rotated position; the weight of sample P is the bilinear hat
+// max(0, 1 - |X_P - x|) max(0, 1 - |Y_P - y|), with X_P, Y_P computed by the
+// forward's own FP32 expression, so the weights equal the forward's to within
+// one rounding.  Lane q of a column evaluates the three candidates of window
+// column q (lane 3 none) and the quad shares weights and brick offsets through
+// DPP quad permutes; the two slabs use the same weights.
 constexpr int GT = 8;  // gather tile edge
+constexpr int GS = 2;  // slabs per gather workgroup
 
 #ifdef SPECT_HOST_TU
 // Value of lane `src` of this lane's quad (all four lanes active).
@@ -943,7 +945,7 @@ __device__ __forceinline__ float quad_bcast(float v)
 }
 
 template <class Args>
-__device__ __forceinline__ void gather_body(const Args &a, int tile, int slab)
+__device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
 {
     const int N = a.g.N, Nz = a.g.Nz;
     const int tiles = (N + GT - 1) / GT;
@@ -952,14 +954,17 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int slab)
     const int x = (tile / tiles) * GT + wave * 2 + (col >> 3);
     const int y = (tile % tiles) * GT + (col & 7);
     if (x >= N || y >= N) return;  // whole quads leave together
+    const int slab0 = pair * GS;
+    const int nsl = min(GS, a.nslab - slab0);  // slabs present in this pair
     const float c = 0.5f * (float)(N - 1);
     const float xx = (float)x - c, yy = (float)y - c;
     const float fxv = (float)x, fyv = (float)y;
-    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    float acc[GS][4] = {};
     const size_t zstride = (size_t)a.nslab * N * N * SLAB;
-    const float *zs = a.z + (size_t)slab * N * N * SLAB;
-    const uint32_t qoff = 16u * (uint32_t)q;
+    const float *zs = a.z + (size_t)slab0 * N * N * SLAB;
+    const int qoff = 16 * q;
     const uint32_t rowb = (uint32_t)N * SLAB * 4;  // bytes per rotated row i' (N <= 256: < 2^22)
+    const int planeb = (int)(N * rowb);             // bytes per slab plane (<= 4 MiB)
     // Candidate window of angle al and the ray origin of this lane's window
     // column; fetched one angle ahead so that the weights are known before
     // the brick loads are issued.
@@ -984,10 +989,11 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int slab)
     for (int al = 0; al < a.L.n; ++al) {
         const Win cur = nxt;
         if (al + 1 < a.L.n) nxt = window(al + 1);
-        // raw buffer over the angle's slab plane: an offset past its end
-        // reads zeros, which is how candidates with a zero weight drop out
+        // raw buffer over the angle's planes of this slab pair: an offset
+        // past its end reads zeros, which is how candidates with a zero
+        // weight (and the second plane of a lone last slab) drop out
         const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<float *>(zs + (size_t)al * zstride), (short)0, (int)(N * rowb), kBufferDword3);
+            const_cast<float *>(zs + (size_t)al * zstride), (short)0, nsl * planeb, kBufferDword3);
         // this lane's window column jlo + q: weights and brick offsets of its
         // three rows (lane 3 has none)
         const int jp = cur.jlo + q;
@@ -1005,15 +1011,19 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int slab)
             oo[di] = wo[di] > 0.f ? (int)((uint32_t)ip * rowb + jb) : kPastEnd;
         }
         // candidate d = 3 di + dj lives in lane dj of the quad
-#define SPECT_CAND(di, dj)                                                                  \
-    {                                                                                       \
-        const float wt = quad_bcast<dj>(wo[di]);                                            \
-        const int off = quad_bcast<dj>(oo[di]) + (int)qoff;                                 \
-        const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(zr, off, 0, 0)); \
-        acc[0] = fmaf(wt, v.x, acc[0]);                                                     \
-        acc[1] = fmaf(wt, v.y, acc[1]);                                                     \
-        acc[2] = fmaf(wt, v.z, acc[2]);                                                     \
-        acc[3] = fmaf(wt, v.w, acc[3]);                                                     \
+#define SPECT_CAND(di, dj)                                                                          \
+    {                                                                                               \
+        const float wt = quad_bcast<dj>(wo[di]);                                                    \
+        const int off = quad_bcast<dj>(oo[di]) + qoff;                                              \
+        _Pragma("unroll") for (int sl = 0; sl < GS; ++sl)                                           \
+        {                                                                                           \
+            const float4 v =                                                                        \
+                __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(zr, off + sl * planeb, 0, 0)); \
+            acc[sl][0] = fmaf(wt, v.x, acc[sl][0]);                                                 \
+            acc[sl][1] = fmaf(wt, v.y, acc[sl][1]);                                                 \
+            acc[sl][2] = fmaf(wt, v.z, acc[sl][2]);                                                 \
+            acc[sl][3] = fmaf(wt, v.w, acc[sl][3]);                                                 \
+        }                                                                                           \
     }
         SPECT_CAND(0, 0) SPECT_CAND(0, 1) SPECT_CAND(0, 2)
         SPECT_CAND(1, 0) SPECT_CAND(1, 1) SPECT_CAND(1, 2)
@@ -1022,23 +1032,26 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int slab)
     }
     const size_t base = ((size_t)x * N + y) * Nz;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int k = slab * SLAB + 4 * q + r;
-        if (k >= Nz) break;
-        float *p = a.out + base + k;
-        if (a.mode == 0) {
-            *p = acc[r];
-        } else if (a.mode == 1) {
-            *p += acc[r];
-        } else if (a.mode == 2) {
-            const float sv = a.sens[base + k];
-            if (sv > 0.f) *p = *p * acc[r] / sv;
-        } else {
-            const float sa = a.bt.sens_all[base + k];
-            if (sa > 0.f) {
-                const float fv = *p;
-                const float step = acc[r] - a.sens[base + k] - a.bt.c_beta * a.bt.prior[base + k];
-                *p = fmaxf(0.f, fv + fv * a.bt.a_over_c / sa * step);
+    for (int sl = 0; sl < GS; ++sl) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = (slab0 + sl) * SLAB + 4 * q + r;
+            if (k >= Nz) break;
+            float *p = a.out + base + k;
+            if (a.mode == 0) {
+                *p = acc[sl][r];
+            } else if (a.mode == 1) {
+                *p += acc[sl][r];
+            } else if (a.mode == 2) {
+                const float sv = a.sens[base + k];
+                if (sv > 0.f) *p = *p * acc[sl][r] / sv;
+            } else {
+                const float sa = a.bt.sens_all[base + k];
+                if (sa > 0.f) {
+                    const float fv = *p;
+                    const float step = acc[sl][r] - a.sens[base + k] - a.bt.c_beta * a.bt.prior[base + k];
+                    *p = fmaxf(0.f, fv + fv * a.bt.a_over_c / sa * step);
+                }
             }
         }
     }
