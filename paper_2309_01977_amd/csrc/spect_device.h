@@ -920,7 +920,9 @@ struct GatherArgs {
 // forward's own FP32 expression, so the weights equal the forward's to within
 // one rounding.  Lane q of a column evaluates the three candidates of window
 // column q (lane 3 none) and the quad shares weights and brick offsets through
-// DPP quad permutes; the two slabs use the same weights.
+// DPP quad permutes; the two slabs use the same weights.  Zero-weight
+// candidates are not loaded: the data-return path, not arithmetic, bounds
+// this kernel.
 constexpr int GT = 8;  // gather tile edge
 constexpr int GS = 2;  // slabs per gather workgroup
 
@@ -986,12 +988,16 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
     };
     Win nxt;
     if (a.L.n > 0) nxt = window(0);
+    float4 vv[GS][9];  // candidate bricks, kept across angles (see below)
+#pragma unroll
+    for (int sl = 0; sl < GS; ++sl)
+#pragma unroll
+        for (int d = 0; d < 9; ++d) vv[sl][d] = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int al = 0; al < a.L.n; ++al) {
         const Win cur = nxt;
         if (al + 1 < a.L.n) nxt = window(al + 1);
         // raw buffer over the angle's planes of this slab pair: an offset
-        // past its end reads zeros, which is how candidates with a zero
-        // weight (and the second plane of a lone last slab) drop out
+        // past its end reads zeros (the second plane of a lone last slab)
         const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float *>(zs + (size_t)al * zstride), (short)0, nsl * planeb, kBufferDword3);
         // this lane's window column jlo + q: weights and brick offsets of its
@@ -1010,19 +1016,25 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
             wo[di] = inr ? wx * wy : 0.f;
             oo[di] = wo[di] > 0.f ? (int)((uint32_t)ip * rowb + jb) : kPastEnd;
         }
-        // candidate d = 3 di + dj lives in lane dj of the quad
+        // candidate d = 3 di + dj lives in lane dj of the quad.  Only
+        // candidates with a non-zero weight are loaded (the weight is the
+        // quad's, so whole quads drop out and return no data); a skipped
+        // candidate multiplies its weight 0 with what the register held: zero
+        // or a value this lane loaded earlier with a positive weight into the
+        // same row sums, so the product is 0 unless that row's sum is already
+        // non-finite.
 #define SPECT_CAND(di, dj)                                                                          \
     {                                                                                               \
+        constexpr int d = 3 * (di) + (dj);                                                          \
         const float wt = quad_bcast<dj>(wo[di]);                                                    \
         const int off = quad_bcast<dj>(oo[di]) + qoff;                                              \
         _Pragma("unroll") for (int sl = 0; sl < GS; ++sl)                                           \
         {                                                                                           \
-            const float4 v =                                                                        \
-                __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(zr, off + sl * planeb, 0, 0)); \
-            acc[sl][0] = fmaf(wt, v.x, acc[sl][0]);                                                 \
-            acc[sl][1] = fmaf(wt, v.y, acc[sl][1]);                                                 \
-            acc[sl][2] = fmaf(wt, v.z, acc[sl][2]);                                                 \
-            acc[sl][3] = fmaf(wt, v.w, acc[sl][3]);                                                 \
+            if (wt > 0.f) vv[sl][d] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(zr, off + sl * planeb, 0, 0)); \
+            acc[sl][0] = fmaf(wt, vv[sl][d].x, acc[sl][0]);                                         \
+            acc[sl][1] = fmaf(wt, vv[sl][d].y, acc[sl][1]);                                         \
+            acc[sl][2] = fmaf(wt, vv[sl][d].z, acc[sl][2]);                                         \
+            acc[sl][3] = fmaf(wt, vv[sl][d].w, acc[sl][3]);                                         \
         }                                                                                           \
     }
         SPECT_CAND(0, 0) SPECT_CAND(0, 1) SPECT_CAND(0, 2)
