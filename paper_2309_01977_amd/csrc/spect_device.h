@@ -296,11 +296,15 @@ __device__ __forceinline__ void blur_bins(const float4 *__restrict__ wb, int i0,
     }
 }
 
+// The plan's tables (radii, taps, tap sums) never change once built, so the
+// kernels read them through the constant address space: uniform reads are
+// then scalar loads even in loops that also store to global memory.
 template <int K>
 __device__ __forceinline__ void load_taps(const float *__restrict__ g, float (&gk)[K + 1])
 {
+    ConstMem<float> *cg = as_const(g);
 #pragma unroll
-    for (int m = 0; m <= K; ++m) gk[m] = g[m];
+    for (int m = 0; m <= K; ++m) gk[m] = cg[m];
 }
 
 // Axial blur as a scatter: input row s (0..7) adds g(|l|) u[s] to output row
@@ -480,7 +484,7 @@ __device__ __forceinline__ void fwd_body(const Args &a, int slab, int chunk, int
 
     const int ihi = N - chunk * a.dchunk - 1;
     const int ilo = max(0, N - (chunk + 1) * a.dchunk);
-    const int *kd = a.g.kdep + (size_t)ang * N;
+    ConstMem<int> *kd = as_const(a.g.kdep + (size_t)ang * N);
     const RowGeom rg = row_geom(kb, Nz);
     // attenuation table: uniform base of this (angle, slab) + per-thread offset
     const float *tab = ATT == ATT_READ ? a.att + brick_offset(al, a.nslab, slab, N, 0, 0) : nullptr;
@@ -712,7 +716,7 @@ __device__ __forceinline__ void back_body(const Args &a, int slab, int chunk, in
     if (MU && chunk > 0 && active) chunk_start(a.tau, al, a.nchunk, chunk, N, Nz, jp, kb, S);
     const int ihi = N - chunk * a.dchunk - 1;
     const int ilo = max(0, N - (chunk + 1) * a.dchunk);
-    const int *kd = a.g.kdep + (size_t)ang * N;
+    ConstMem<int> *kd = as_const(a.g.kdep + (size_t)ang * N);
     const RowGeom rg = row_geom(kb, Nz);
     // table and rotated-frame bricks: uniform base of this (angle, slab) + per-thread offset
     const size_t wg0 = brick_offset(al, a.nslab, slab, N, 0, 0);
@@ -829,13 +833,13 @@ __device__ __forceinline__ void sens_body(const Args &a, int slab, int chunk, in
     if (MU && chunk > 0) chunk_start(a.tau, al, a.nchunk, chunk, N, Nz, jp, kb, S);
     const int ihi = N - chunk * a.dchunk - 1;
     const int ilo = max(0, N - (chunk + 1) * a.dchunk);
-    const int *kd = a.g.kdep + (size_t)ang * N;
+    ConstMem<int> *kd = as_const(a.g.kdep + (size_t)ang * N);
     const RowGeom rg = row_geom(kb, Nz);
     const size_t wg0 = brick_offset(al, a.nslab, slab, N, 0, 0);
     const uint32_t toff = 4u * (uint32_t)(jp * SLAB + h * ROWS);
     for (int ip = ihi; ip >= ilo; --ip) {
         const int K = kd[ip];
-        const float *ct = a.g.ctaps + ((size_t)ang * N + ip) * a.g.TS;
+        ConstMem<float> *ct = as_const(a.g.ctaps + ((size_t)ang * N + ip) * a.g.TS);
         const float g0 = ct[0];
         const float er = ct[min(K, jp)] + ct[min(K, N - 1 - jp)] - g0;
         float u[ROWS];
