@@ -356,7 +356,7 @@ int bsrem_reconstruct(const spect_plan *plan, float *f, const float *mu, const f
  * launch's own stream.  spect_profile_query waits for the recorded launches of
  * the named kernel ("tau_prepass", "fwd_main", "fwd_reduce", "back_rot",
  * "back_gather", "fill_zero", "rdp_grad", "vol_sum", "fwd_batch", "reduce_batch",
- * "back_batch", "gather_batch", "sens_rot") and returns their count and summed duration in
+ * "back_batch", "gather_batch", "sens_line") and returns their count and summed duration in
  * milliseconds; spect_profile_reset waits for and frees all records.
  * Errors: SPECT_EINVAL (NULL argument, unknown name), SPECT_EHIP. */
 int spect_profile_enable(int enable);

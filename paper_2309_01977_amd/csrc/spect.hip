@@ -45,7 +45,7 @@ enum KernelId {
 const char *const kKernelNames[K_COUNT] = {"tau_prepass", "fwd_main", "fwd_reduce", "back_rot",
                                            "back_gather", "fill_zero", "rdp_grad", "vol_sum",
                                            "fwd_batch", "reduce_batch", "back_batch", "gather_batch",
-                                           "sens_rot"};
+                                           "sens_line"};
 
 struct ProfRec {
     int kernel;
@@ -412,6 +412,7 @@ void allow_smem(const void *fn, size_t bytes)
 }
 
 bool aligned16(const void *q) { return ((uintptr_t)q & 15) == 0; }
+bool aligned8(const void *q) { return ((uintptr_t)q & 7) == 0; }
 
 int check_plan(const spect_plan *p)
 {
@@ -557,7 +558,9 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
         return fail(SPECT_EINVAL, "workspace too small for a %d-angle back-projection launch", L.n);
     const float *tau = nullptr;
     size_t off = 0;
-    const size_t tb = tau_bytes(p, t, L.n, att);
+    // the sensitivity pass (ones) keeps one running attenuation sum per
+    // thread and needs no chunk offsets
+    const size_t tb = ones ? 0 : tau_bytes(p, t, L.n, att);
     if (tb) {
         off += tb;
         if (tau_given) {
@@ -583,14 +586,18 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
     b.dchunk = t.dchunk;
     b.vec = vec;
     if (ones) {
-        // constant projection: the blur reduces to in-range tap sums (sens_rot)
+        // constant projection: the blur reduces to in-range tap sums, and the
+        // pass walks every depth in one thread (no chunk offsets)
+        const bool v2 = p->Nz % 2 == 0 && (mu == nullptr || aligned8(mu));
         BackFn sk = nullptr;
-        if (att == ATT_WRITE) sk = vec ? sens_rot<ATT_WRITE, true> : sens_rot<ATT_WRITE, false>;
-        else if (att == ATT_SAMPLE) sk = vec ? sens_rot<ATT_SAMPLE, true> : sens_rot<ATT_SAMPLE, false>;
-        else if (att == ATT_NONE) sk = sens_rot<ATT_NONE, true>;
+        if (att == ATT_WRITE) sk = v2 ? sens_line<ATT_WRITE, true> : sens_line<ATT_WRITE, false>;
+        else if (att == ATT_SAMPLE) sk = v2 ? sens_line<ATT_SAMPLE, true> : sens_line<ATT_SAMPLE, false>;
+        else if (att == ATT_NONE) sk = sens_line<ATT_NONE, false>;
         if (!sk) return fail(SPECT_EINVAL, "no sensitivity pass for attenuation mode %d", att);
+        b.nchunk = 1;
         ProfScope ps(K_SENS, st);
-        hipLaunchKernelGGL(sk, dim3(t.nslab, t.nchunk, L.n), dim3(block_threads(p->N)), 0, st, b);
+        hipLaunchKernelGGL(sk, dim3((p->N * (SLAB / 2) + SL_THREADS - 1) / SL_THREADS, t.nslab, L.n),
+                           dim3(SL_THREADS), 0, st, b);
     } else {
         BackFn bk = back_kernel(att, p->kmc, vec);
         allow_smem(reinterpret_cast<const void *>(bk), back_smem(p));

@@ -877,13 +877,8 @@ __device__ __forceinline__ void sens_body(const Args &a, int slab, int chunk, in
     }
 }
 
-template <int ATT, bool VEC>
-__global__ __launch_bounds__(512) void sens_rot(BackRotArgs a)
-{
-    sens_body<ATT, VEC>(a, blockIdx.x, blockIdx.y, blockIdx.z);
-}
-
-// The same over a batch work-list, one task per workgroup.
+// The sensitivity pass over a batch work-list, one task (angle, slab, depth
+// chunk) per workgroup.
 template <int ATT, bool VEC>
 __global__ __launch_bounds__(512) void sens_batch(BatchList<BackRotArgs> b)
 {
@@ -892,6 +887,108 @@ __global__ __launch_bounds__(512) void sens_batch(BatchList<BackRotArgs> b)
     for (int t = blockIdx.x; t < b.ntasks; t += gridDim.x)
         sens_body<ATT, VEC>(args[tasks[t].r], tasks[t].x, tasks[t].y, tasks[t].z);
 }
+
+// Sensitivity pass of one angle list with one thread per (angle, slab, bin,
+// pair of axial rows) walking every depth from the detector side.  The blur
+// of a constant projection needs no neighbours (the tap-sum product of
+// sens_body), so there is no LDS and no depth split: the attenuation sum is
+// one running sum per row and mu is sampled once per depth.  Per-depth values
+// are computed as in sens_body with a single depth chunk.  V2: Nz even and an
+// 8-byte aligned mu, so a pair of rows loads as one float2.
+constexpr int SL_THREADS = 256;
+
+template <int ATT, bool V2>
+__global__ __launch_bounds__(SL_THREADS) void sens_line(BackRotArgs a)
+{
+    constexpr bool MU = ATT == ATT_SAMPLE || ATT == ATT_WRITE;
+    const int N = a.g.N, Nz = a.g.Nz;
+    const int t = blockIdx.x * SL_THREADS + threadIdx.x;
+    const int jp = t >> 3, rp = t & 7;
+    if (jp >= N) return;
+    const int slab = blockIdx.y, al = blockIdx.z;
+    const int ang = a.L.idx[al];
+    const int k0 = slab * SLAB;
+    const int k = k0 + 2 * rp;  // rows k and k + 1; rows past Nz get values the gather never reads
+    const bool in0 = k < Nz, in1 = k + 1 < Nz;
+    const float2 cs = a.g.cs[ang];
+    const float2 o = a.g.xy0[(size_t)ang * N + jp];
+    ConstMem<int> *kd = as_const(a.g.kdep + (size_t)ang * N);
+    // mu is only read here, so its loads may move ahead of this thread's
+    // stores (next depth's corners are loaded before this depth is stored)
+    ConstMem<float> *mu = as_const(a.mu);
+    const uint32_t rowb = 4u * (uint32_t)Nz;
+    // byte offsets of the two rows in a z-run, clamped to valid rows (V2: k
+    // and Nz even, so both rows are in range or both past Nz)
+    const uint32_t dk0 = 4u * (uint32_t)min(k, Nz - 1), dk1 = 4u * (uint32_t)min(k + 1, Nz - 1);
+    const uint32_t dkp = 4u * (uint32_t)max(0, min(k, Nz - 2));
+    const size_t e0 = brick_offset(al, a.nslab, slab, N, 0, 0) + (size_t)jp * SLAB + 2 * rp;
+    struct Samp {
+        Corners cn;
+        float v0[4], v1[4];
+    };
+    auto sample = [&](int ip, Samp &sp) {
+        sp.cn = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, rowb);
+        const uint32_t oc[4] = {sp.cn.b00, sp.cn.b10, sp.cn.b01, sp.cn.b11};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if constexpr (V2) {
+                typedef float pair_t __attribute__((ext_vector_type(2)));
+                const pair_t pr = *reinterpret_cast<ConstMem<pair_t> *>(reinterpret_cast<ConstMem<char> *>(mu) + oc[j] + dkp);
+                sp.v0[j] = pr.x;
+                sp.v1[j] = pr.y;
+            } else {
+                sp.v0[j] = *reinterpret_cast<ConstMem<float> *>(reinterpret_cast<ConstMem<char> *>(mu) + oc[j] + dk0);
+                sp.v1[j] = *reinterpret_cast<ConstMem<float> *>(reinterpret_cast<ConstMem<char> *>(mu) + oc[j] + dk1);
+            }
+        }
+    };
+    float S0 = 0.f, S1 = 0.f;
+    // one depth from the samples in sp (loaded one depth earlier)
+    auto step = [&](int ip, const Samp &sp) {
+        const int K = kd[ip];
+        ConstMem<float> *ct = as_const(a.g.ctaps + ((size_t)ang * N + ip) * a.g.TS);
+        const float g0 = ct[0], cK = ct[K];
+        // in-range tap sums across bins and rows; an interior slab (both
+        // sides reach K inside the detector) takes 2 C[K] - g0
+        const float cr0 = ct[min(K, jp)], cr1 = ct[min(K, N - 1 - jp)];
+        const bool zin = k0 - K >= 0 && k0 + SLAB - 1 + K < Nz;
+        const float cz0 = ct[min(K, max(k, 0))], cz1 = ct[max(0, min(K, Nz - 1 - k))];
+        const float cz2 = ct[min(K, max(k + 1, 0))], cz3 = ct[max(0, min(K, Nz - 2 - k))];
+        const float er = cr0 + cr1 - g0;
+        const float ezi = 2.f * cK - g0;
+        float u0 = er * (zin ? ezi : cz0 + cz1 - g0);
+        float u1 = er * (zin ? ezi : cz2 + cz3 - g0);
+        const size_t e = e0 + (size_t)ip * N * SLAB;
+        if (MU) {
+            const Corners &cn = sp.cn;
+            float m0 = fmaf(cn.w11, sp.v0[3], fmaf(cn.w01, sp.v0[2], fmaf(cn.w10, sp.v0[1], cn.w00 * sp.v0[0])));
+            float m1 = fmaf(cn.w11, sp.v1[3], fmaf(cn.w01, sp.v1[2], fmaf(cn.w10, sp.v1[1], cn.w00 * sp.v1[0])));
+            if (!in0) m0 = 0.f;
+            if (!in1) m1 = 0.f;
+            const float a0 = __builtin_amdgcn_exp2f(-a.g.tau_scale * fmaf(0.5f, m0, S0));
+            const float a1 = __builtin_amdgcn_exp2f(-a.g.tau_scale * fmaf(0.5f, m1, S1));
+            S0 += m0;
+            S1 += m1;
+            u0 *= a0;
+            u1 *= a1;
+            if (ATT == ATT_WRITE) *reinterpret_cast<float2 *>(a.att + e) = make_float2(a0, a1);
+        }
+        *reinterpret_cast<float2 *>(a.z + e) = make_float2(u0, u1);
+    };
+    // two sample buffers used in turn: the next depth's corners are loaded
+    // before this depth is computed and stored, and every load is waited for
+    // only where it is used (no register copies)
+    Samp sa, sb;
+    if (MU) sample(N - 1, sa);
+    for (int ip = N - 1; ip >= 0; ip -= 2) {
+        if (MU) sample(max(ip - 1, 0), sb);
+        step(ip, sa);
+        if (ip == 0) break;
+        if (MU) sample(max(ip - 2, 0), sa);
+        step(ip - 1, sb);
+    }
+}
+
 #endif  // SPECT_HOST_TU
 
 // Terms of the BSREM update (gather mode 3): where sens_all > 0,
