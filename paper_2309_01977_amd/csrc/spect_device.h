@@ -975,17 +975,27 @@ __global__ __launch_bounds__(SL_THREADS) void sens_line(BackRotArgs a)
         }
         *reinterpret_cast<float2 *>(a.z + e) = make_float2(u0, u1);
     };
-    // two sample buffers used in turn: the next depth's corners are loaded
-    // before this depth is computed and stored, and every load is waited for
-    // only where it is used (no register copies)
-    Samp sa, sb;
-    if (MU) sample(N - 1, sa);
-    for (int ip = N - 1; ip >= 0; ip -= 2) {
-        if (MU) sample(max(ip - 1, 0), sb);
-        step(ip, sa);
-        if (ip == 0) break;
-        if (MU) sample(max(ip - 2, 0), sa);
-        step(ip - 1, sb);
+    // four sample buffers used in turn: the corners of the depth three
+    // steps ahead are loaded before this depth is computed and stored, and
+    // every load is waited for only where it is used (no register copies)
+    Samp s0, s1, s2, s3;
+    if (MU) {
+        sample(N - 1, s0);
+        sample(max(N - 2, 0), s1);
+        sample(max(N - 3, 0), s2);
+    }
+    for (int ip = N - 1; ip >= 0; ip -= 4) {
+        if (MU) sample(max(ip - 3, 0), s3);
+        step(ip, s0);
+        if (ip - 1 < 0) break;
+        if (MU) sample(max(ip - 4, 0), s0);
+        step(ip - 1, s1);
+        if (ip - 2 < 0) break;
+        if (MU) sample(max(ip - 5, 0), s1);
+        step(ip - 2, s2);
+        if (ip - 3 < 0) break;
+        if (MU) sample(max(ip - 6, 0), s2);
+        step(ip - 3, s3);
     }
 }
 
