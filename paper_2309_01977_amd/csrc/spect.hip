@@ -1452,9 +1452,11 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
                 sgg.out = sens;
                 sgg.sens = nullptr;
                 sg.push_back(sgg);
+                const int sblk = (p->N * (SLAB / 2) + SL_THREADS - 1) / SL_THREADS;
                 for (int al = 0; al < L.n; ++al)
                     for (int sl = 0; sl < t.nslab; ++sl)
-                        stk.push_back({(long)p->N * p->N, Task{(int)li, sl, 0, al}});
+                        for (int k = 0; k < sblk; ++k)
+                            stk.push_back({(long)p->N * p->N, Task{(int)li, k, sl, al}});
                 const int li_ = (int)li;
                 const long cost = (long)t.dchunk * p->N;  // depths x bins of one task
                 for (int al = 0; al < L.n; ++al)
@@ -1537,9 +1539,9 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
                       o.nb};
             l.gat = {reinterpret_cast<const GatherArgs *>(d + o.ga), reinterpret_cast<const Task *>(d + o.gt), o.ng};
             if (b->mu)
-                l.sk = vec ? sens_batch<ATT_WRITE, true> : sens_batch<ATT_WRITE, false>;
+                l.sk = vec ? sensl_batch<ATT_WRITE, true> : sensl_batch<ATT_WRITE, false>;
             else
-                l.sk = sens_batch<ATT_NONE, true>;
+                l.sk = sensl_batch<ATT_NONE, false>;
             l.sback = {reinterpret_cast<const BackRotArgs *>(d + o.sa), reinterpret_cast<const Task *>(d + o.st),
                        o.ns};
             l.sgat = {reinterpret_cast<const GatherArgs *>(d + o.sg), reinterpret_cast<const Task *>(d + o.gt), o.ng};
@@ -1556,7 +1558,7 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
                 l.gr = std::max(1, std::min(o.nr, 8 * b->cus));
                 l.gg = std::max(1, std::min(o.ng, 8 * b->cus));
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(l.sk),
-                                                                  l.threads, 0) != hipSuccess || nb < 1)
+                                                                  SL_THREADS, 0) != hipSuccess || nb < 1)
                     nb = 1;
                 l.gsb = std::max(1, std::min(o.ns, nb * b->cus));
             } else {
@@ -1633,7 +1635,7 @@ int batch_sensitivities(const spect_batch *b, hipStream_t st)
         for (const BatchLaunch &l : b->steps[m]) {
             {
                 ProfScope ps(K_SENS, st);
-                hipLaunchKernelGGL(l.sk, dim3(l.gsb), dim3(l.threads), 0, st, l.sback);
+                hipLaunchKernelGGL(l.sk, dim3(l.gsb), dim3(SL_THREADS), 0, st, l.sback);
             }
             {
                 ProfScope ps(K_GATHER_B, st);

@@ -810,102 +810,24 @@ __global__ __launch_bounds__(512) void back_batch(BatchList<BackRotArgs> b)
 // tap sums along the bin axis and the axial axis:
 //     (G_r G_z 1)(j', k) = e_r(j') e_z(k),  e_r(j') = sum_{|m|<=K, 0<=j'+m<N} g_|m|
 //                                                  = C[min(K, j')] + C[min(K, N-1-j')] - g_0
-// with the running tap sums C (e_z likewise over 0 <= k+l < Nz); the value is that product times the
-// attenuation factor, written to the rotated-frame bricks like back_rot
-// (ATT_WRITE also stores the factors).  Same grid and thread mapping as
-// back_rot; no LDS.
-template <int ATT, bool VEC, class Args>
-__device__ __forceinline__ void sens_body(const Args &a, int slab, int chunk, int al)
-{
-    constexpr bool MU = ATT == ATT_SAMPLE || ATT == ATT_WRITE;
-    const int N = a.g.N, Nz = a.g.Nz;
-    const int ang = a.L.idx[al];
-    const int jp = threadIdx.x >> 1, h = threadIdx.x & 1;
-    if (jp >= N) return;
-    const int k0 = slab * SLAB;
-    const int kb = k0 + h * ROWS;
-    const bool full = k0 + SLAB <= Nz;
-    const float2 cs = a.g.cs[ang];
-    const float2 o = a.g.xy0[(size_t)ang * N + jp];
-    float S[ROWS];
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) S[r] = 0.f;
-    if (MU && chunk > 0) chunk_start(a.tau, al, a.nchunk, chunk, N, Nz, jp, kb, S);
-    const int ihi = N - chunk * a.dchunk - 1;
-    const int ilo = max(0, N - (chunk + 1) * a.dchunk);
-    ConstMem<int> *kd = as_const(a.g.kdep + (size_t)ang * N);
-    const RowGeom rg = row_geom(kb, Nz);
-    const size_t wg0 = brick_offset(al, a.nslab, slab, N, 0, 0);
-    const uint32_t toff = 4u * (uint32_t)(jp * SLAB + h * ROWS);
-    for (int ip = ihi; ip >= ilo; --ip) {
-        const int K = kd[ip];
-        ConstMem<float> *ct = as_const(a.g.ctaps + ((size_t)ang * N + ip) * a.g.TS);
-        const float g0 = ct[0];
-        const float er = ct[min(K, jp)] + ct[min(K, N - 1 - jp)] - g0;
-        float u[ROWS];
-        if (k0 - K >= 0 && k0 + SLAB - 1 + K < Nz) {
-            const float ez = 2.f * ct[K] - g0;
-#pragma unroll
-            for (int r = 0; r < ROWS; ++r) u[r] = er * ez;
-        } else {
-#pragma unroll
-            for (int r = 0; r < ROWS; ++r) {
-                const int k = kb + r;  // rows past Nz get a value the gather never reads
-                const float ez = ct[min(K, max(k, 0))] + ct[max(0, min(K, Nz - 1 - k))] - g0;
-                u[r] = er * ez;
-            }
-        }
-        const size_t row0 = wg0 + (size_t)ip * N * SLAB;
-        if (MU) {
-            const Corners cn = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, rg.rowb);
-            Raw rm;
-            load_raw<VEC>(a.mu, cn, rg, kb, Nz, rm);
-            float m[ROWS], att[ROWS];
-            combine(rm, cn, kb, Nz, m, full);
-            attenuate(m, S, a.g.tau_scale, att);
-#pragma unroll
-            for (int r = 0; r < ROWS; ++r) u[r] *= att[r];
-            if (ATT == ATT_WRITE) {
-                float4 *tb = reinterpret_cast<float4 *>(reinterpret_cast<char *>(a.att + row0) + toff);
-                tb[0] = make_float4(att[0], att[1], att[2], att[3]);
-                tb[1] = make_float4(att[4], att[5], att[6], att[7]);
-            }
-        }
-        float4 *dst = reinterpret_cast<float4 *>(reinterpret_cast<char *>(a.z + row0) + toff);
-        dst[0] = make_float4(u[0], u[1], u[2], u[3]);
-        dst[1] = make_float4(u[4], u[5], u[6], u[7]);
-    }
-}
-
-// The sensitivity pass over a batch work-list, one task (angle, slab, depth
-// chunk) per workgroup.
-template <int ATT, bool VEC>
-__global__ __launch_bounds__(512) void sens_batch(BatchList<BackRotArgs> b)
-{
-    ConstMem<BackRotArgs> *args = as_const(b.args);
-    ConstMem<Task> *tasks = as_const(b.tasks);
-    for (int t = blockIdx.x; t < b.ntasks; t += gridDim.x)
-        sens_body<ATT, VEC>(args[tasks[t].r], tasks[t].x, tasks[t].y, tasks[t].z);
-}
-
-// Sensitivity pass of one angle list with one thread per (angle, slab, bin,
-// pair of axial rows) walking every depth from the detector side.  The blur
-// of a constant projection needs no neighbours (the tap-sum product of
-// sens_body), so there is no LDS and no depth split: the attenuation sum is
-// one running sum per row and mu is sampled once per depth.  Per-depth values
-// are computed as in sens_body with a single depth chunk.  V2: Nz even and an
-// 8-byte aligned mu, so a pair of rows loads as one float2.
+// with the running tap sums C (e_z likewise over 0 <= k+l < Nz); the value is
+// that product times the attenuation factor, written to the rotated-frame
+// bricks like back_rot (ATT_WRITE also stores the factors).  No neighbours
+// are needed, so one thread per (angle, slab, bin, pair of axial rows) walks
+// every depth from the detector side with no LDS and no depth split: the
+// attenuation sum is one running sum per row and mu is sampled once per
+// depth.  V2: Nz even and an 8-byte aligned mu, so a pair of rows loads as
+// one float2.
 constexpr int SL_THREADS = 256;
 
-template <int ATT, bool V2>
-__global__ __launch_bounds__(SL_THREADS) void sens_line(BackRotArgs a)
+template <int ATT, bool V2, class Args>
+__device__ __forceinline__ void sensl_body(const Args &a, int blk, int slab, int al)
 {
     constexpr bool MU = ATT == ATT_SAMPLE || ATT == ATT_WRITE;
     const int N = a.g.N, Nz = a.g.Nz;
-    const int t = blockIdx.x * SL_THREADS + threadIdx.x;
+    const int t = blk * SL_THREADS + threadIdx.x;
     const int jp = t >> 3, rp = t & 7;
     if (jp >= N) return;
-    const int slab = blockIdx.y, al = blockIdx.z;
     const int ang = a.L.idx[al];
     const int k0 = slab * SLAB;
     const int k = k0 + 2 * rp;  // rows k and k + 1; rows past Nz get values the gather never reads
@@ -997,6 +919,22 @@ __global__ __launch_bounds__(SL_THREADS) void sens_line(BackRotArgs a)
         if (MU) sample(max(ip - 6, 0), s2);
         step(ip - 3, s3);
     }
+}
+
+template <int ATT, bool V2>
+__global__ __launch_bounds__(SL_THREADS) void sens_line(BackRotArgs a)
+{
+    sensl_body<ATT, V2>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// The same over a batch work-list: task (member, thread block, slab, angle).
+template <int ATT, bool V2>
+__global__ __launch_bounds__(SL_THREADS) void sensl_batch(BatchList<BackRotArgs> b)
+{
+    ConstMem<BackRotArgs> *args = as_const(b.args);
+    ConstMem<Task> *tasks = as_const(b.tasks);
+    for (int t = blockIdx.x; t < b.ntasks; t += gridDim.x)
+        sensl_body<ATT, V2>(args[tasks[t].r], tasks[t].x, tasks[t].y, tasks[t].z);
 }
 
 #endif  // SPECT_HOST_TU
