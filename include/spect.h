@@ -160,10 +160,10 @@ int spect_sensitivity(const spect_plan *plan, const float *mu, float *sens,
  * work-list of (member, angle, axial slab, depth chunk) tasks.  Each member's
  * state lives in its own region of one workspace (spect_batch_workspace_size
  * bytes, 256-byte aligned, caller-owned; it also holds copies of the images
- * for osem_batch_autotune).  Results equal osem_reconstruct per member up to
- * FP32 rounding: the batch's sensitivity pass sums each ray's attenuation
- * over all depths at once, and schedules 4-7 do the same for the forward
- * depth sums (without attenuation, schedules 0-3 are bitwise equal).
+ * for osem_batch_autotune).  With schedules 0-3 the results equal
+ * osem_reconstruct per member bitwise; schedules 4-7 sum each ray's forward
+ * depth contributions over all depths at once, which changes only the FP32
+ * rounding.
  *
  * Arrays f, mu, g, s_add are host arrays of R device pointers, laid out as in
  * osem_reconstruct; mu must be given for every member if the batch was created
