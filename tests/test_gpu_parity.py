@@ -169,6 +169,22 @@ def test_sensitivity_parity():
     assert e <= BACK_TOL
 
 
+@pytest.mark.parametrize("n,nz,A,with_mu", [(29, 19, 9, True), (16, 8, 6, False), (37, 20, 5, True), (1, 3, 2, True)],
+                         ids=["odd_nz_mu", "no_mu", "ragged_n_mu", "one_column_mu"])
+def test_sensitivity_parity_small(n, nz, A, with_mu):
+    """H^T 1 of a random angle subset against the oracle: odd Nz takes the
+    sensitivity pass's scalar loads, no map its attenuation-free form."""
+    og, plan = both(n, nz, A, angles=list(np.random.default_rng(n).uniform(0, 360, A)))
+    r = np.random.default_rng(13 + n)
+    mu = P.random_mu(og.object_shape, r, 0.2) if with_mu else None
+    idx = sorted(r.choice(A, size=max(1, A // 2), replace=False).tolist())
+    ref = O.back(og, np.ones(og.proj_shape), None if mu is None else mu.astype(np.float64), idx)
+    got = host(plan.sensitivity(None if mu is None else dev(mu), idx))
+    e = rel_l2(got, ref)
+    say(f"  n={n} nz={nz} A={A} mu={with_mu}: sensitivity rel L2 {e:.2e}")
+    assert e <= BACK_TOL
+
+
 def test_deterministic_results():
     """The gather-form back projection and the chunk reduction use a fixed
     summation order: repeated calls give identical bits."""
