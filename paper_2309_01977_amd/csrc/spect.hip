@@ -402,6 +402,9 @@ size_t fwd_smem(int N, int kmc)
 // floats, skewed by 8 floats per group of 8 bins.
 size_t back_smem(int N, int kmc) { return wb_bytes(N, kmc) + sizeof(float) * (size_t)N * (SLAB + 2 * kmc + 2); }
 
+// Sensitivity pass: one angle's running tap sums, N depths of TS floats.
+size_t sens_smem(int N, int TS) { return sizeof(float) * (size_t)N * TS; }
+
 size_t fwd_smem(const spect_plan *p) { return fwd_smem(p->N, p->kmc); }
 size_t back_smem(const spect_plan *p) { return back_smem(p->N, p->kmc); }
 
@@ -595,9 +598,11 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
         else if (att == ATT_NONE) sk = sens_line<ATT_NONE, false>;
         if (!sk) return fail(SPECT_EINVAL, "no sensitivity pass for attenuation mode %d", att);
         b.nchunk = 1;
+        const size_t smem = sens_smem(p->N, p->TS);
+        allow_smem(reinterpret_cast<const void *>(sk), smem);
         ProfScope ps(K_SENS, st);
         hipLaunchKernelGGL(sk, dim3((p->N * (SLAB / 2) + SL_THREADS - 1) / SL_THREADS, t.nslab, L.n),
-                           dim3(SL_THREADS), 0, st, b);
+                           dim3(SL_THREADS), smem, st, b);
     } else {
         BackFn bk = back_kernel(att, p->kmc, vec);
         allow_smem(reinterpret_cast<const void *>(bk), back_smem(p));
@@ -1259,7 +1264,7 @@ int bsrem_subset_step(const spect_plan *plan, float *f, const float *mu, const f
 
 struct BatchLaunch {
     int threads = 0;
-    size_t fsmem = 0, bsmem = 0;
+    size_t fsmem = 0, bsmem = 0, ssmem = 0;
     FwdBatchFn fk = nullptr;
     BackBatchFn bk = nullptr;
     BatchList<FwdArgs> fwd{};
@@ -1529,6 +1534,7 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
             for (int r : groups[gi]) Nmax = std::max(Nmax, b->plans[r]->N);
             l.fsmem = fwd_smem(Nmax, gkmc[gi]);
             l.bsmem = back_smem(Nmax, gkmc[gi]);
+            for (int r : groups[gi]) l.ssmem = std::max(l.ssmem, sens_smem(b->plans[r]->N, b->plans[r]->TS));
             l.fk = fwd_batch_kernel(att, gkmc[gi], vec, persist);
             l.bk = back_batch_kernel(att, gkmc[gi], vec, persist);
             allow_smem(reinterpret_cast<const void *>(l.fk), l.fsmem);
@@ -1545,6 +1551,7 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
             l.sback = {reinterpret_cast<const BackRotArgs *>(d + o.sa), reinterpret_cast<const Task *>(d + o.st),
                        o.ns};
             l.sgat = {reinterpret_cast<const GatherArgs *>(d + o.sg), reinterpret_cast<const Task *>(d + o.gt), o.ng};
+            allow_smem(reinterpret_cast<const void *>(l.sk), l.ssmem);
             if (persist) {
                 int nb = 0;
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(l.fk),
@@ -1558,7 +1565,7 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
                 l.gr = std::max(1, std::min(o.nr, 8 * b->cus));
                 l.gg = std::max(1, std::min(o.ng, 8 * b->cus));
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(l.sk),
-                                                                  SL_THREADS, 0) != hipSuccess || nb < 1)
+                                                                  SL_THREADS, l.ssmem) != hipSuccess || nb < 1)
                     nb = 1;
                 l.gsb = std::max(1, std::min(o.ns, nb * b->cus));
             } else {
@@ -1635,7 +1642,7 @@ int batch_sensitivities(const spect_batch *b, hipStream_t st)
         for (const BatchLaunch &l : b->steps[m]) {
             {
                 ProfScope ps(K_SENS, st);
-                hipLaunchKernelGGL(l.sk, dim3(l.gsb), dim3(SL_THREADS), 0, st, l.sback);
+                hipLaunchKernelGGL(l.sk, dim3(l.gsb), dim3(SL_THREADS), l.ssmem, st, l.sback);
             }
             {
                 ProfScope ps(K_GATHER_B, st);

@@ -821,14 +821,40 @@ __global__ __launch_bounds__(512) void back_batch(BatchList<BackRotArgs> b)
 constexpr int SL_THREADS = 256;
 
 template <int ATT, bool V2, class Args>
+__device__ __forceinline__ void sensl_walk(const Args &a, int jp, int rp, int slab, int al, int ang,
+                                           const float *ctl);
+
+template <int ATT, bool V2, class Args>
 __device__ __forceinline__ void sensl_body(const Args &a, int blk, int slab, int al)
+{
+    const int N = a.g.N;
+    const int t = blk * SL_THREADS + threadIdx.x;
+    const int jp = t >> 3, rp = t & 7;
+    const int ang = a.L.idx[al];
+    // this angle's running tap sums C[i'][m] in LDS: the per-lane lookups of
+    // the in-range sums then use the LDS pipe, not the vector-memory return
+    // path that the mu samples need (dynamic LDS of N * TS floats)
+    extern __shared__ float4 smem[];
+    float *ctl = reinterpret_cast<float *>(smem);
+    const int TS = a.g.TS;
+    {
+        ConstMem<float> *cta = as_const(a.g.ctaps + (size_t)ang * N * TS);
+        for (int i = threadIdx.x; i < N * TS; i += SL_THREADS) ctl[i] = cta[i];
+    }
+    __syncthreads();
+    if (jp < N) sensl_walk<ATT, V2>(a, jp, rp, slab, al, ang, ctl);
+    __syncthreads();  // a batch's next task rewrites the sums
+}
+
+// The depth walk of one (bin, pair of rows) thread of the sensitivity pass;
+// ctl holds the angle's running tap sums, TS per depth.
+template <int ATT, bool V2, class Args>
+__device__ __forceinline__ void sensl_walk(const Args &a, int jp, int rp, int slab, int al, int ang,
+                                           const float *ctl)
 {
     constexpr bool MU = ATT == ATT_SAMPLE || ATT == ATT_WRITE;
     const int N = a.g.N, Nz = a.g.Nz;
-    const int t = blk * SL_THREADS + threadIdx.x;
-    const int jp = t >> 3, rp = t & 7;
-    if (jp >= N) return;
-    const int ang = a.L.idx[al];
+    const int TS = a.g.TS;
     const int k0 = slab * SLAB;
     const int k = k0 + 2 * rp;  // rows k and k + 1; rows past Nz get values the gather never reads
     const bool in0 = k < Nz, in1 = k + 1 < Nz;
@@ -868,7 +894,7 @@ __device__ __forceinline__ void sensl_body(const Args &a, int blk, int slab, int
     // one depth from the samples in sp (loaded one depth earlier)
     auto step = [&](int ip, const Samp &sp) {
         const int K = kd[ip];
-        ConstMem<float> *ct = as_const(a.g.ctaps + ((size_t)ang * N + ip) * a.g.TS);
+        const float *ct = ctl + ip * TS;
         const float g0 = ct[0], cK = ct[K];
         // in-range tap sums across bins and rows; an interior slab (both
         // sides reach K inside the detector) takes 2 C[K] - g0
