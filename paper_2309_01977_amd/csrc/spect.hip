@@ -30,6 +30,14 @@ struct spect_plan {
     int back_slots[4];  // same for the rotated-frame back-projection kernel
     void *dmem;
     DevGeom g;
+    // depth chunking: per boundary set (0: equal depth counts, 1: equal
+    // blur work 6 + K per depth) and angle, the prefix sums wpre[set][a][i]
+    // of the per-depth work over depths < i; the boundaries are uploaded to
+    // g.cbnd; chunk_cost[set][nc] is the largest chunk's work over all
+    // angles, in depths of average work
+    int cap = 1;
+    std::vector<double> wpre[2];       // [A][N + 1]
+    std::vector<double> chunk_cost[2]; // [cap + 1]
 };
 
 namespace {
@@ -148,7 +156,7 @@ int hip_fail(hipError_t e, const char *what)
 }
 
 struct Tuning {
-    int nslab, nchunk, dchunk;
+    int nslab, nchunk;
 };
 
 enum { T_FWD = 1, T_BACK = 2, T_BOTH = 3 };
@@ -161,34 +169,72 @@ enum { T_FWD = 1, T_BACK = 2, T_BOTH = 3 };
 bool samples_mu(int att) { return att == ATT_SAMPLE || att == ATT_WRITE; }
 int att_of(bool mu) { return mu ? ATT_SAMPLE : ATT_NONE; }
 
+// Boundary set of the rotated-frame pass: blur-balanced unless it shares
+// attenuation offsets with the forward (mu sampled).
+int back_set(int att) { return samples_mu(att) ? 0 : 1; }
+
 Tuning tune(const spect_plan *p, int n_list, int att, int which)
 {
     Tuning t;
     t.nslab = (p->Nz + SLAB - 1) / SLAB;
     const long base = (long)std::max(1, n_list) * t.nslab;
-    const int cap = std::max(1, p->N / 8);  // at least 8 depths per chunk
     double best = 1e300;
     t.nchunk = 1;
-    t.dchunk = p->N;
-    for (int nc = 1; nc <= cap; ++nc) {
-        const int D = (p->N + nc - 1) / nc;
-        const int ncc = (p->N + D - 1) / D;
-        if (ncc != nc) continue;
-        const long wgs = base * ncc;
+    for (int nc = 1; nc <= p->cap; ++nc) {
+        // the largest chunk, in depths of average work, of each pass
+        const double Df = p->chunk_cost[0][nc], Db = p->chunk_cost[back_set(att)][nc];
+        const long wgs = base * nc;
         double cost = 0;
-        if (which & T_FWD) cost += (double)((wgs + p->fwd_slots[att] - 1) / p->fwd_slots[att]) * (D + 6);
-        if (which & T_BACK) cost += (double)((wgs + p->back_slots[att] - 1) / p->back_slots[att]) * (D + 6);
-        if (samples_mu(att) && ncc > 1) cost += 2 + D / 4.0;
+        if (which & T_FWD) cost += (double)((wgs + p->fwd_slots[att] - 1) / p->fwd_slots[att]) * (Df + 6);
+        if (which & T_BACK) cost += (double)((wgs + p->back_slots[att] - 1) / p->back_slots[att]) * (Db + 6);
+        if (samples_mu(att) && nc > 1) cost += 2 + ((p->N + nc - 1) / nc) / 4.0;
         if (cost < best - 1e-9) {
             best = cost;
-            t.nchunk = ncc;
-            t.dchunk = D;
+            t.nchunk = nc;
         }
     }
     return t;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Per-depth blur work (fixed part + radius) used to balance depth chunks.
+constexpr double kChunkW0 = 6.0;
+
+// Depth-chunk boundaries of one angle for nc chunks from the prefix sums
+// pre[i] of its per-depth work (depths < i): b[0] = N > b[1] > ... > b[nc] =
+// 0, chunk c covering depths b[c+1] .. b[c]-1 (chunk 0 touches the
+// detector), each chunk's work as close to 1/nc of the angle's as whole
+// depths allow.
+void chunk_bounds(const double *pre, int N, int nc, int *b)
+{
+    const double tot = pre[N];
+    b[0] = N;
+    b[nc] = 0;
+    for (int c = 1; c < nc; ++c) {
+        // work nearer the detector than boundary i is tot - pre[i]
+        const double target = tot * c / nc;
+        int best = b[c - 1] - 1;
+        double bd = 1e300;
+        for (int i = b[c - 1] - 1; i >= nc - c; --i) {
+            const double d = std::fabs((tot - pre[i]) - target);
+            if (d < bd) {
+                bd = d;
+                best = i;
+            }
+        }
+        b[c] = best;
+    }
+}
+
+// Work of chunk c of nc chunks at angle a in boundary set `set`.
+double chunk_work(const spect_plan *p, int set, int nc, int a, int c)
+{
+    const double *pre = p->wpre[set].data() + (size_t)a * (p->N + 1);
+    std::vector<int> b(nc + 1);
+    chunk_bounds(pre, p->N, nc, b.data());
+    return pre[b[c]] - pre[b[c + 1]];
+}
 
 size_t tau_bytes(const spect_plan *p, const Tuning &t, int n_list, int att)
 {
@@ -477,7 +523,7 @@ void launch_tau(const spect_plan *p, const AngleList &L, const Tuning &t, const 
     a.mu = mu;
     a.tau = tau;
     a.nchunk = t.nchunk;
-    a.dchunk = t.dchunk;
+    a.cbset = 0;
     a.vec = vec;
     const int ngrp = (p->Nz + ROWS - 1) / ROWS;
     dim3 grid((p->N * ngrp + 255) / 256, t.nchunk - 1, L.n);
@@ -519,7 +565,7 @@ int run_forward(const spect_plan *p, const float *f, const float *mu, int att, c
     a.part = part;
     a.nslab = t.nslab;
     a.nchunk = t.nchunk;
-    a.dchunk = t.dchunk;
+    a.cbset = 0;
     a.vec = vec;
     KernelFn fk = fwd_kernel(att, p->kmc, vec);
     allow_smem(reinterpret_cast<const void *>(fk), fwd_smem(p));
@@ -586,7 +632,7 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
     b.z = z;
     b.nslab = t.nslab;
     b.nchunk = t.nchunk;
-    b.dchunk = t.dchunk;
+    b.cbset = back_set(att);
     b.vec = vec;
     if (ones) {
         // constant projection: the blur reduces to in-range tap sums, and the
@@ -598,6 +644,7 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
         else if (att == ATT_NONE) sk = sens_line<ATT_NONE, false>;
         if (!sk) return fail(SPECT_EINVAL, "no sensitivity pass for attenuation mode %d", att);
         b.nchunk = 1;
+        b.cbset = 0;
         const size_t smem = sens_smem(p->N, p->TS);
         allow_smem(reinterpret_cast<const void *>(sk), smem);
         ProfScope ps(K_SENS, st);
@@ -796,9 +843,33 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
             }
         }
     }
+    // depth chunking: per-depth work 6 + K, boundaries per chunk count and
+    // angle (at least 8 depths per chunk on average)
+    p->cap = std::max(1, N / 8);
+    const int cap = p->cap;
+    std::vector<int> cb((size_t)2 * cap * A * (cap + 1), 0);
+    for (int set = 0; set < 2; ++set) {
+        std::vector<double> &wp = p->wpre[set];
+        wp.assign((size_t)A * (N + 1), 0.0);
+        for (int i = 0; i < A; ++i)
+            for (int ip = 0; ip < N; ++ip)
+                wp[(size_t)i * (N + 1) + ip + 1] =
+                    wp[(size_t)i * (N + 1) + ip] + (set == 0 ? 1.0 : kChunkW0 + kd[(size_t)i * N + ip]);
+        p->chunk_cost[set].assign(cap + 1, 0.0);
+        for (int nc = 1; nc <= cap; ++nc)
+            for (int i = 0; i < A; ++i) {
+                int *b = cb.data() + (((size_t)set * cap + nc - 1) * A + i) * (cap + 1);
+                const double *pre = wp.data() + (size_t)i * (N + 1);
+                chunk_bounds(pre, N, nc, b);
+                const double avg = pre[N] / N;
+                for (int c = 0; c < nc; ++c)
+                    p->chunk_cost[set][nc] = std::max(p->chunk_cost[set][nc], (pre[b[c]] - pre[b[c + 1]]) / avg);
+            }
+    }
     const size_t b_cs = align256(sizeof(float2) * A), b_xy = align256(sizeof(float2) * (size_t)A * N);
     const size_t b_kd = align256(sizeof(int) * (size_t)A * N), b_tp = align256(sizeof(float) * taps.size());
-    hipError_t e = hipMalloc(&p->dmem, b_cs + b_xy + b_kd + 2 * b_tp);
+    const size_t b_cb = align256(sizeof(int) * cb.size());
+    hipError_t e = hipMalloc(&p->dmem, b_cs + b_xy + b_kd + 2 * b_tp + b_cb);
     if (e != hipSuccess) {
         delete p;
         return fail(SPECT_ENOMEM, "hipMalloc of plan tables failed: %s", hipGetErrorString(e));
@@ -812,6 +883,8 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
     if (e == hipSuccess)
         e = hipMemcpy(base + b_cs + b_xy + b_kd + b_tp, ctaps.data(), sizeof(float) * ctaps.size(),
                       hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(base + b_cs + b_xy + b_kd + 2 * b_tp, cb.data(), sizeof(int) * cb.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(p->dmem);
         delete p;
@@ -822,6 +895,8 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
     p->g.kdep = reinterpret_cast<const int *>(base + b_cs + b_xy);
     p->g.taps = reinterpret_cast<const float *>(base + b_cs + b_xy + b_kd);
     p->g.ctaps = reinterpret_cast<const float *>(base + b_cs + b_xy + b_kd + b_tp);
+    p->g.cbnd = reinterpret_cast<const int *>(base + b_cs + b_xy + b_kd + 2 * b_tp);
+    p->g.cap = cap;
     p->g.N = N;
     p->g.Nz = g.nz;
     p->g.A = A;
@@ -1407,7 +1482,7 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
                 a.part = scr;
                 a.nslab = t.nslab;
                 a.nchunk = t.nchunk;
-                a.dchunk = t.dchunk;
+                a.cbset = 0;
                 a.vec = vec;
                 fa.push_back(a);
                 ReduceArgs rr{};
@@ -1432,7 +1507,7 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
                 bb.z = scr;
                 bb.nslab = t.nslab;
                 bb.nchunk = t.nchunk;
-                bb.dchunk = t.dchunk;
+                bb.cbset = 1;
                 bb.vec = vec;
                 ba.push_back(bb);
                 GatherArgs gg{};
@@ -1450,7 +1525,7 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
                 sb.ones = 1;
                 sb.mu = b->mu ? P.mu[r] : nullptr;
                 sb.nchunk = 1;
-                sb.dchunk = p->N;
+                sb.cbset = 0;
                 sa.push_back(sb);
                 GatherArgs sgg = gg;
                 sgg.mode = 0;
@@ -1463,15 +1538,16 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
                         for (int k = 0; k < sblk; ++k)
                             stk.push_back({(long)p->N * p->N, Task{(int)li, k, sl, al}});
                 const int li_ = (int)li;
-                const long cost = (long)t.dchunk * p->N;  // depths x bins of one task
                 for (int al = 0; al < L.n; ++al)
-                    for (int sl = 0; sl < t.nslab; ++sl)
-                        for (int c = 0; c < t.nchunk; ++c) {
-                            const int d = std::min(t.dchunk, p->N - c * t.dchunk);
-                            ft.push_back({(long)d * p->N, Task{li_, sl, c, al}});
-                            bt.push_back({(long)d * p->N, Task{li_, sl, c, al}});
+                    for (int c = 0; c < t.nchunk; ++c) {
+                        // blur work of the chunk's depths x bins
+                        const long fc = (long)(chunk_work(p, 0, t.nchunk, L.idx[al], c) * p->N);
+                        const long bc = (long)(chunk_work(p, 1, t.nchunk, L.idx[al], c) * p->N);
+                        for (int sl = 0; sl < t.nslab; ++sl) {
+                            ft.push_back({fc, Task{li_, sl, c, al}});
+                            bt.push_back({bc, Task{li_, sl, c, al}});
                         }
-                (void)cost;
+                    }
                 const int blocks = (p->N * p->Nz + 255) / 256;
                 for (int al = 0; al < L.n; ++al)
                     for (int k = 0; k < blocks; ++k) rt.push_back(Task{li_, k, 0, al});
@@ -1742,7 +1818,7 @@ int spect_batch_create(const spect_plan *const *plans, int32_t n_members, int32_
             const int nl = (int)list.size();
             const Tuning t = tune(p, nl, att, T_BOTH);
             ts.push_back(t);
-            t1.push_back(Tuning{t.nslab, 1, p->N});
+            t1.push_back(Tuning{t.nslab, 1});
             tabs.push_back(rel);
             if (b->mu) rel += table_bytes(p, nl);
             scr = std::max(scr, batch_part_bytes(p, t, nl, b->kmc_max));

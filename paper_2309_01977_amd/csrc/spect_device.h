@@ -97,9 +97,25 @@ struct DevGeom {
     const int *kdep;    // [A][N] blur radius per depth
     const float *taps;  // [A][N][TS] one-sided taps g[0..K]
     const float *ctaps; // [A][N][TS] their running sums C[m] = g[0] + ... + g[m]
+    const int *cbnd;    // [2][cap][A][cap + 1] depth-chunk boundaries (see chunk_range)
     int N, Nz, A, TS;
+    int cap;            // largest depth-chunk count
     float tau_scale;    // dx * log2(e): exp(-tau) = exp2(-tau_scale * (sum mu))
 };
+
+// Depths of chunk `chunk` of a launch split into nchunk chunks, for angle
+// ang: ihi down to ilo (chunk 0 touches the detector).  The boundaries come
+// from the plan: set 0 gives the chunks equal depth counts (the forward,
+// whose time hardly depends on the blur radius, and the passes that share
+// attenuation offsets), set 1 balances the blur work of the rotated-frame
+// pass (about 6 + K per depth).
+template <class G>
+__device__ __forceinline__ void chunk_range(const G &g, int set, int nchunk, int ang, int chunk, int &ihi, int &ilo)
+{
+    ConstMem<int> *cb = as_const(g.cbnd + (((size_t)set * g.cap + nchunk - 1) * g.A + ang) * (g.cap + 1));
+    ihi = cb[chunk] - 1;
+    ilo = cb[chunk + 1];
+}
 
 // --------------------------------------------------------------- helpers --
 
@@ -387,15 +403,14 @@ struct TauArgs {
     AngleList L;
     const float *mu;
     float *tau;      // [L][nchunk][N][Nz]: sum of mu samples over the depths of chunk c
-    int nchunk, dchunk;
+    int nchunk, cbset;
     int vec;
 };
 
 // One thread per (angle, chunk, bin, 8 axial rows): sum the attenuation
-// samples of the chunk's depths.  Chunk c covers depths
-// [N - (c+1) D, N - c D); chunk 0 touches the detector.  A chunk's starting
-// attenuation is the sum of the partial sums of the chunks nearer the
-// detector (the last chunk's own sum is never needed).
+// samples of the chunk's depths (chunk_range; chunk 0 touches the detector).
+// A chunk's starting attenuation is the sum of the partial sums of the
+// chunks nearer the detector (the last chunk's own sum is never needed).
 template <bool VEC>
 __global__ __launch_bounds__(256) void tau_prepass(TauArgs a)
 {
@@ -411,8 +426,8 @@ __global__ __launch_bounds__(256) void tau_prepass(TauArgs a)
     float S[ROWS];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) S[r] = 0.f;
-    const int ihi = N - ch * a.dchunk - 1;
-    const int ilo = max(0, N - (ch + 1) * a.dchunk);
+    int ihi, ilo;
+    chunk_range(a.g, a.cbset, a.nchunk, ang, ch, ihi, ilo);
     const RowGeom rg = row_geom(kb, Nz);
 #pragma unroll 2
     for (int ip = ihi; ip >= ilo; --ip) {
@@ -452,7 +467,7 @@ struct FwdArgs {
     const float *tau;   // chunk offsets or nullptr when nchunk == 1
     const float *att;   // ATT_READ: attenuation table [L][nslab][N][N][16]
     float *part;        // [L][nslab][nchunk][N][SLAB + 2 KMC]
-    int nslab, nchunk, dchunk;
+    int nslab, nchunk, cbset;
     int vec;
 };
 
@@ -482,8 +497,8 @@ __device__ __forceinline__ void fwd_body(const Args &a, int slab, int chunk, int
 #pragma unroll
     for (int t = 0; t < ROWS + 2 * KMC; ++t) acc[t] = 0.f;
 
-    const int ihi = N - chunk * a.dchunk - 1;
-    const int ilo = max(0, N - (chunk + 1) * a.dchunk);
+    int ihi, ilo;
+    chunk_range(a.g, a.cbset, a.nchunk, ang, chunk, ihi, ilo);
     ConstMem<int> *kd = as_const(a.g.kdep + (size_t)ang * N);
     const RowGeom rg = row_geom(kb, Nz);
     // attenuation table: uniform base of this (angle, slab) + per-thread offset
@@ -671,7 +686,7 @@ struct BackRotArgs {
     const float *tau;
     float *att;         // ATT_WRITE / ATT_READ: attenuation table [L][nslab][N][N][16]
     float *z;           // [L][nslab][N][N][SLAB] rotated-frame values
-    int nslab, nchunk, dchunk;
+    int nslab, nchunk, cbset;
     int vec;
 };
 
@@ -714,8 +729,8 @@ __device__ __forceinline__ void back_body(const Args &a, int slab, int chunk, in
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) S[r] = 0.f;
     if (MU && chunk > 0 && active) chunk_start(a.tau, al, a.nchunk, chunk, N, Nz, jp, kb, S);
-    const int ihi = N - chunk * a.dchunk - 1;
-    const int ilo = max(0, N - (chunk + 1) * a.dchunk);
+    int ihi, ilo;
+    chunk_range(a.g, a.cbset, a.nchunk, ang, chunk, ihi, ilo);
     ConstMem<int> *kd = as_const(a.g.kdep + (size_t)ang * N);
     const RowGeom rg = row_geom(kb, Nz);
     // table and rotated-frame bricks: uniform base of this (angle, slab) + per-thread offset
