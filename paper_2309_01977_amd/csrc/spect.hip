@@ -31,7 +31,7 @@ struct spect_plan {
     void *dmem;
     DevGeom g;
     // depth chunking: per boundary set (0: equal depth counts, 1: equal
-    // blur work 6 + K per depth) and angle, the prefix sums wpre[set][a][i]
+    // blur work 10 + K per depth) and angle, the prefix sums wpre[set][a][i]
     // of the per-depth work over depths < i; the boundaries are uploaded to
     // g.cbnd; chunk_cost[set][nc] is the largest chunk's work over all
     // angles, in depths of average work
@@ -199,7 +199,7 @@ Tuning tune(const spect_plan *p, int n_list, int att, int which)
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Per-depth blur work (fixed part + radius) used to balance depth chunks.
-constexpr double kChunkW0 = 6.0;
+constexpr double kChunkW0 = 10.0;
 
 // Depth-chunk boundaries of one angle for nc chunks from the prefix sums
 // pre[i] of its per-depth work (depths < i): b[0] = N > b[1] > ... > b[nc] =
@@ -843,7 +843,7 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
             }
         }
     }
-    // depth chunking: per-depth work 6 + K, boundaries per chunk count and
+    // depth chunking: per-depth work 10 + K, boundaries per chunk count and
     // angle (at least 8 depths per chunk on average)
     p->cap = std::max(1, N / 8);
     const int cap = p->cap;

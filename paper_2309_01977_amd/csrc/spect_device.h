@@ -108,7 +108,7 @@ struct DevGeom {
 // from the plan: set 0 gives the chunks equal depth counts (the forward,
 // whose time hardly depends on the blur radius, and the passes that share
 // attenuation offsets), set 1 balances the blur work of the rotated-frame
-// pass (about 6 + K per depth).
+// pass (about 10 + K per depth).
 template <class G>
 __device__ __forceinline__ void chunk_range(const G &g, int set, int nchunk, int ang, int chunk, int &ihi, int &ilo)
 {
