@@ -166,6 +166,39 @@ def test_p6_point_source_blur_width_and_position(depth):
     assert abs(p.sum() - 1) < 1e-12
 
 
+def test_p6_each_angle_blurs_with_its_own_detector_distance():
+    """A point source seen at 0, 90, 180 and 270 degrees (exact permutations,
+    R3) with a different detector radius per angle: projection n is the
+    sampled Gaussian of sigma = a d_n + b, d_n = max(0, R_n - (i'_n - c) dx),
+    centred on the point's rotated (bin, slice), cut at the detector edge
+    (zero padding, R7).  The 2 cm radius puts the point beyond the detector
+    face at 0 degrees (d clamped to 0, R6); at 270 degrees the kernel runs
+    past the last bin."""
+    n, nz, dx, a, b = 24, 21, 0.48, 0.03, 0.1
+    radii = [2.0, 15.0, 22.0, 30.0]
+    g = O.Geometry(n, nz, 4, dx, a, b, 4.0, [0.0, 90.0, 180.0, 270.0], radii)
+    x0, y0, k0 = 16, 12, 10
+    f = np.zeros((n, n, nz))
+    f[x0, y0, k0] = 1.0
+    p = O.forward(g, f)
+    c = 0.5 * (n - 1)
+    # rotated (depth, bin) of object voxel (x0, y0): inverse of the R3 map
+    hits = [(x0, y0), (y0, n - 1 - x0), (n - 1 - x0, n - 1 - y0), (n - 1 - y0, x0)]
+    widths = []
+    for m, ((ip, jp), R) in enumerate(zip(hits, radii)):
+        d = max(0.0, R - (ip - c) * dx)
+        s = (a * d + b) / dx
+        K = int(np.ceil(4 * s - 1e-9))
+        k1 = _gauss_taps(s, K)
+        big = np.zeros((n + 2 * K, nz + 2 * K))
+        big[jp:jp + 2 * K + 1, k0:k0 + 2 * K + 1] = np.outer(k1, k1)
+        expect = big[K:K + n, K:K + nz]
+        np.testing.assert_allclose(p[m], expect, rtol=1e-12, atol=1e-15, err_msg=f"angle {m}")
+        widths.append(K)
+    assert widths[0] == 1 and jp + widths[3] > n - 1  # the clamp and the edge are exercised
+    assert p[3].sum() < 1 - 1e-5  # the tail past the last bin is lost
+
+
 def test_p6_second_moment_matches_sigma_squared():
     """Second moment of the discrete kernel equals sigma(d)^2 within 0.2 %
     where sigma is at least one pixel (closed form of the continuous
