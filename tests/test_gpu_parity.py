@@ -317,6 +317,34 @@ def test_noncircular_orbit_parity():
     assert e <= OSEM_TOL
 
 
+def test_osem_with_additive_term_and_empty_rays():
+    """The fused ratio g / (H f + s) with a non-zero additive term s, from a
+    start image whose lowest axial rows are zero so that those rows of every
+    projection have H f = 0; s is 0 there too, so the ratio takes the R12
+    branch (0 where H f + s <= 0).  Whole reconstruction and the stepwise
+    driver against the oracle's OSEM with the same s and start image."""
+    n, nz, A, M = 40, 24, 12, 4
+    og, plan = both(n, nz, A, angles=list(np.random.default_rng(3).uniform(0, 360, A)))
+    r = np.random.default_rng(21)
+    mu = P.random_mu(og.object_shape, r, 0.12)
+    mu64 = mu.astype(np.float64)
+    f_true = P.random_object(og.object_shape, r)
+    s_add = (0.05 * P.random_object(og.proj_shape, r)).astype(np.float32)
+    s_add[:, :, :6] = 0.0
+    g = P.poisson_counts(O.forward(og, f_true.astype(np.float64), mu64) + s_add, 3e5, r)
+    f0 = (0.5 + P.random_object(og.object_shape, r)).astype(np.float32)
+    f0[:, :, :14] = 0.0
+    hf0 = O.forward(og, f0.astype(np.float64), mu64)
+    assert not hf0[:, :, :6].any() and hf0[:, :, 6:].min() >= 0  # the R12 branch is reached
+    ref = O.osem(og, g.astype(np.float64), mu64, 2, M, s=s_add.astype(np.float64), f0=f0.astype(np.float64))
+    got = host(S.osem(plan, dev(g), 2, M, dev(mu), s_add=dev(s_add), f0=dev(f0)))
+    got_s = host(S.osem_steps(plan, dev(g), 2, M, dev(mu), s_add=dev(s_add), f0=dev(f0)))
+    e, e_s = rel_l2(got, ref), rel_l2(got_s, ref)
+    say(f"  OSEM with s: whole {e:.2e}, stepwise {e_s:.2e}")
+    assert e <= OSEM_TOL and e_s <= OSEM_TOL
+    assert np.isfinite(got).all() and not got[:, :, :14].any()
+
+
 def test_kernel_timer_counts_launches():
     og, plan = both(32, 16, 8)
     r = np.random.default_rng(15)
