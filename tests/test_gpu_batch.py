@@ -93,6 +93,31 @@ def test_batch_members_equal_single_reconstructions_and_the_oracle(with_mu):
         assert e1 == 0.0 and e2 <= OSEM_TOL
 
 
+def test_batch_members_with_additive_terms():
+    """Members with and without an additive term s in one batch: each equals
+    its own osem_reconstruct with the same s bitwise, graph-replayed and
+    eager, and the oracle's OSEM with that s within the OSEM bar."""
+    M, I = 4, 2
+    mem = members(SHAPES, True, 74)
+    r = np.random.default_rng(75)
+    ss = [(0.1 * P.random_object(og.proj_shape, r)).astype(np.float32) if k % 2 == 0 else None
+          for k, (og, _, _, _) in enumerate(mem)]
+    batch = S.Batch([m[1] for m in mem], M, True)
+    for eager in (False, True):
+        fs = [torch.ones(m[1].object_shape, device="cuda") for m in mem]
+        batch.reconstruct(fs, [dev(m[2]) for m in mem], [dev(m[3]) for m in mem], I,
+                          s_adds=[None if s is None else dev(s) for s in ss], eager=eager)
+        for (og, plan, mu, g), s, f in zip(mem, ss, fs):
+            fb = host(f)
+            single = host(S.osem(plan, dev(g), I, M, dev(mu), s_add=None if s is None else dev(s)))
+            ref = O.osem(og, g.astype(np.float64), mu.astype(np.float64), I, M,
+                         s=None if s is None else s.astype(np.float64))
+            e1, e2 = rel_l2(fb, single), rel_l2(fb, ref)
+            say(f"  eager={eager} {og.object_shape} x {og.n_angles} s={s is not None}: "
+                f"batch vs single {e1:.2e}, vs oracle {e2:.2e}")
+            assert e1 == 0.0 and e2 <= OSEM_TOL
+
+
 def test_every_schedule_and_the_eager_path_give_the_same_images():
     M, I = 4, 2
     mem = members(SHAPES, True, 71)
