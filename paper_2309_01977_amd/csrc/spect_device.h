@@ -175,17 +175,74 @@ __device__ __forceinline__ const T &at_byte(const float *base, uint32_t off)
 }
 
 // Raw corner values of ROWS axial rows starting at kb: v[corner][row] for the
-// corners (x0,y0), (x0+1,y0), (x0,y0+1), (x0+1,y0+1).  Every load is issued
-// unconditionally (rows past Nz read a clamped, valid address and are zeroed
-// when combined), so all of them are in flight together.  Vector path:
+// corners (x0,y0), (x0+1,y0), (x0,y0+1), (x0+1,y0+1).  Rows past Nz read a
+// clamped, valid address and are zeroed when combined.  Vector path:
 // Nz % 4 == 0 and a 16-byte aligned volume.
 struct Raw {
     float v[4][ROWS];
 };
 
+// A corner whose bilinear weight is 0 (outside the grid) is not loaded and
+// reads as 0, so the samples of a rotated grid that fall outside the object
+// (up to 17 % of them, at 45 degrees) cost no gathered loads; the loads of
+// the other corners are all issued before any is used.
 template <bool VEC>
 __device__ __forceinline__ void load_raw(const float *__restrict__ vol, const Corners &c, const RowGeom &rg, int kb,
                                          int Nz, Raw &r)
+{
+    const uint32_t o[4] = {c.b00, c.b10, c.b01, c.b11};
+    const float wt[4] = {c.w00, c.w10, c.w01, c.w11};
+    if constexpr (VEC) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float4 t0 = make_float4(0.f, 0.f, 0.f, 0.f), t1 = t0;
+            if (wt[j] != 0.f) {
+                t0 = at_byte<float4>(vol, o[j] + rg.dk0);
+                t1 = at_byte<float4>(vol, o[j] + rg.dk1);
+            }
+            r.v[j][0] = t0.x;
+            r.v[j][1] = t0.y;
+            r.v[j][2] = t0.z;
+            r.v[j][3] = t0.w;
+            r.v[j][4] = t1.x;
+            r.v[j][5] = t1.y;
+            r.v[j][6] = t1.z;
+            r.v[j][7] = t1.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+            for (int rr = 0; rr < ROWS; ++rr) r.v[j][rr] = 0.f;
+            if (wt[j] != 0.f) {
+#pragma unroll
+                for (int rr = 0; rr < ROWS; ++rr)
+                    r.v[j][rr] = at_byte<float>(vol, o[j] + 4u * (uint32_t)min(kb + rr, Nz - 1));
+            }
+        }
+    }
+}
+
+// Bilinear combination of raw corner values; rows >= Nz give 0.
+__device__ __forceinline__ void combine(const Raw &r, const Corners &c, int kb, int Nz, float (&v)[ROWS],
+                                        bool full = false)
+{
+#pragma unroll
+    for (int rr = 0; rr < ROWS; ++rr)
+        v[rr] = fmaf(c.w11, r.v[3][rr], fmaf(c.w01, r.v[2][rr], fmaf(c.w10, r.v[1][rr], c.w00 * r.v[0][rr])));
+    if (!full) {
+#pragma unroll
+        for (int rr = 0; rr < ROWS; ++rr)
+            if (kb + rr >= Nz) v[rr] = 0.f;
+    }
+}
+
+// Every corner loaded unconditionally (the attenuation pre-pass, which keeps
+// two depths of loads in flight: masking its loads would raise it from 60 to
+// 97 VGPRs).
+template <bool VEC>
+__device__ __forceinline__ void load_raw_all(const float *__restrict__ vol, const Corners &c, const RowGeom &rg,
+                                             int kb, int Nz, Raw &r)
 {
     const uint32_t o[4] = {c.b00, c.b10, c.b01, c.b11};
     if constexpr (VEC) {
@@ -212,26 +269,12 @@ __device__ __forceinline__ void load_raw(const float *__restrict__ vol, const Co
     }
 }
 
-// Bilinear combination of raw corner values; rows >= Nz give 0.
-__device__ __forceinline__ void combine(const Raw &r, const Corners &c, int kb, int Nz, float (&v)[ROWS],
-                                        bool full = false)
-{
-#pragma unroll
-    for (int rr = 0; rr < ROWS; ++rr)
-        v[rr] = fmaf(c.w11, r.v[3][rr], fmaf(c.w01, r.v[2][rr], fmaf(c.w10, r.v[1][rr], c.w00 * r.v[0][rr])));
-    if (!full) {
-#pragma unroll
-        for (int rr = 0; rr < ROWS; ++rr)
-            if (kb + rr >= Nz) v[rr] = 0.f;
-    }
-}
-
 template <bool VEC>
 __device__ __forceinline__ void sample_rows(const float *__restrict__ vol, const Corners &c, const RowGeom &rg,
                                             int kb, int Nz, float (&v)[ROWS])
 {
     Raw r;
-    load_raw<VEC>(vol, c, rg, kb, Nz, r);
+    load_raw_all<VEC>(vol, c, rg, kb, Nz, r);
     combine(r, c, kb, Nz, v);
 }
 
