@@ -317,6 +317,33 @@ def test_noncircular_orbit_parity():
     assert e <= OSEM_TOL
 
 
+def test_largest_grid_and_blur_radius():
+    """At the limits the plan accepts: N = 256 (512-thread workgroups) and a
+    blur radius of 32 pixels at the far depths (the widest blur class, whose
+    rotated-frame pass needs more than 64 KB of LDS), with a slab tail
+    (Nz = 20): projections, back projection, sensitivity and the table calls
+    against the oracle."""
+    n, nz, A = 256, 20, 3
+    og, plan = both(n, nz, A, angles=[0.0, 33.0, 250.0])
+    assert len(O.psf_taps(og, 0)) - 1 == 32
+    r = np.random.default_rng(31)
+    f = P.random_object(og.object_shape, r)
+    mu = P.random_mu(og.object_shape, r, 0.05)
+    mu64 = mu.astype(np.float64)
+    check_forward(og, plan, f, mu, label="n=256, K=32")
+    y = P.random_object(og.proj_shape, r)
+    e_b = rel_l2(host(plan.back(dev(y), dev(mu))), O.back(og, y.astype(np.float64), mu64))
+    idx = [0, 2]
+    sens_t, table = plan.sensitivity_table(dev(mu), idx)
+    e_s = rel_l2(host(sens_t), O.back(og, np.ones(og.proj_shape), mu64, idx))
+    fp = host(plan.forward_table(dev(f), table, idx))
+    ref_f = O.forward(og, f.astype(np.float64), mu64, idx)
+    worst = max(rel_l2(fp[i], ref_f[i]) for i in idx)
+    e_bt = rel_l2(host(plan.back_table(dev(y), table, idx)), O.back(og, y.astype(np.float64), mu64, idx))
+    say(f"  back {e_b:.2e}; table calls: sens {e_s:.2e}, forward worst {worst:.2e}, back {e_bt:.2e}")
+    assert e_b <= BACK_TOL and e_s <= BACK_TOL and worst <= FWD_TOL and e_bt <= BACK_TOL
+
+
 def test_osem_with_additive_term_and_empty_rays():
     """The fused ratio g / (H f + s) with a non-zero additive term s, from a
     start image whose lowest axial rows are zero so that those rows of every
