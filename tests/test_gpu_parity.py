@@ -89,6 +89,8 @@ SMALL = [
     (1, 3, 2, False, (0.0, 0.0), False),      # one voxel column
     (48, 40, 3, True, (0.06, 0.2), True),     # wider blur class
     (64, 64, 10, True, (0.03, 0.1), False),
+    (29, 1, 4, True, (0.03, 0.1), True),      # one slice: the axial blur keeps only its centre tap
+    (16, 16, 3, True, (0.03, 0.1), True),     # exactly one full slab
 ]
 
 
