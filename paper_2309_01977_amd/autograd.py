@@ -46,12 +46,28 @@ def _member(a: Optional[torch.Tensor], b: int, batched: bool, rank: int):
     return a
 
 
-def _fwd(plan: Plan, x, mu, table, idx):
-    return plan.forward(x, mu, idx) if table is None else plan.forward_table(x, table, idx)
+def _fwd(plan: Plan, x, mu, table, idx, out):
+    return plan.forward(x, mu, idx, out) if table is None else plan.forward_table(x, table, idx, out)
 
 
-def _back(plan: Plan, y, mu, table, idx):
-    return plan.back(y, mu, idx) if table is None else plan.back_table(y, table, idx)
+def _back(plan: Plan, y, mu, table, idx, out):
+    return plan.back(y, mu, idx, out) if table is None else plan.back_table(y, table, idx, out)
+
+
+def _apply(plan: Plan, x, mu, table, idx, adjoint: bool):
+    """H x (rows idx, zeros elsewhere) or H^T x, member by member straight into
+    one output tensor (no per-member results to stack)."""
+    batched = x.dim() == 4
+    x = x.contiguous()
+    lead = (x.shape[0],) if batched else ()
+    if adjoint:
+        out = torch.empty(lead + plan.object_shape, dtype=torch.float32, device=x.device)
+    else:
+        out = torch.zeros(lead + plan.proj_shape, dtype=torch.float32, device=x.device)
+    op = _back if adjoint else _fwd
+    for b, xb in enumerate(_members(x, 3)):
+        op(plan, xb, _member(mu, b, batched, 3), _member(table, b, batched, 1), idx, out[b] if batched else out)
+    return out
 
 
 class _Pair(torch.autograd.Function):
@@ -61,19 +77,11 @@ class _Pair(torch.autograd.Function):
     def forward(ctx, x, plan: Plan, mu, table, idx, adjoint: bool):
         ctx.plan, ctx.idx, ctx.adjoint = plan, idx, adjoint
         ctx.mu, ctx.table = mu, table
-        batched = x.dim() == 4
-        op = _back if adjoint else _fwd
-        outs = [op(plan, xb, _member(mu, b, batched, 3), _member(table, b, batched, 1), idx)
-                for b, xb in enumerate(_members(x.contiguous(), 3))]
-        return torch.stack(outs) if batched else outs[0]
+        return _apply(plan, x, mu, table, idx, adjoint)
 
     @staticmethod
     def backward(ctx, gy):
-        batched = gy.dim() == 4
-        op = _fwd if ctx.adjoint else _back
-        outs = [op(ctx.plan, gb, _member(ctx.mu, b, batched, 3), _member(ctx.table, b, batched, 1), ctx.idx)
-                for b, gb in enumerate(_members(gy.contiguous(), 3))]
-        return (torch.stack(outs) if batched else outs[0]), None, None, None, None, None
+        return _apply(ctx.plan, gy, ctx.mu, ctx.table, ctx.idx, not ctx.adjoint), None, None, None, None, None
 
 
 def project(f: torch.Tensor, plan: Plan, mu: Optional[torch.Tensor] = None,
@@ -96,18 +104,72 @@ def _safe_div(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
     return torch.where(pos, a / torch.where(pos, b, torch.ones_like(b)), torch.zeros_like(a))
 
 
+def _rows_apply(plan: Plan, x, mu, table, idx, rows, adjoint: bool):
+    """adjoint=False: the rows idx of H x as a compact (..., len(idx), N, Nz)
+    tensor; adjoint=True: H^T of such compact rows.  The full projection
+    buffer the calls take is left unfilled outside the rows idx: the forward
+    writes and the back projection reads no other row."""
+    batched = x.dim() == 4
+    x = x.contiguous()
+    lead = (x.shape[0],) if batched else ()
+    full = torch.empty(lead + plan.proj_shape, dtype=torch.float32, device=x.device)
+    if adjoint:
+        full.index_copy_(-3, rows, x)
+        out = torch.empty(lead + plan.object_shape, dtype=torch.float32, device=x.device)
+        for b in range(x.shape[0] if batched else 1):
+            _back(plan, full[b] if batched else full, _member(mu, b, batched, 3), _member(table, b, batched, 1),
+                  idx, out[b] if batched else out)
+        return out
+    for b, xb in enumerate(_members(x, 3)):
+        _fwd(plan, xb, _member(mu, b, batched, 3), _member(table, b, batched, 1), idx,
+             full[b] if batched else full)
+    return full.index_select(-3, rows)
+
+
+class _Rows(torch.autograd.Function):
+    """Compact-row form of the pair (see _rows_apply); the backward applies
+    the other operator."""
+
+    @staticmethod
+    def forward(ctx, x, plan: Plan, mu, table, idx, rows, adjoint: bool):
+        ctx.args = (plan, mu, table, idx, rows, adjoint)
+        return _rows_apply(plan, x, mu, table, idx, rows, adjoint)
+
+    @staticmethod
+    def backward(ctx, gy):
+        plan, mu, table, idx, rows, adjoint = ctx.args
+        return _rows_apply(plan, gy, mu, table, idx, rows, not adjoint), None, None, None, None, None, None
+
+
+class _Subset:
+    """What one subiteration needs that does not depend on the image: the
+    subset's rows, the measured (and additive) rows, where sens_m > 0 and
+    sens_m with 1 where it is 0."""
+
+    def __init__(self, g, sens_m, idx, s_add, device):
+        self.idx = list(idx)
+        self.rows = torch.as_tensor(self.idx, dtype=torch.long, device=device)
+        self.g = g.index_select(-3, self.rows)
+        self.s = None if s_add is None else s_add.index_select(-3, self.rows)
+        self.pos = sens_m > 0
+        self.sens = torch.where(self.pos, sens_m, torch.ones_like(sens_m))
+
+
+def _osem_step(f, sub: _Subset, plan: Plan, mu, table):
+    gh = _Rows.apply(f, plan, mu, table, sub.idx, sub.rows, False)
+    if sub.s is not None:
+        gh = gh + sub.s
+    b = _Rows.apply(_safe_div(sub.g, gh), plan, mu, table, sub.idx, sub.rows, True)
+    return torch.where(sub.pos, f * b / sub.sens, f)
+
+
 def osem_update(f: torch.Tensor, g: torch.Tensor, sens_m: torch.Tensor, plan: Plan, idx,
                 mu: Optional[torch.Tensor] = None, s_add: Optional[torch.Tensor] = None,
                 table: Optional[torch.Tensor] = None) -> torch.Tensor:
     """One OSEM subiteration on the angles idx, differentiable in f:
-    f * H_m^T(g / (H_m f + s)) / sens_m (f where sens_m = 0)."""
-    ghat = project(f, plan, mu, idx, table)
-    if s_add is not None:
-        ghat = ghat + s_add
-    q = _safe_div(g, ghat)
-    b = back_project(q, plan, mu, idx, table)
-    pos = sens_m > 0
-    return torch.where(pos, f * b / torch.where(pos, sens_m, torch.ones_like(sens_m)), f)
+    f * H_m^T(g / (H_m f + s)) / sens_m (f where sens_m = 0).  The ratio is
+    formed on the rows idx only: H_m^T reads no other row."""
+    return _osem_step(f, _Subset(g, sens_m, idx, s_add, f.device), plan, mu, table)
 
 
 def subset_sensitivities(plan: Plan, n_subsets: int, mu: Optional[torch.Tensor] = None,
@@ -148,13 +210,14 @@ def unrolled_osem(plan: Plan, g: torch.Tensor, f0: torch.Tensor, n_steps: int, n
     batch = f0.shape[0] if f0.dim() == 4 else None
     if sens is None:
         sens = subset_sensitivities(plan, n_subsets, mu, batch)
+    subs = [_Subset(g, sens[m], subset_angles(plan.n_angles, n_subsets, m), s_add, f0.device)
+            for m in range(min(n_subsets, n_steps))]
     f = f0
     for k in range(n_steps):
         m = k % n_subsets
-        idx = subset_angles(plan.n_angles, n_subsets, m)
         tab = None if tables is None else tables[m]
         if checkpointing:
-            f = checkpoint(osem_update, f, g, sens[m], plan, idx, mu, s_add, tab, use_reentrant=False)
+            f = checkpoint(_osem_step, f, subs[m], plan, mu, tab, use_reentrant=False)
         else:
-            f = osem_update(f, g, sens[m], plan, idx, mu, s_add, tab)
+            f = _osem_step(f, subs[m], plan, mu, tab)
     return f
