@@ -679,10 +679,12 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
 int launch_rdp(const spect_plan *p, const float *f, float *grad, float gamma, hipStream_t st)
 {
     RdpArgs a{f, grad, p->N, p->Nz, gamma};
-    const size_t n = (size_t)p->N * p->N * p->Nz;
+    // one workgroup per 2 x 4 x 32 block of voxels (x, y, z)
+    const size_t nblk = (size_t)((p->N + RDP_TX - 1) / RDP_TX) * ((p->N + RDP_TY - 1) / RDP_TY) *
+                        ((p->Nz + RDP_TZ - 1) / RDP_TZ);
     {
         ProfScope ps(K_RDP, st);
-        hipLaunchKernelGGL(rdp_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(rdp_grad, dim3((unsigned)nblk), dim3(256), 0, st, a);
     }
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? SPECT_OK : hip_fail(e, "prior gradient launch");

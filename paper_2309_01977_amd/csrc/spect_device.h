@@ -1284,15 +1284,37 @@ struct RdpArgs {
     float gamma;
 };
 
+// A workgroup covers a 2 x 4 x 32 (x, y, z) block of voxels; the block and
+// its one-voxel halo are staged in LDS with coalesced z-runs (3.2 global
+// loads per voxel instead of 27), and each voxel reads its 26 neighbours
+// from there in the same order as a direct gather.
+constexpr int RDP_TX = 2, RDP_TY = 4, RDP_TZ = 32;
+constexpr int RDP_HX = RDP_TX + 2, RDP_HY = RDP_TY + 2, RDP_HZ = RDP_TZ + 2;
+
 __global__ __launch_bounds__(256) void rdp_grad(RdpArgs a)
 {
+    __shared__ float tile[RDP_HX * RDP_HY * RDP_HZ];
     const int N = a.N, Nz = a.Nz;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)N * N * Nz) return;
-    const int k = (int)(i % Nz);
-    const int y = (int)((i / Nz) % N);
-    const int x = (int)(i / ((size_t)Nz * N));
-    const float fr = a.f[i];
+    const int nzt = (Nz + RDP_TZ - 1) / RDP_TZ, nyt = (N + RDP_TY - 1) / RDP_TY;
+    int blk = blockIdx.x;
+    const int z0 = (blk % nzt) * RDP_TZ;
+    blk /= nzt;
+    const int y0 = (blk % nyt) * RDP_TY;
+    const int x0 = (blk / nyt) * RDP_TX;
+    for (int t = threadIdx.x; t < RDP_HX * RDP_HY * RDP_HZ; t += blockDim.x) {
+        const int hz = t % RDP_HZ, hy = (t / RDP_HZ) % RDP_HY, hx = t / (RDP_HZ * RDP_HY);
+        const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+        float v = 0.f;
+        if ((unsigned)x < (unsigned)N && (unsigned)y < (unsigned)N && (unsigned)z < (unsigned)Nz)
+            v = a.f[((size_t)x * N + y) * Nz + z];
+        tile[t] = v;
+    }
+    __syncthreads();
+    const int tz = threadIdx.x % RDP_TZ, ty = (threadIdx.x / RDP_TZ) % RDP_TY, tx = threadIdx.x / (RDP_TZ * RDP_TY);
+    const int x = x0 + tx, y = y0 + ty, k = z0 + tz;
+    if (x >= N || y >= N || k >= Nz) return;
+    const float *c0 = tile + ((tx + 1) * RDP_HY + (ty + 1)) * RDP_HZ + tz + 1;
+    const float fr = c0[0];
     const float w2 = 1.41421356237309515f / 2.f, w3 = 1.73205080756887719f / 3.f;
     float acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;  // face, edge and corner neighbours
 #pragma unroll
@@ -1301,19 +1323,19 @@ __global__ __launch_bounds__(256) void rdp_grad(RdpArgs a)
 #pragma unroll
         for (int dy = -1; dy <= 1; ++dy) {
             if ((unsigned)(y + dy) >= (unsigned)N) continue;
-            const float *col = a.f + ((size_t)(x + dx) * N + (y + dy)) * Nz;
+            const float *col = c0 + (dx * RDP_HY + dy) * RDP_HZ;
 #pragma unroll
             for (int dz = -1; dz <= 1; ++dz) {
                 const int nd = (dx != 0) + (dy != 0) + (dz != 0);
                 if (nd == 0 || (unsigned)(k + dz) >= (unsigned)Nz) continue;
-                const float t = rdp_pair(fr, col[k + dz], a.gamma);
+                const float t = rdp_pair(fr, col[dz], a.gamma);
                 if (nd == 1) acc1 += t;
                 else if (nd == 2) acc2 += t;
                 else acc3 += t;
             }
         }
     }
-    a.grad[i] = 2.f * (acc1 + w2 * acc2 + w3 * acc3);
+    a.grad[((size_t)x * N + y) * Nz + k] = 2.f * (acc1 + w2 * acc2 + w3 * acc3);
 }
 
 #endif  // SPECT_HOST_TU
