@@ -44,7 +44,9 @@
  *   - Calls are asynchronous on the given stream (a hipStream_t; NULL is the
  *     null stream).  Results are valid once the stream reaches them.
  *   - angle_idx is a host array of angle indices in [0, n_angles); NULL means
- *     all angles in order (n_idx is then ignored).
+ *     all angles in order (n_idx is then ignored).  An index may repeat: a
+ *     projection call writes that row (with the same values) once more, a
+ *     back projection or sensitivity adds its term once per occurrence.
  *   - The workspace is device memory of at least spect_workspace_size() bytes
  *     for the same op and angle count, 256-byte aligned; it holds nothing
  *     between calls.  Two calls in flight at once need separate workspaces.

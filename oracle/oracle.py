@@ -131,12 +131,14 @@ def _idx(geom: Geometry, idx):
 
 
 def forward(geom: Geometry, f, mu=None, idx=None, out=None) -> np.ndarray:
-    """Rows idx of H f (Eq. 1); other rows of ``out`` are left as they are."""
+    """Rows idx of H f (Eq. 1); other rows of ``out`` are left as they are.
+    The rows are a set: an angle listed twice is projected once (its row is
+    not summed twice, and two threads never write one row)."""
     lib = _load()
     g, ang, rad = geom._c()
     f = np.ascontiguousarray(f, dtype=np.float64).reshape(geom.object_shape)
     mu = None if mu is None else np.ascontiguousarray(mu, dtype=np.float64).reshape(geom.object_shape)
-    ix = _idx(geom, idx)
+    ix = np.ascontiguousarray(np.unique(_idx(geom, idx)), dtype=np.int32)
     if out is None:
         out = np.zeros(geom.proj_shape, dtype=np.float64)
     assert out.dtype == np.float64 and out.flags.c_contiguous and out.shape == geom.proj_shape

@@ -319,6 +319,27 @@ def test_noncircular_orbit_parity():
     assert e <= OSEM_TOL
 
 
+def test_repeated_angles_in_a_list():
+    """An angle listed twice: the forward writes its row once more with the
+    same values, the back projection and the sensitivity count it once per
+    occurrence; against the oracle."""
+    og, plan = both(24, 20, 8)
+    r = np.random.default_rng(61)
+    f = P.random_object(og.object_shape, r)
+    y = P.random_object(og.proj_shape, r)
+    mu = P.random_mu(og.object_shape, r, 0.15)
+    mu64 = mu.astype(np.float64)
+    idx = [3, 6, 3, 3]
+    got = host(plan.forward(dev(f), dev(mu), idx))
+    ref = O.forward(og, f.astype(np.float64), mu64, idx)
+    assert max(rel_l2(got[n], ref[n]) for n in (3, 6)) <= FWD_TOL
+    assert not np.delete(got, [3, 6], axis=0).any()
+    e_b = rel_l2(host(plan.back(dev(y), dev(mu), idx)), O.back(og, y.astype(np.float64), mu64, idx))
+    e_s = rel_l2(host(plan.sensitivity(dev(mu), idx)), O.back(og, np.ones(og.proj_shape), mu64, idx))
+    say(f"  repeated angles: back {e_b:.2e}, sensitivity {e_s:.2e}")
+    assert e_b <= BACK_TOL and e_s <= BACK_TOL
+
+
 def test_largest_grid_and_blur_radius():
     """At the limits the plan accepts: N = 256 (512-thread workgroups) and a
     blur radius of 32 pixels at the far depths (the widest blur class, whose

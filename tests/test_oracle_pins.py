@@ -199,6 +199,19 @@ def test_p6_each_angle_blurs_with_its_own_detector_distance():
     assert p[3].sum() < 1 - 1e-5  # the tail past the last bin is lost
 
 
+def test_repeated_angles_project_once_and_back_project_per_occurrence():
+    """An angle listed twice: the forward's rows are a set (the row equals the
+    one projected alone, whatever the thread schedule), the back projection
+    is a sum over list entries (linearity: twice that angle's term)."""
+    g = O.Geometry(12, 5, 6, 0.5, 0.03, 0.1)
+    r = rng(41)
+    f, y, mu = r.random(g.object_shape), r.random(g.proj_shape), 0.1 * r.random(g.object_shape)
+    np.testing.assert_array_equal(O.forward(g, f, mu, [3, 3, 5]), O.forward(g, f, mu, [3, 5]))
+    np.testing.assert_array_equal(O.forward(g, f, mu, [5, 3, 3, 3]), O.forward(g, f, mu, [3, 5]))
+    b = O.back(g, y, mu, [3, 3, 5])
+    np.testing.assert_allclose(b, 2 * O.back(g, y, mu, [3]) + O.back(g, y, mu, [5]), rtol=1e-13, atol=1e-15)
+
+
 def test_p6_second_moment_matches_sigma_squared():
     """Second moment of the discrete kernel equals sigma(d)^2 within 0.2 %
     where sigma is at least one pixel (closed form of the continuous
