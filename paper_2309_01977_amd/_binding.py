@@ -150,7 +150,7 @@ class Plan:
         h = ctypes.c_void_p()
         _check(lib.spect_plan_create(ctypes.byref(g), ctypes.byref(h)))
         self._h = h
-        self._ws: Dict[Tuple[int, int, int], torch.Tensor] = {}
+        self._ws: Dict[Tuple[int, int, int, int], torch.Tensor] = {}
 
     @classmethod
     def for_workload(cls, w) -> "Plan":
@@ -192,7 +192,11 @@ class Plan:
         return b.value
 
     def workspace(self, op: int, n_idx: int, with_mu) -> torch.Tensor:
-        key = (op, int(n_idx), self._mu_code(with_mu))
+        """The scratch of one call, kept for reuse per (op, size, attenuation
+        mode, stream): calls on one stream run in order, calls on different
+        streams get different scratch (two calls in flight at once must not
+        share it)."""
+        key = (op, int(n_idx), self._mu_code(with_mu), torch.cuda.current_stream().cuda_stream)
         ws = self._ws.get(key)
         if ws is None:
             nbytes = max(self.workspace_size(op, n_idx, with_mu), 256)

@@ -319,6 +319,32 @@ def test_noncircular_orbit_parity():
     assert e <= OSEM_TOL
 
 
+def test_one_plan_on_two_streams():
+    """Projector calls with one plan issued on two streams at once (each
+    stream gets its own scratch) give the results of the same calls one
+    after another, bitwise."""
+    og, plan = both(48, 32, 12)
+    r = np.random.default_rng(62)
+    fs = [dev(P.random_object(og.object_shape, r)) for _ in range(2)]
+    mu = dev(P.random_mu(og.object_shape, r, 0.15))
+    idx = [1, 5, 9]
+    ref = [host(plan.forward(f, mu, idx)) for f in fs]
+    ref_b = [host(plan.back(dev(x), mu, idx)) for x in ref]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    outs = [[], []]
+    for _ in range(4):
+        for k in range(2):
+            with torch.cuda.stream(streams[k]):
+                p = plan.forward(fs[k], mu, idx)
+                outs[k].append((p, plan.back(p, mu, idx)))
+    torch.cuda.synchronize()
+    for k in range(2):
+        for p, b in outs[k]:
+            np.testing.assert_array_equal(host(p), ref[k])
+            np.testing.assert_array_equal(host(b), ref_b[k])
+
+
 def test_repeated_angles_in_a_list():
     """An angle listed twice: the forward writes its row once more with the
     same values, the back projection and the sensitivity count it once per
