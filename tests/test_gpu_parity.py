@@ -319,6 +319,28 @@ def test_noncircular_orbit_parity():
     assert e <= OSEM_TOL
 
 
+def test_osem_subset_extremes():
+    """One angle per subset (n_subsets = n_angles: every launch lists a
+    single angle), a single subset (plain MLEM), and zero iterations (only
+    the sensitivities: the image stays as given, bitwise), against the
+    oracle."""
+    n, nz, A = 32, 20, 6
+    og, plan = both(n, nz, A, angles=list(np.random.default_rng(8).uniform(0, 360, A)))
+    r = np.random.default_rng(63)
+    f_true = P.random_object(og.object_shape, r)
+    mu = P.random_mu(og.object_shape, r, 0.12)
+    mu64 = mu.astype(np.float64)
+    g = P.poisson_counts(O.forward(og, f_true.astype(np.float64), mu64), 1e5, r)
+    for I, M in ((2, A), (3, 1)):
+        got = host(S.osem(plan, dev(g), I, M, dev(mu)))
+        ref = O.osem(og, g.astype(np.float64), mu64, I, M)
+        e = rel_l2(got, ref)
+        say(f"  {I} it x {M} subsets: rel L2 {e:.2e}")
+        assert e <= OSEM_TOL
+    f0 = (0.5 + P.random_object(og.object_shape, r)).astype(np.float32)
+    np.testing.assert_array_equal(host(S.osem(plan, dev(g), 0, 3, dev(mu), f0=dev(f0))), f0.astype(np.float64))
+
+
 def test_one_plan_on_two_streams():
     """Projector calls with one plan issued on two streams at once (each
     stream gets its own scratch) give the results of the same calls one
