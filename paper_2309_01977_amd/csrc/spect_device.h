@@ -581,6 +581,9 @@ __device__ __forceinline__ void fwd_body(const Args &a, int slab, int chunk, int
         const float *gt = a.g.taps + ((size_t)ang * N + ip) * a.g.TS;
         float w[ROWS];
         if (active) {
+            // this depth's loads go out at raised priority, so they are in
+            // flight while the other waves of the SIMD blur
+            __builtin_amdgcn_s_setprio(2);
             const Corners cn = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, rg.rowb);
             Raw rf, rm;
             float4 t0, t1;
@@ -591,6 +594,7 @@ __device__ __forceinline__ void fwd_body(const Args &a, int slab, int chunk, int
                 t0 = stream_f4(trow, toff);
                 t1 = stream_f4(trow, toff + 16);
             }
+            __builtin_amdgcn_s_setprio(0);
             combine(rf, cn, kb, Nz, w, full);
             if (ATT == ATT_READ) {
                 w[0] *= t0.x;
