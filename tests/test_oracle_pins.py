@@ -252,6 +252,90 @@ def test_p6_blur_equals_library_2d_convolution():
     np.testing.assert_allclose(p, ref, rtol=1e-12, atol=1e-14)
 
 
+# ------------------------------------------------- Eq. 1 operator order ----
+#
+# Eq. 1 applies T_att before T_cdr.  At 0 and 90 degrees the rotation is an
+# exact permutation (R3), so with an absorber that covers only part of the
+# detector bins every value below is a closed form: the sampled Gaussian of
+# the source depth (R6, R7) times exp(-mu dx (t + 1/2)), t being the voxels
+# between the emitting voxel and the detector (R5).  Blurring first and
+# attenuating afterwards would attenuate each blurred bin by its own ray, so
+# the bins beyond the absorber edge would come out unattenuated.
+
+def _rot_to_obj(deg, n):
+    """Object (x, y) of rotated-frame (depth i', bin j') at 0 or 90 degrees."""
+    return (lambda i, j: (i, j)) if deg == 0.0 else (lambda i, j: (n - 1 - j, i))
+
+
+def _half_absorber(deg, n, nz, mu0, j_edge):
+    """mu0 on every rotated ray with bin j' <= j_edge (all depths, all
+    slices), 0 on the others."""
+    to_obj = _rot_to_obj(deg, n)
+    mu = np.zeros((n, n, nz))
+    for i in range(n):
+        for j in range(j_edge + 1):
+            mu[to_obj(i, j)] = mu0
+    return mu
+
+
+def _depth_taps(n, dx, a, b, depth):
+    c = 0.5 * (n - 1)
+    s = (a * (n * dx / 2 - (depth - c) * dx) + b) / dx
+    K = int(np.ceil(4 * s - 1e-9))
+    return _gauss_taps(s, K), K
+
+
+@pytest.mark.parametrize("deg", [0.0, 90.0])
+def test_eq1_point_source_is_attenuated_once_then_blurred(deg):
+    """Forward: a point source at rotated (depth 4, bin 11, slice 7), with
+    the absorber covering bins 0..11, projects to exp(-tau of the source)
+    times g_4 (x) g_4 centred on (bin 11, slice 7); half of the kernel lies
+    on bins outside the absorber and still carries the source's factor."""
+    n, nz, dx, mu0, a, b = 24, 15, 0.48, 0.15, 0.03, 0.1
+    ip, jp, k0 = 4, 11, 7
+    g = O.Geometry(n, nz, 1, dx, a, b, angles_deg=[deg])
+    to_obj = _rot_to_obj(deg, n)
+    f = np.zeros((n, n, nz))
+    f[to_obj(ip, jp) + (k0,)] = 1.0
+    mu = _half_absorber(deg, n, nz, mu0, jp)
+    p = O.forward(g, f, mu)[0]
+    k1, K = _depth_taps(n, dx, a, b, ip)
+    assert K == 4
+    att = np.exp(-mu0 * dx * ((n - 1 - ip) + 0.5))
+    expect = np.zeros((n, nz))
+    expect[jp - K:jp + K + 1, k0 - K:k0 + K + 1] = att * np.outer(k1, k1)
+    np.testing.assert_allclose(p, expect, rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("deg", [0.0, 90.0])
+def test_eq1_back_projection_blurs_then_attenuates_by_the_voxel_ray(deg):
+    """Back projection (the transpose, applied in reverse order): a unit
+    count in (bin 11, slice 7) reaches the voxel at rotated (i', j', k) as
+    g_i'(j' - 11) g_i'(k - 7) times the attenuation factor of that voxel's
+    own ray: exp(-mu dx (N - 1 - i' + 1/2)) for j' <= 11 inside the
+    absorber, 1 beyond its edge."""
+    n, nz, dx, mu0, a, b = 24, 15, 0.48, 0.15, 0.03, 0.1
+    jp, k0 = 11, 7
+    g = O.Geometry(n, nz, 1, dx, a, b, angles_deg=[deg])
+    to_obj = _rot_to_obj(deg, n)
+    mu = _half_absorber(deg, n, nz, mu0, jp)
+    y = np.zeros(g.proj_shape)
+    y[0, jp, k0] = 1.0
+    out = O.back(g, y, mu)
+    expect = np.zeros((n, n, nz))
+    for i in range(n):
+        k1, K = _depth_taps(n, dx, a, b, i)
+        for m in range(-K, K + 1):
+            j = jp + m
+            if not 0 <= j < n:
+                continue
+            att = np.exp(-mu0 * dx * ((n - 1 - i) + 0.5)) if j <= jp else 1.0
+            lo, hi = max(0, k0 - K), min(nz, k0 + K + 1)
+            expect[to_obj(i, j) + (slice(lo, hi),)] = att * k1[K + m] * k1[K + lo - k0:K + hi - k0]
+    assert (expect > 0).sum() > 300
+    np.testing.assert_allclose(out, expect, rtol=1e-12, atol=1e-15)
+
+
 # ------------------------------------------------------------------- P7 ----
 
 def _bin_chord(v_lo, v_hi, rho):
