@@ -223,6 +223,13 @@ int spect_batch_set_schedule(spect_batch *batch, int32_t schedule);
  * untouched until then.  Results equal osem_reconstruct alone.  Not
  * thread-safe: one host thread drives a server.
  *
+ * Ordering: spect_server_submit records an event on `stream` (the caller's
+ * HIP stream; NULL = the null stream), and the request's kernels wait for it
+ * on the device, so f, mu, g and s_add may still be being written by work
+ * the caller queued on that stream before the call.  A request is finished
+ * once spect_server_wait returns or its state reads SPECT_REQ_DONE; the
+ * caller may then read f on any stream.
+ *
  * spect_server_submit fails with SPECT_EINVAL if the request's workspace can
  * never fit in the pool.  spect_server_status: *state = SPECT_REQ_*; a failed
  * request returns its error code and message.  spect_server_forget drops the
@@ -238,7 +245,7 @@ int spect_server_create(int32_t n_slots, size_t pool_bytes, spect_server **out);
 int spect_server_destroy(spect_server *server);
 int spect_server_submit(spect_server *server, const spect_plan *plan, float *f, const float *mu,
                         const float *g, const float *s_add, int32_t n_iters, int32_t n_subsets,
-                        int64_t *request_id);
+                        void *stream, int64_t *request_id);
 int spect_server_progress(spect_server *server, int32_t *n_running, int32_t *n_queued);
 int spect_server_status(spect_server *server, int64_t request_id, int32_t *state);
 int spect_server_wait(spect_server *server, int64_t request_id);

@@ -93,7 +93,7 @@ def load_library(path: Optional[str] = None):
     i64 = ctypes.c_int64
     lib.spect_server_create.argtypes = [i32, sz, vpp]
     lib.spect_server_destroy.argtypes = [vp]
-    lib.spect_server_submit.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, ctypes.POINTER(i64)]
+    lib.spect_server_submit.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, vp, ctypes.POINTER(i64)]
     lib.spect_server_progress.argtypes = [vp, i32p, i32p]
     lib.spect_server_status.argtypes = [vp, i64, i32p]
     lib.spect_server_wait.argtypes = [vp, i64]
@@ -528,7 +528,7 @@ class Server:
         _check(load_library().spect_server_submit(
             self._h, plan._h, _ptr(f, plan.object_shape, "f"), _ptr(mu, plan.object_shape, "mu"),
             _ptr(g, plan.proj_shape, "g"), _ptr(s_add, plan.proj_shape, "s_add"), int(n_iters), int(n_subsets),
-            ctypes.byref(rid)))
+            _stream(), ctypes.byref(rid)))
         self._keep[rid.value] = (plan, f, g, mu, s_add)
         return rid.value
 

@@ -1378,6 +1378,10 @@ struct spect_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int graph_sched = -1;
+    // vector (16-byte) or scalar kernels in the launch tables, and in the
+    // captured graph: arrays that change alignment switch the kernels, so the
+    // graph is captured again
+    int tables_vec = -1, graph_vec = -1;
 };
 
 namespace {
@@ -1396,6 +1400,7 @@ void drop_graph(spect_batch *b)
     b->exec = nullptr;
     b->graph = nullptr;
     b->graph_sched = -1;
+    b->graph_vec = -1;
 }
 
 struct Ptrs {
@@ -1708,6 +1713,7 @@ int capture_iteration(spect_batch *b)
         return hip_fail(e, "graph instantiation");
     }
     b->graph_sched = b->sched;
+    b->graph_vec = b->tables_vec;
     return SPECT_OK;
 }
 
@@ -1766,6 +1772,7 @@ int prepare(spect_batch *b, const Ptrs &P, bool vec)
     if (key == b->key && b->key_sched == b->sched) return SPECT_OK;
     const int st = build_tables(b, P, vec, b->sched);
     if (st) return st;
+    b->tables_vec = vec ? 1 : 0;
     b->key = key;
     b->key_sched = b->sched;
     return SPECT_OK;
@@ -1906,7 +1913,7 @@ int osem_batch_reconstruct(spect_batch *b, float *const *f, const float *const *
                 if ((st = launch_step(b, m, s, false))) return st;
         return ok();
     }
-    if (!b->exec || b->graph_sched != b->sched)
+    if (!b->exec || b->graph_sched != b->sched || b->graph_vec != b->tables_vec)
         if ((st = capture_iteration(b))) return st;
     for (int it = 0; it < n_iters; ++it) {
         const hipError_t e = hipGraphLaunch(b->exec, s);

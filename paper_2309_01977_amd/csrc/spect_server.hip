@@ -7,7 +7,10 @@
 // stream) is idle and the pool has a free block of the request's workspace
 // size, so requests that arrive while others run start without waiting for
 // them, and their kernels overlap on the device.  Completion is detected by
-// polling an event recorded after the request's launches.
+// polling an event recorded after the request's launches.  A request's
+// launches wait (on the device) for an event recorded on the caller's stream
+// when it was submitted, so inputs the caller produced asynchronously are
+// complete before the reconstruction reads them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,6 +35,7 @@ struct Request {
     const float *mu = nullptr, *g = nullptr, *s = nullptr;
     int iters = 0, subsets = 1;
     size_t ws = 0, off = 0;
+    hipEvent_t ready = nullptr;  // recorded on the caller's stream at submission
     int state = SPECT_REQ_QUEUED;
     int slot = -1;
     int err = SPECT_OK;
@@ -101,6 +105,12 @@ struct spect_server {
         }
     }
 
+    static void drop_ready(Request &r)
+    {
+        if (r.ready) (void)hipEventDestroy(r.ready);
+        r.ready = nullptr;
+    }
+
     int running() const
     {
         int n = 0;
@@ -124,6 +134,7 @@ struct spect_server {
                 r.msg = hipGetErrorString(e);
             }
             release(r.off, r.ws);
+            drop_ready(r);
             r.slot = -1;
             busy[k] = -1;
         }
@@ -140,13 +151,22 @@ struct spect_server {
             if (!alloc(r.ws, &off)) break;  // the head waits for memory; arrival order is kept
             const int64_t id = queue.front();
             queue.pop_front();
-            int st = osem_reconstruct(r.plan, r.f, r.mu, r.g, r.s, r.iters, r.subsets, pool + off, r.ws, slots[k]);
-            if (st == SPECT_OK && hipEventRecord(done[k], slots[k]) != hipSuccess) st = SPECT_EHIP;
+            int st = SPECT_OK;
+            if (hipStreamWaitEvent(slots[k], r.ready, 0) != hipSuccess) {
+                st = set_error(SPECT_EHIP, "slot stream could not wait for the submission event");
+            } else {
+                st = osem_reconstruct(r.plan, r.f, r.mu, r.g, r.s, r.iters, r.subsets, pool + off, r.ws, slots[k]);
+                if (st == SPECT_OK && hipEventRecord(done[k], slots[k]) != hipSuccess) st = SPECT_EHIP;
+            }
             if (st != SPECT_OK) {
                 r.state = SPECT_REQ_FAILED;
                 r.err = st;
                 r.msg = spect_last_error();
                 release(off, r.ws);
+                // the slot stream may hold the wait on the event: destroy it
+                // only once the stream has drained
+                (void)hipStreamSynchronize(slots[k]);
+                drop_ready(r);
                 continue;
             }
             r.off = off;
@@ -200,13 +220,15 @@ int spect_server_destroy(spect_server *s)
     for (size_t k = 0; k < s->slots.size(); ++k) (void)hipStreamSynchronize(s->slots[k]);
     for (hipStream_t st : s->slots) (void)hipStreamDestroy(st);
     for (hipEvent_t ev : s->done) (void)hipEventDestroy(ev);
+    for (auto &kv : s->reqs) spect_server::drop_ready(kv.second);
     if (s->pool) (void)hipFree(s->pool);
     delete s;
     return clear_error();
 }
 
 int spect_server_submit(spect_server *s, const spect_plan *plan, float *f, const float *mu, const float *g,
-                        const float *s_add, int32_t n_iters, int32_t n_subsets, int64_t *request_id)
+                        const float *s_add, int32_t n_iters, int32_t n_subsets, void *stream,
+                        int64_t *request_id)
 {
     if (!s) return set_error(SPECT_EINVAL, "server is NULL");
     if (!request_id) return set_error(SPECT_EINVAL, "request_id is NULL");
@@ -227,6 +249,12 @@ int spect_server_submit(spect_server *s, const spect_plan *plan, float *f, const
     r.iters = n_iters;
     r.subsets = n_subsets;
     r.ws = ws;
+    if (hipEventCreateWithFlags(&r.ready, hipEventDisableTiming) != hipSuccess)
+        return set_error(SPECT_EHIP, "event creation failed");
+    if (hipEventRecord(r.ready, static_cast<hipStream_t>(stream)) != hipSuccess) {
+        (void)hipEventDestroy(r.ready);
+        return set_error(SPECT_EHIP, "could not record the submission event on the caller's stream");
+    }
     const int64_t id = s->next_id++;
     s->reqs[id] = r;
     s->queue.push_back(id);

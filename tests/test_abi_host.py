@@ -146,7 +146,7 @@ def test_server_calls_reject_bad_arguments_before_any_device_call():
     assert h.value is None
     assert lib.spect_server_create(2, 16, ctypes.byref(h)) == B.SPECT_EINVAL
     rid = ctypes.c_int64()
-    assert lib.spect_server_submit(None, None, None, None, None, None, 1, 1, ctypes.byref(rid)) == B.SPECT_EINVAL
+    assert lib.spect_server_submit(None, None, None, None, None, None, 1, 1, None, ctypes.byref(rid)) == B.SPECT_EINVAL
     assert lib.spect_server_progress(None, None, None) == B.SPECT_EINVAL
     st = ctypes.c_int32()
     assert lib.spect_server_status(None, 1, ctypes.byref(st)) == B.SPECT_EINVAL

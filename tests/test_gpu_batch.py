@@ -185,3 +185,36 @@ def test_autotune_picks_a_timed_schedule_and_keeps_the_images():
     ref, _ = run_batch(mem, M, I, True, eager=True)
     for f, b in zip(fs, ref):
         np.testing.assert_array_equal(host(f), b)
+
+
+def test_graph_is_captured_again_when_the_arrays_lose_16_byte_alignment():
+    """The same batch first with 16-byte aligned images (vector kernels),
+    then with images that start 4 bytes into their storage (scalar kernels):
+    the captured iteration must not replay the vector kernels on the
+    unaligned arrays.  Both runs against the oracle and bitwise against the
+    eager path on the same arrays."""
+    M, I = 4, 2
+    mem = members(SHAPES, True, 76)
+    batch = S.Batch([m[1] for m in mem], M, True)
+    mus = [dev(m[2]) for m in mem]
+    gs = [dev(m[3]) for m in mem]
+    refs = [O.osem(og, g.astype(np.float64), mu.astype(np.float64), I, M) for og, _, mu, g in mem]
+    for offset in (0, 1):
+        fs = []
+        for m in mem:
+            n = int(np.prod(m[1].object_shape))
+            buf = torch.empty(n + 4, device="cuda")
+            f = buf[offset:offset + n].view(m[1].object_shape)
+            assert (f.data_ptr() % 16 == 0) == (offset == 0)
+            f.fill_(1.0)
+            fs.append(f)
+        batch.reconstruct(fs, mus, gs, I)
+        got = [host(f) for f in fs]
+        for f in fs:
+            f.fill_(1.0)
+        batch.reconstruct(fs, mus, gs, I, eager=True)
+        for a, f, ref, m in zip(got, fs, refs, mem):
+            e = rel_l2(a, ref)
+            say(f"  offset {4 * offset} B {m[0].object_shape}: vs oracle {e:.2e}")
+            assert e <= OSEM_TOL
+            np.testing.assert_array_equal(a, host(f))

@@ -162,3 +162,32 @@ def test_replayed_poisson_trace_completes_with_the_same_results():
         mu = None if mus is None else mus[s.data_index]
         assert rel_l2(host(s.f), alone(plan, gs[s.data_index], mu, I, M)) <= OSEM_TOL
     server.close()
+
+
+def test_requests_wait_for_inputs_written_on_the_callers_stream():
+    """The initial image, the data and the attenuation map are written by
+    work queued on the caller's (torch's) stream right before submission,
+    behind a dozen milliseconds of other kernels; the request must be
+    ordered after that work, so the result equals the reconstruction alone
+    and not one of the placeholder values the arrays held before."""
+    cls = make_classes(85, per_class=1)
+    og, plan, gs, mus, I, M = cls[1]
+    g_src, mu_src = dev(gs[0]), dev(mus[0])
+    f = torch.full(plan.object_shape, 7.0, device="cuda")
+    g = torch.full(plan.proj_shape, 1e6, device="cuda")
+    mu = torch.full(plan.object_shape, 5.0, device="cuda")
+    torch.cuda.synchronize()
+    a = torch.randn(4096, 4096, device="cuda")
+    for _ in range(12):
+        a = torch.tanh(a @ a)
+    f.fill_(1.0)
+    g.copy_(g_src)
+    mu.copy_(mu_src)
+    server = S.Server(2, 1 << 30)
+    rid = server.submit(plan, f, g, I, M, mu)
+    server.wait(rid)
+    got, ref = host(f), alone(plan, gs[0], mus[0], I, M)
+    e = rel_l2(got, ref)
+    say(f"  inputs written on the caller's stream: vs alone {e:.2e}")
+    assert e == 0.0
+    server.close()
