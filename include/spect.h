@@ -134,6 +134,24 @@ int spect_fwd(const spect_plan *plan, const float *f, const float *mu, float *pr
               const int32_t *angle_idx, int32_t n_idx, void *ws, size_t ws_bytes,
               void *stream);
 
+/* Allocation-free forward projection, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc): the same computation as spect_fwd, bitwise, with
+ * the scratch taken from a fixed device array of the library
+ * (SPECT_STATIC_SCRATCH_BYTES on every device the library runs on, held until
+ * the process ends) instead of a caller workspace.  The call allocates
+ * nothing.  It returns SPECT_EINVAL, launching nothing, when the listed
+ * angles need more scratch than that (spect_workspace_size with SPECT_OP_FWD
+ * gives the need; 128^3 with 120 angles and the 0.48 cm blur fits).  Every
+ * call on one device uses the same array: calls that overlap in time on one
+ * device (several streams, or several host threads) race and must be
+ * serialised by the caller, e.g. by issuing them on one stream.  The array
+ * needs no clearing between calls (every scratch element a call reads is
+ * written earlier in the same call). */
+#define SPECT_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int spect_fwd_static(const spect_plan *plan, const float *f, const float *mu, float *proj,
+                     const int32_t *angle_idx, int32_t n_idx, void *stream);
+
 /* Back projection (BP, Section 2.1.1): f_out = sum over listed n of
  * H_n^T proj[n] (accumulate == 0), or f_out += that sum (accumulate != 0).
  * proj: device (A, N, Nz), only listed rows are read; f_out: device

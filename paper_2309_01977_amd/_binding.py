@@ -24,7 +24,7 @@ SPECT_EUNSUPPORTED = -4
 OP_FWD, OP_BACK, OP_SENS, OP_OSEM, OP_RECON, OP_BSREM_STEP, OP_BSREM = 0, 1, 2, 3, 4, 5, 6
 ATT_TABLE = 2   # with_mu code of the attenuation-table calls
 
-EXPORTS = ("spect_plan_create", "spect_plan_destroy", "spect_workspace_size", "spect_fwd",
+EXPORTS = ("spect_plan_create", "spect_plan_destroy", "spect_workspace_size", "spect_fwd", "spect_fwd_static",
            "spect_back", "spect_sensitivity", "spect_table_size", "spect_sensitivity_table",
            "spect_fwd_table", "spect_back_table", "osem_subset_step", "osem_reconstruct",
            "spect_rdp_gradient", "bsrem_subset_step", "bsrem_reconstruct", "spect_batch_create",
@@ -70,6 +70,7 @@ def load_library(path: Optional[str] = None):
     lib.spect_plan_destroy.argtypes = [vp]
     lib.spect_workspace_size.argtypes = [vp, ctypes.c_int, i32, ctypes.c_int, ctypes.POINTER(sz)]
     lib.spect_fwd.argtypes = [vp, vp, vp, vp, i32p, i32, vp, sz, vp]
+    lib.spect_fwd_static.argtypes = [vp, vp, vp, vp, i32p, i32, vp]
     lib.spect_back.argtypes = [vp, vp, vp, vp, i32p, i32, ctypes.c_int, vp, sz, vp]
     lib.spect_sensitivity.argtypes = [vp, vp, vp, i32p, i32, vp, sz, vp]
     lib.spect_table_size.argtypes = [vp, i32, ctypes.POINTER(sz)]
@@ -221,6 +222,18 @@ class Plan:
                                          _ptr(mu, self.object_shape, "mu"),
                                          _ptr(out, self.proj_shape, "proj"), arr, n,
                                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+        return out
+
+    def forward_static(self, f: torch.Tensor, mu: Optional[torch.Tensor] = None, idx=None,
+                       out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Rows idx of H f through spect_fwd_static: no workspace, the
+        library's fixed scratch array (calls on one device must not overlap)."""
+        if out is None:
+            out = torch.zeros(self.proj_shape, dtype=torch.float32, device=f.device)
+        arr, n = self._idx(idx)
+        _check(load_library().spect_fwd_static(self._h, _ptr(f, self.object_shape, "f"),
+                                                _ptr(mu, self.object_shape, "mu"),
+                                                _ptr(out, self.proj_shape, "proj"), arr, n, _stream()))
         return out
 
     def back(self, proj: torch.Tensor, mu: Optional[torch.Tensor] = None, idx=None,

@@ -17,6 +17,14 @@
 
 using namespace spectk;
 
+// ======================================================= static scratch ===
+// Scratch of the allocation-free forward projection (spect_fwd_static): a
+// device array of fixed size; every device holds its own copy.  Host code
+// never uses the array's name as an address: the device address is looked up
+// once per device (bind_static_scratch, run when a plan is created on that
+// device) and kept in g_scratch_dev.
+static __device__ __align__(256) char scratch[SPECT_STATIC_SCRATCH_BYTES];
+
 // ================================================================= host ===
 
 struct spect_plan {
@@ -711,6 +719,31 @@ int clear(float *p, size_t n, hipStream_t st)
     return e == hipSuccess ? SPECT_OK : hip_fail(e, "clear launch");
 }
 
+std::mutex g_scratch_mu;
+std::vector<char *> g_scratch_dev;  // device address of `scratch`, per device id
+
+// Look up this device's copy of the static scratch array (the device must be
+// current); done once per device.
+int bind_static_scratch(int device)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0) return fail(SPECT_EHIP, "invalid device %d", device);
+    if ((int)g_scratch_dev.size() <= device) g_scratch_dev.resize(device + 1, nullptr);
+    if (g_scratch_dev[device]) return SPECT_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "device address of the static scratch array");
+    if (!ptr || ((uintptr_t)ptr & 255)) return fail(SPECT_EHIP, "static scratch array has no usable address");
+    g_scratch_dev[device] = static_cast<char *>(ptr);
+    return SPECT_OK;
+}
+
+char *static_scratch(int device)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return device >= 0 && device < (int)g_scratch_dev.size() ? g_scratch_dev[device] : nullptr;
+}
+
 bool want_vec(const spect_plan *p, std::initializer_list<const void *> ptrs)
 {
     if (p->Nz % 4) return false;
@@ -922,6 +955,11 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
         p->back_slots[att] = std::max(1, nb) * cus;
     }
     (void)hipGetLastError();
+    // the library's per-device set-up: the static scratch array's address
+    if (const int st = bind_static_scratch(p->device)) {
+        spect_plan_destroy(p);
+        return st;
+    }
     *out = p;
     return ok();
 }
@@ -1071,6 +1109,24 @@ int spect_fwd(const spect_plan *plan, const float *f, const float *mu, float *pr
 {
     const int st = check_ptr(mu, "mu", true);
     return st ? st : do_fwd(plan, f, mu, nullptr, proj, angle_idx, n_idx, ws, ws_bytes, stream);
+}
+
+int spect_fwd_static(const spect_plan *plan, const float *f, const float *mu, float *proj,
+                     const int32_t *angle_idx, int32_t n_idx, void *stream)
+{
+    int st;
+    if ((st = check_plan(plan))) return st;
+    if ((st = check_ptr(mu, "mu", true))) return st;
+    std::vector<int> list;
+    if ((st = make_list(plan, angle_idx, n_idx, &list))) return st;
+    if (list.empty()) return ok();
+    const size_t need = fwd_ws(plan, (int)list.size(), att_of(mu != nullptr));
+    if (need > SPECT_STATIC_SCRATCH_BYTES)
+        return fail(SPECT_EINVAL, "%zu angles need %zu scratch bytes; the static scratch holds %zu",
+                    list.size(), need, (size_t)SPECT_STATIC_SCRATCH_BYTES);
+    char *ws = static_scratch(plan->device);
+    if (!ws) return fail(SPECT_EHIP, "static scratch not set up on device %d", plan->device);
+    return do_fwd(plan, f, mu, nullptr, proj, angle_idx, n_idx, ws, SPECT_STATIC_SCRATCH_BYTES, stream);
 }
 
 int spect_back(const spect_plan *plan, const float *proj, const float *mu, float *f_out,
