@@ -109,7 +109,7 @@ typedef struct {
  * several streams at once.  The angle and radius arrays are copied.
  * Errors: SPECT_EINVAL (NULL pointers, sizes < 1, flags != 0, non-finite or
  * out-of-range values), SPECT_EUNSUPPORTED (N > SPECT_MAX_N, blur radius >
- * SPECT_MAX_K, an object of 2^30 voxels (4 GiB) or more, a projection set
+ * SPECT_MAX_K, an object of 2^29 voxels (2 GiB) or more, a projection set
  * of 2^31 elements or more, Nz >= 2^22), SPECT_ENOMEM, SPECT_EHIP. */
 int spect_plan_create(const spect_geometry *geom, spect_plan **out);
 

@@ -442,14 +442,20 @@ BackBatchFn back_batch_kernel(int att, int kmc, bool vec, bool persist)
     }
 }
 
+// Threads of a forward workgroup (FQ lanes per bin) and of a rotated-frame
+// back-projection workgroup (2 lanes per bin), whole waves.
+int fwd_threads(int N) { return std::min(FWD_MAX_THREADS, ((FQ * N + 63) / 64) * 64); }
 int block_threads(int N) { return std::min(512, ((2 * N + 63) / 64) * 64); }
 
 size_t wb_bytes(int N, int kmc) { return sizeof(float4) * 2 * 2 * 2 * (size_t)(N + 2 * kmc); }
 
+// Forward: the two row buffers ([2][N + 2 kmc][FQ] float4), later reused to
+// merge the slab's partial rows ([N][SLAB + 2 kmc] floats).
 size_t fwd_smem(int N, int kmc)
 {
-    const size_t merge = sizeof(float) * (size_t)N * (ROWS + 2 * kmc + 1);
-    return std::max(wb_bytes(N, kmc), merge);
+    const size_t rows = sizeof(float4) * 2 * FQ * (size_t)(N + 2 * kmc);
+    const size_t merge = sizeof(float) * (size_t)N * (SLAB + 2 * kmc);
+    return std::max(rows, merge);
 }
 
 // Row buffers plus the projection columns: N columns of SLAB + 2 kmc + 1
@@ -579,7 +585,7 @@ int run_forward(const spect_plan *p, const float *f, const float *mu, int att, c
     allow_smem(reinterpret_cast<const void *>(fk), fwd_smem(p));
     {
         ProfScope ps(K_FWD, st);
-        hipLaunchKernelGGL(fk, dim3(t.nslab, t.nchunk, L.n), dim3(block_threads(p->N)), fwd_smem(p), st, a);
+        hipLaunchKernelGGL(fk, dim3(t.nslab, t.nchunk, L.n), dim3(fwd_threads(p->N)), fwd_smem(p), st, a);
     }
     ReduceArgs r;
     r.L = L;
@@ -824,7 +830,7 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
     if (g.n > SPECT_MAX_N) return fail(SPECT_EUNSUPPORTED, "n = %d exceeds %d", g.n, SPECT_MAX_N);
     const double vol = (double)g.n * g.n * g.nz, prj = (double)g.n_angles * g.n * g.nz;
     // kernels address a volume with 32-bit byte offsets and 24-bit row products
-    if (vol >= 1073741824.0) return fail(SPECT_EUNSUPPORTED, "object of 2^30 voxels or more");
+    if (vol >= 536870912.0) return fail(SPECT_EUNSUPPORTED, "object of 2^29 voxels or more");
     if (prj >= 2147483647.0) return fail(SPECT_EUNSUPPORTED, "projection element count exceeds 2^31");
     if (g.nz >= (1 << 22)) return fail(SPECT_EUNSUPPORTED, "nz = %d is 2^22 or more", g.nz);
     std::vector<double> ang(g.n_angles), rad(g.n_angles);
@@ -945,7 +951,7 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
         int nb = 0;
         const void *fk = reinterpret_cast<const void *>(fwd_kernel(att == ATT_WRITE ? ATT_SAMPLE : att, p->kmc, true));
         allow_smem(fk, fwd_smem(p));
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk, block_threads(N), fwd_smem(p)) != hipSuccess)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk, fwd_threads(N), fwd_smem(p)) != hipSuccess)
             nb = 1;
         p->fwd_slots[att] = std::max(1, nb) * cus;
         const void *bk = reinterpret_cast<const void *>(back_kernel(att, p->kmc, true));
@@ -1396,7 +1402,7 @@ int bsrem_subset_step(const spect_plan *plan, float *f, const float *mu, const f
 // chosen by timing the candidates (osem_batch_autotune).
 
 struct BatchLaunch {
-    int threads = 0;
+    int fthreads = 0, bthreads = 0;  // forward and rotated-frame workgroup sizes
     size_t fsmem = 0, bsmem = 0, ssmem = 0;
     FwdBatchFn fk = nullptr;
     BackBatchFn bk = nullptr;
@@ -1486,7 +1492,7 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
     const std::vector<std::vector<Tuning>> &tuning = (sched & 4) ? b->tun1 : b->tun;
     // groups: members sharing block size and blur class, or all members
     std::vector<std::vector<int>> groups;
-    std::vector<int> gkmc, gthreads;
+    std::vector<int> gkmc;
     if (grouped) {
         std::vector<std::pair<std::pair<int, int>, int>> keys;
         for (int r = 0; r < b->R; ++r) keys.push_back({{block_threads(b->plans[r]->N), b->plans[r]->kmc}, r});
@@ -1495,19 +1501,13 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
         for (size_t i = 0; i < keys.size(); ++i) {
             if (i == 0 || keys[i].first != keys[i - 1].first) {
                 groups.emplace_back();
-                gthreads.push_back(keys[i].first.first);
                 gkmc.push_back(keys[i].first.second);
             }
             groups.back().push_back(keys[i].second);
         }
     } else {
         groups.emplace_back();
-        int th = 64;
-        for (int r = 0; r < b->R; ++r) {
-            groups.back().push_back(r);
-            th = std::max(th, block_threads(b->plans[r]->N));
-        }
-        gthreads.push_back(th);
+        for (int r = 0; r < b->R; ++r) groups.back().push_back(r);
         gkmc.push_back(b->kmc_max);
     }
     struct Offs {
@@ -1668,9 +1668,10 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
         for (size_t gi = 0; gi < groups.size(); ++gi) {
             const Offs &o = offs[m][gi];
             BatchLaunch l;
-            l.threads = gthreads[gi];
             int Nmax = 0;
             for (int r : groups[gi]) Nmax = std::max(Nmax, b->plans[r]->N);
+            l.fthreads = fwd_threads(Nmax);
+            l.bthreads = block_threads(Nmax);
             l.fsmem = fwd_smem(Nmax, gkmc[gi]);
             l.bsmem = back_smem(Nmax, gkmc[gi]);
             for (int r : groups[gi]) l.ssmem = std::max(l.ssmem, sens_smem(b->plans[r]->N, b->plans[r]->TS));
@@ -1694,11 +1695,11 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
             if (persist) {
                 int nb = 0;
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(l.fk),
-                                                                  l.threads, l.fsmem) != hipSuccess || nb < 1)
+                                                                  l.fthreads, l.fsmem) != hipSuccess || nb < 1)
                     nb = 1;
                 l.gf = std::max(1, std::min(o.nf, nb * b->cus));
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(l.bk),
-                                                                  l.threads, l.bsmem) != hipSuccess || nb < 1)
+                                                                  l.bthreads, l.bsmem) != hipSuccess || nb < 1)
                     nb = 1;
                 l.gb = std::max(1, std::min(o.nb, nb * b->cus));
                 l.gr = std::max(1, std::min(o.nr, 8 * b->cus));
@@ -1727,7 +1728,7 @@ int launch_step(const spect_batch *b, int m, hipStream_t st, bool capturing)
     for (const BatchLaunch &l : b->steps[m]) {
         {
             ProfScope ps(K_FWD_B, st, !capturing);
-            hipLaunchKernelGGL(l.fk, dim3(l.gf), dim3(l.threads), l.fsmem, st, l.fwd);
+            hipLaunchKernelGGL(l.fk, dim3(l.gf), dim3(l.fthreads), l.fsmem, st, l.fwd);
         }
         {
             ProfScope ps(K_REDUCE_B, st, !capturing);
@@ -1737,7 +1738,7 @@ int launch_step(const spect_batch *b, int m, hipStream_t st, bool capturing)
     for (const BatchLaunch &l : b->steps[m]) {
         {
             ProfScope ps(K_BACK_B, st, !capturing);
-            hipLaunchKernelGGL(l.bk, dim3(l.gb), dim3(l.threads), l.bsmem, st, l.back);
+            hipLaunchKernelGGL(l.bk, dim3(l.gb), dim3(l.bthreads), l.bsmem, st, l.back);
         }
         {
             ProfScope ps(K_GATHER_B, st, !capturing);

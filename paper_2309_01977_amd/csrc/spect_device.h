@@ -126,7 +126,7 @@ struct Corners {
 
 // Byte offsets of one volume row: rowb = 4 Nz (one z-run), per-thread axial
 // offsets dk0 / dk1 of its two quads of rows.  The plan guarantees that a
-// volume is below 4 GiB and that 4 Nz and N^2 fit 24 bits, so the offsets
+// volume is below 2 GiB and that 4 Nz and N^2 fit 24 bits, so the offsets
 // are formed with 24-bit multiplies and used as 32-bit offsets from the
 // (uniform) volume base.
 struct RowGeom {
@@ -393,37 +393,6 @@ __device__ __forceinline__ void load_taps(const float *__restrict__ g, float (&g
     for (int m = 0; m <= K; ++m) gk[m] = cg[m];
 }
 
-// Axial blur as a scatter: input row s (0..7) adds g(|l|) u[s] to output row
-// s + l, l in [-K, K]; acc[t] holds output row kb - KMC + t.
-template <int K, int KMC>
-__device__ __forceinline__ void zscatter(float (&acc)[ROWS + 2 * KMC], const float (&u)[ROWS],
-                                         const float (&gk)[K + 1])
-{
-#pragma unroll
-    for (int s = 0; s < ROWS; ++s)
-#pragma unroll
-        for (int l = -K; l <= K; ++l) acc[s + l + KMC] = fmaf(gk[l < 0 ? -l : l], u[s], acc[s + l + KMC]);
-}
-
-// Forward, after the row buffer of a depth is complete: bin-axis blur, then
-// the axial scatter into the partial rows, with one dispatch on the radius.
-template <int KMC>
-struct FwdBlur {
-    float (&acc)[ROWS + 2 * KMC];
-    const float (&w)[ROWS];
-    const float4 *wb;
-    int i0, i1;
-    const float *g;
-    template <int K>
-    __device__ __forceinline__ void go()
-    {
-        float gk[K + 1], u[ROWS];
-        load_taps<K>(g, gk);
-        blur_bins<K>(wb, i0, i1, gk, w, u);
-        zscatter<K, KMC>(acc, u, gk);
-    }
-};
-
 // Adjoint, bin-axis blur of the row buffer.
 struct BackBlur {
     const float (&v)[ROWS];
@@ -528,6 +497,25 @@ __device__ __forceinline__ void chunk_start(const float *__restrict__ tau, int a
 }
 
 // ------------------------------------------------------------- forward ----
+//
+// Forward lanes: FQ = 4 lanes per detector bin, lane q owning the FR = 4
+// axial rows 4q .. 4q+3 of the 16-row slab, so that a bilinear corner is one
+// 16-byte load per lane and the four lanes of a bin read its whole 64-byte
+// z-run.  Per depth a lane samples its rows (four corner loads), multiplies
+// by the attenuation factors (read one depth ahead from the table, or
+// formed from mu samples and a running sum), writes them to the row buffer,
+// and after one workgroup barrier blurs along the bins from LDS and scatters
+// the axial blur into its partial rows.
+
+constexpr int FQ = 4;
+constexpr int FR = SLAB / FQ;
+
+// Third descriptor word of a raw (unswizzled, unformatted) buffer resource on
+// gfx9-family GPUs.
+constexpr int kBufferDword3 = 0x00020000;
+// A byte offset past the end of every object volume a plan accepts (below
+// 2^29 voxels, 2 GiB): a raw buffer load there returns zeros.
+constexpr int kVolPastEnd = (int)0x80000000u;
 
 struct FwdArgs {
     DevGeom g;
@@ -541,125 +529,329 @@ struct FwdArgs {
     int vec;
 };
 
+// LDS row buffers of the forward: [buf][row j' + KMC][q] float4, two buffers
+// of nrows = N + 2 KMC rows (KMC zero rows on each side).
+__device__ __forceinline__ int fwb_index(int buf, int row, int q, int nrows) { return (buf * nrows + row) * FQ + q; }
+
+// Workgroup barrier that orders LDS accesses only: global loads in flight
+// stay in flight across it (__syncthreads() would also wait for them).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Bilinear corners of one sample: weights and byte offsets of the corners'
+// z-runs (plus the lane's row offset dk), for raw buffer loads over the
+// volume.  Such a load returns zeros past the end of the volume, and at
+// "negative" offsets, which are above 2^31 as unsigned; so a corner with x
+// outside [0, N) needs no test (its offset falls outside the volume for every
+// sample of a rotated grid, |X - c| <= sqrt(2) c), while a corner with y
+// outside [0, N) would alias a neighbouring column and gets the
+// past-the-end offset.  Corners outside the grid thus read zeros and keep
+// their weights.
+struct FCorner {
+    float w[4];
+    int o[4];
+};
+
+__device__ __forceinline__ FCorner fcorners(float X, float Y, int N, uint32_t rowb, uint32_t colb, uint32_t dk)
+{
+    const float xf = floorf(X), yf = floorf(Y);
+    const int x0 = (int)xf, y0 = (int)yf;
+    const float fx = X - xf, fy = Y - yf;
+    const float gx = 1.f - fx, gy = 1.f - fy;
+    FCorner r;
+    r.w[0] = gx * gy;
+    r.w[1] = fx * gy;
+    r.w[2] = gx * fy;
+    r.w[3] = fx * fy;
+    const uint32_t base = (uint32_t)(x0 * N + y0) * rowb + dk;
+    const bool vy0 = (unsigned)y0 < (unsigned)N, vy1 = (unsigned)(y0 + 1) < (unsigned)N;
+    r.o[0] = vy0 ? (int)base : kVolPastEnd;
+    r.o[1] = vy0 ? (int)(base + colb) : kVolPastEnd;
+    r.o[2] = vy1 ? (int)(base + rowb) : kVolPastEnd;
+    r.o[3] = vy1 ? (int)(base + colb + rowb) : kVolPastEnd;
+    return r;
+}
+
+// The lane's 4 rows of each corner.  Vector path: one 16-byte load per
+// corner (the row offset is in the corner offsets); scalar path: one load per
+// row at the clamped row offsets dks[r].
+template <bool VEC>
+__device__ __forceinline__ void fload(__amdgpu_buffer_rsrc_t rs, const FCorner &c, const int (&dks)[FR],
+                                      float4 (&v)[4])
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if constexpr (VEC) {
+            v[j] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, c.o[j], 0, 0));
+        } else {
+            float t[FR];
+#pragma unroll
+            for (int r = 0; r < FR; ++r)
+                t[r] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                     rs, (int)((uint32_t)c.o[j] + (uint32_t)dks[r]), 0, 0));
+            v[j] = make_float4(t[0], t[1], t[2], t[3]);
+        }
+    }
+}
+
+// Bilinear combination of the corners' rows.
+__device__ __forceinline__ float4 fcombine(const FCorner &c, const float4 (&v)[4])
+{
+    float4 r;
+    r.x = fmaf(c.w[3], v[3].x, fmaf(c.w[2], v[2].x, fmaf(c.w[1], v[1].x, c.w[0] * v[0].x)));
+    r.y = fmaf(c.w[3], v[3].y, fmaf(c.w[2], v[2].y, fmaf(c.w[1], v[1].y, c.w[0] * v[0].y)));
+    r.z = fmaf(c.w[3], v[3].z, fmaf(c.w[2], v[2].z, fmaf(c.w[1], v[1].z, c.w[0] * v[0].z)));
+    r.w = fmaf(c.w[3], v[3].w, fmaf(c.w[2], v[2].w, fmaf(c.w[1], v[1].w, c.w[0] * v[0].w)));
+    return r;
+}
+
+// Bin-axis blur of the lane's rows with a compile-time radius K (KSwitch
+// picks the code path per depth; the taps gz are already in registers), so
+// that every LDS read of the depth can be issued before the arithmetic:
+// U = g0 W(j') + sum_m g_m (W(j'-m) + W(j'+m)), i0 the lane's float4 of row
+// j' (bin stride FQ float4).
+template <int KMC>
+struct FBinBlur {
+    const float4 *wb;
+    int i0;
+    const float (&gz)[KMC + 1];
+    const float4 &self;
+    float (&u)[FR];
+    template <int K>
+    __device__ __forceinline__ void go()
+    {
+        u[0] = gz[0] * self.x;
+        u[1] = gz[0] * self.y;
+        u[2] = gz[0] * self.z;
+        u[3] = gz[0] * self.w;
+#pragma unroll
+        for (int m = 1; m <= K; ++m) {
+            const float4 a = wb[i0 - FQ * m], b = wb[i0 + FQ * m];
+            u[0] = fmaf(gz[m], a.x + b.x, u[0]);
+            u[1] = fmaf(gz[m], a.y + b.y, u[1]);
+            u[2] = fmaf(gz[m], a.z + b.z, u[2]);
+            u[3] = fmaf(gz[m], a.w + b.w, u[3]);
+        }
+    }
+};
+
+// Axial blur as a scatter, with the depth's radius K <= KMC at run time:
+// input row s (0..3) adds g(|l|) U[s] to output row s + l, |l| <= K;
+// acc[t] holds output row kb - KMC + t.  The guards are scalar branches (K
+// is uniform) and every accumulator is updated in place along one chain of
+// guarded blocks, with no code path per radius.
+template <int KMC>
+__device__ __forceinline__ void fzscatter(float (&acc)[FR + 2 * KMC], const float (&u)[FR], const float (&gz)[KMC + 1],
+                                          int K)
+{
+#pragma unroll
+    for (int s = 0; s < FR; ++s) acc[s + KMC] = fmaf(gz[0], u[s], acc[s + KMC]);
+#pragma unroll
+    for (int l = 1; l <= KMC; ++l) {
+        if (l > K) continue;
+#pragma unroll
+        for (int s = 0; s < FR; ++s) {
+            acc[s + KMC + l] = fmaf(gz[l], u[s], acc[s + KMC + l]);
+            acc[s + KMC - l] = fmaf(gz[l], u[s], acc[s + KMC - l]);
+        }
+    }
+}
+
+// The forward of one workgroup (angle, slab, depth chunk): the state that
+// lives across depths, and one depth.
+template <int ATT, int KMC, bool VEC>
+struct FwdWalk {
+    static constexpr bool MU = ATT == ATT_SAMPLE;
+    float4 *smem;
+    const float *taps;  // this angle's taps, TS per depth
+    int TS, N, Nz, jp, q, kb, nrows, ilo;
+    int dks[FR];
+    bool active, live, full;  // live: the lane has rows below Nz
+    float2 cs, o;
+    uint32_t rowb, colb, dk;
+    float tau_scale;
+    __amdgpu_buffer_rsrc_t rf, rm;
+    const float *tab;  // ATT_READ: the lane's 4 factors of depth 0
+    float acc[FR + 2 * KMC];
+    float S[FR];       // running attenuation sums (mu sampled)
+    float4 vt;         // attenuation factors of the current depth (table)
+    int buf;
+
+    __device__ __forceinline__ void tload(int ip)
+    {
+        vt = live ? stream_f4(tab + (size_t)ip * N * SLAB, 0u) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+
+    __device__ __forceinline__ float4 zero_past_nz(float4 v) const
+    {
+        if (!full) {
+            if (kb + 0 >= Nz) v.x = 0.f;
+            if (kb + 1 >= Nz) v.y = 0.f;
+            if (kb + 2 >= Nz) v.z = 0.f;
+            if (kb + 3 >= Nz) v.w = 0.f;
+        }
+        return v;
+    }
+
+    // depth ip of radius K
+    __device__ __forceinline__ void depth(int ip, int K)
+    {
+        float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (active) {
+            const FCorner cn = fcorners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, rowb, colb,
+                                        VEC ? dk : 0u);
+            float4 vf[4], vm[4];
+            fload<VEC>(rf, cn, dks, vf);
+            if (MU) fload<VEC>(rm, cn, dks, vm);
+            w = zero_past_nz(fcombine(cn, vf));
+            if (ATT == ATT_READ) {
+                w.x *= vt.x;
+                w.y *= vt.y;
+                w.z *= vt.z;
+                w.w *= vt.w;
+                // the next depth's factors, in flight during this blur
+                if (ip > ilo) tload(ip - 1);
+            }
+            if (MU) {
+                const float4 m = zero_past_nz(fcombine(cn, vm));
+                const float mm[FR] = {m.x, m.y, m.z, m.w};
+                float at[FR];
+#pragma unroll
+                for (int r = 0; r < FR; ++r) {
+                    at[r] = __builtin_amdgcn_exp2f(-tau_scale * fmaf(0.5f, mm[r], S[r]));
+                    S[r] += mm[r];
+                }
+                w.x *= at[0];
+                w.y *= at[1];
+                w.z *= at[2];
+                w.w *= at[3];
+            }
+            smem[fwb_index(buf, jp + KMC, q, nrows)] = w;
+        }
+        // the depth's taps, loaded while the workgroup gathers at the barrier
+        // (indices past the plan's radius read zeros, or the next depth's taps
+        // when a batched member's radius class is below KMC; the guards never
+        // use them)
+        float gz[KMC + 1];
+        {
+            ConstMem<float> *cg = as_const(taps + (size_t)ip * TS);
+#pragma unroll
+            for (int l = 0; l <= KMC; ++l) gz[l] = cg[l];
+        }
+        lds_barrier();
+        if (active) {
+            float u[FR];
+            FBinBlur<KMC> bb{smem, fwb_index(buf, jp + KMC, q, nrows), gz, w, u};
+            KSwitch<0, KMC>::run(K, bb);
+            fzscatter<KMC>(acc, u, gz, K);
+        }
+        buf ^= 1;
+    }
+};
+
 template <int ATT, int KMC, bool VEC, class Args>
 __device__ __forceinline__ void fwd_body(const Args &a, int slab, int chunk, int al)
 {
     static_assert(ATT != ATT_WRITE, "the forward kernel does not write the table");
     constexpr bool MU = ATT == ATT_SAMPLE;
+    constexpr int R = SLAB + 2 * KMC;  // the slab's partial rows
     extern __shared__ float4 smem[];
+    FwdWalk<ATT, KMC, VEC> w;
     const int N = a.g.N, Nz = a.g.Nz;
     const int ang = a.L.idx[al];
-    const int jp = threadIdx.x >> 1, h = threadIdx.x & 1;
-    const bool active = jp < N;
-    const int nrows = N + 2 * KMC;
-    const int kb = slab * SLAB + h * ROWS;
-    const bool full = slab * SLAB + SLAB <= Nz;  // no rows past Nz in this slab
+    w.smem = smem;
+    w.N = N;
+    w.Nz = Nz;
+    w.TS = a.g.TS;
+    w.taps = a.g.taps + (size_t)ang * N * a.g.TS;
+    w.jp = threadIdx.x / FQ;
+    w.q = threadIdx.x % FQ;
+    w.active = w.jp < N;
+    w.nrows = N + 2 * KMC;
+    w.kb = slab * SLAB + w.q * FR;
+    w.live = w.active && w.kb < Nz;
+    w.full = slab * SLAB + SLAB <= Nz;  // no rows past Nz in this slab
+    w.tau_scale = a.g.tau_scale;
 
-    zero_padding<KMC>(smem, N, nrows);
+    // zero the KMC padding rows of both buffers
+    if constexpr (KMC > 0) {
+        for (int i = threadIdx.x; i < 2 * 2 * KMC * FQ; i += blockDim.x) {
+            const int qq = i % FQ, rest = i / FQ;
+            const int prow = rest % (2 * KMC), bb = rest / (2 * KMC);
+            smem[fwb_index(bb, prow < KMC ? prow : prow + N, qq, w.nrows)] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
 
-    const float2 cs = a.g.cs[ang];
-    const float2 o = active ? a.g.xy0[(size_t)ang * N + jp] : make_float2(0.f, 0.f);
-    float S[ROWS];
+    w.cs = a.g.cs[ang];
+    w.o = w.active ? a.g.xy0[(size_t)ang * N + w.jp] : make_float2(0.f, 0.f);
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) S[r] = 0.f;
-    if (MU && chunk > 0 && active) chunk_start(a.tau, al, a.nchunk, chunk, N, Nz, jp, kb, S);
-    float acc[ROWS + 2 * KMC];
+    for (int r = 0; r < FR; ++r) w.S[r] = 0.f;
+    if (MU && chunk > 0 && w.active) {
+        for (int c = 0; c < chunk; ++c) {
+            const float *src = a.tau + (((size_t)al * a.nchunk + c) * N + w.jp) * Nz;
 #pragma unroll
-    for (int t = 0; t < ROWS + 2 * KMC; ++t) acc[t] = 0.f;
+            for (int r = 0; r < FR; ++r) w.S[r] += (w.kb + r < Nz) ? src[w.kb + r] : 0.f;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < FR + 2 * KMC; ++t) w.acc[t] = 0.f;
 
     int ihi, ilo;
     chunk_range(a.g, a.cbset, a.nchunk, ang, chunk, ihi, ilo);
     ConstMem<int> *kd = as_const(a.g.kdep + (size_t)ang * N);
-    const RowGeom rg = row_geom(kb, Nz);
-    // attenuation table: uniform base of this (angle, slab) + per-thread offset
-    const float *tab = ATT == ATT_READ ? a.att + brick_offset(al, a.nslab, slab, N, 0, 0) : nullptr;
-    const uint32_t toff = 4u * (uint32_t)(jp * SLAB + h * ROWS);
-    int buf = 0;
-    __syncthreads();
-    for (int ip = ihi; ip >= ilo; --ip) {
-        const int K = kd[ip];
-        const float *gt = a.g.taps + ((size_t)ang * N + ip) * a.g.TS;
-        float w[ROWS];
-        if (active) {
-            // this depth's loads go out at raised priority, so they are in
-            // flight while the other waves of the SIMD blur
-            __builtin_amdgcn_s_setprio(2);
-            const Corners cn = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, rg.rowb);
-            Raw rf, rm;
-            float4 t0, t1;
-            load_raw<VEC>(a.f, cn, rg, kb, Nz, rf);
-            if (MU) load_raw<VEC>(a.mu, cn, rg, kb, Nz, rm);
-            if (ATT == ATT_READ) {
-                const float *trow = tab + (size_t)ip * N * SLAB;
-                t0 = stream_f4(trow, toff);
-                t1 = stream_f4(trow, toff + 16);
-            }
-            __builtin_amdgcn_s_setprio(0);
-            combine(rf, cn, kb, Nz, w, full);
-            if (ATT == ATT_READ) {
-                w[0] *= t0.x;
-                w[1] *= t0.y;
-                w[2] *= t0.z;
-                w[3] *= t0.w;
-                w[4] *= t1.x;
-                w[5] *= t1.y;
-                w[6] *= t1.z;
-                w[7] *= t1.w;
-            }
-            if (MU) {
-                float m[ROWS], att[ROWS];
-                combine(rm, cn, kb, Nz, m, full);
-                attenuate(m, S, a.g.tau_scale, att);
+    w.ilo = ilo;
+    w.rowb = 4u * (uint32_t)Nz;
+    w.colb = w.rowb * (uint32_t)N;
+    // row offsets in a z-run (clamped to valid rows; rows past Nz are zeroed)
+    w.dk = 4u * (uint32_t)max(min(w.kb, Nz - 4), 0);
 #pragma unroll
-                for (int r = 0; r < ROWS; ++r) w[r] *= att[r];
-            }
-            smem[wb_index(buf, 0, jp + KMC, h, nrows)] = make_float4(w[0], w[1], w[2], w[3]);
-            smem[wb_index(buf, 1, jp + KMC, h, nrows)] = make_float4(w[4], w[5], w[6], w[7]);
+    for (int r = 0; r < FR; ++r) w.dks[r] = 4 * min(w.kb + r, Nz - 1);
+    const int vbytes = (int)(w.colb * (uint32_t)N);
+    w.rf = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(a.f), (short)0, vbytes, kBufferDword3);
+    w.rm = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(MU ? a.mu : a.f), (short)0, vbytes, kBufferDword3);
+    // attenuation table: the lane's rows in the 16-row brick of (angle, slab,
+    // depth 0, bin j')
+    w.tab = ATT == ATT_READ && w.live ? a.att + brick_offset(al, a.nslab, slab, N, 0, w.jp) + w.q * FR : nullptr;
+    w.buf = 0;
+    if (ATT == ATT_READ && w.active && ihi >= ilo) w.tload(ihi);
+    __syncthreads();
+    for (int ip = ihi; ip >= ilo; --ip) w.depth(ip, kd[ip]);
+
+    // merge the four lanes of each bin in LDS ([N][R], lane q's row t is the
+    // slab's partial row 4q + t; lanes added in order q = 0..3), then store
+    // the slab's partial rows with coalesced 16-byte stores
+    float *mb = reinterpret_cast<float *>(smem);
+    __syncthreads();
+    for (int i = threadIdx.x; i < N * R; i += blockDim.x) mb[i] = 0.f;
+    __syncthreads();
+#pragma unroll
+    for (int qq = 0; qq < FQ; ++qq) {
+        if (w.active && w.q == qq) {
+#pragma unroll
+            for (int t = 0; t < FR + 2 * KMC; ++t) mb[w.jp * R + FR * qq + t] += w.acc[t];
         }
         __syncthreads();
-        if (active) {
-            FwdBlur<KMC> op{acc, w, smem, wb_index(buf, 0, jp + KMC, h, nrows), wb_index(buf, 1, jp + KMC, h, nrows),
-                            gt};
-            KSwitch<0, KMC>::run(K, op);
-        }
-        buf ^= 1;
     }
-
-    // merge the two half-slabs of each bin and write the partial rows
-    __syncthreads();
-    float *mb = reinterpret_cast<float *>(smem);
-    constexpr int AC = ROWS + 2 * KMC;
-    constexpr int R = SLAB + 2 * KMC;
-    if (active && h == 1) {
-#pragma unroll
-        for (int t = 0; t < AC; ++t) mb[jp * (AC + 1) + t] = acc[t];
-    }
-    __syncthreads();
-    if (active && h == 0) {
-        float *dst = a.part + ((((size_t)al * a.nslab + slab) * a.nchunk + chunk) * N + jp) * R;
-#pragma unroll
-        for (int t = 0; t < R; t += 4) {
-            float v[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int tt = t + e;
-                float x = (tt < AC) ? acc[tt < AC ? tt : 0] : 0.f;
-                if (tt >= ROWS) x += mb[jp * (AC + 1) + tt - ROWS];
-                v[e] = x;
-            }
-            *reinterpret_cast<float4 *>(dst + t) = make_float4(v[0], v[1], v[2], v[3]);
-        }
-    }
+    float4 *dst = reinterpret_cast<float4 *>(a.part + (((size_t)al * a.nslab + slab) * a.nchunk + chunk) * N * R);
+    const float4 *src = reinterpret_cast<const float4 *>(mb);
+    for (int i = threadIdx.x; i < N * R / 4; i += blockDim.x) dst[i] = src[i];
 }
 
+// Largest forward workgroup: FQ lanes per bin, N <= 256.
+constexpr int FWD_MAX_THREADS = FQ * 256;
+
 template <int ATT, int KMC, bool VEC>
-__global__ __launch_bounds__(512) void fwd_main(FwdArgs a)
+__global__ __launch_bounds__(FWD_MAX_THREADS) void fwd_main(FwdArgs a)
 {
     fwd_body<ATT, KMC, VEC>(a, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 template <int ATT, int KMC, bool VEC, bool PERSIST>
-__global__ __launch_bounds__(512) void fwd_batch(BatchList<FwdArgs> b)
+__global__ __launch_bounds__(FWD_MAX_THREADS) void fwd_batch(BatchList<FwdArgs> b)
 {
     ConstMem<FwdArgs> *args = as_const(b.args);
     ConstMem<Task> *tasks = as_const(b.tasks);
@@ -1091,13 +1283,11 @@ constexpr int GT = 8;  // gather tile edge
 constexpr int GS = 2;  // slabs per gather workgroup
 
 #ifdef SPECT_HOST_TU
-// Value of lane `src` of this lane's quad (all four lanes active).
-// Third descriptor word of a raw (unswizzled, unformatted) buffer resource on
-// gfx9-family GPUs; a byte offset of kPastEnd lies beyond every buffer built
-// here, so a load there returns zeros.
-constexpr int kBufferDword3 = 0x00020000;
+// A byte offset of kPastEnd lies beyond every rotated-frame buffer the gather
+// reads (at most two 4 MiB planes), so a raw buffer load there returns zeros.
 constexpr int kPastEnd = 0x40000000;
 
+// Value of lane `src` of this lane's quad (all four lanes active).
 template <int SRC>
 __device__ __forceinline__ int quad_bcast(int v)
 {

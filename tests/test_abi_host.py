@@ -45,8 +45,9 @@ def _geom(**kw):
     (dict(voxel_cm=float("nan")), B.SPECT_EINVAL), (dict(psf_a=-1.0), B.SPECT_EINVAL),
     (dict(psf_b=float("inf")), B.SPECT_EINVAL), (dict(n=257), B.SPECT_EUNSUPPORTED),
     (dict(psf_a=1.0), B.SPECT_EUNSUPPORTED),
-    # 32-bit byte offsets: an object of 2^30 voxels is refused, one voxel less is not
-    (dict(n=256, nz=16384, n_angles=1), B.SPECT_EUNSUPPORTED),
+    # 32-bit byte offsets with a past-the-end offset of 2 GiB: an object of
+    # 2^29 voxels is refused
+    (dict(n=256, nz=8192, n_angles=1), B.SPECT_EUNSUPPORTED),
     (dict(n=1, nz=1 << 22, n_angles=1), B.SPECT_EUNSUPPORTED),
 ])
 def test_plan_create_rejects_invalid_geometry(kw, code):
