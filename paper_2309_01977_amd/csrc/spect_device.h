@@ -8,14 +8,14 @@
 // discretisation and the array layouts.
 //
 // Parallel decomposition (one launch covers a list of angles):
-//   workgroup = (angle, axial slab of 16 slices, depth chunk); thread (j', h)
-//   owns detector bin j' and axial rows 8h..8h+7 of the slab and walks the
-//   depth axis of its chunk from the detector side.  Per depth it samples the
-//   object (four bilinear corners, each a contiguous z-run), updates its
-//   running attenuation sum, blurs along the bin axis through LDS (the
-//   neighbouring bins belong to other threads), and scatters the axial blur
-//   of its own eight rows into registers that hold the slab's partial
-//   projection rows.  A reduction kernel adds the partial rows of
+//   workgroup = (angle, axial slab of 16 slices, depth chunk); in the forward
+//   four lanes share detector bin j', lane q owning axial rows 4q..4q+3 of
+//   the slab, and walk the depth axis of their chunk from the detector side.
+//   Per depth a lane samples the object (four bilinear corners, each a
+//   contiguous z-run), applies the attenuation factors, blurs along the bin
+//   axis through LDS (the neighbouring bins belong to other lanes), and
+//   scatters the axial blur of its rows into registers that hold the slab's
+//   partial projection rows.  A reduction kernel adds the partial rows of
 //   neighbouring slabs and of the depth chunks.
 //   Depth chunks raise parallelism for small angle subsets; their
 //   attenuation offsets come from a pre-pass that walks each ray once.
@@ -124,24 +124,6 @@ struct Corners {
     float w00, w10, w01, w11;     // bilinear weights, 0 for corners outside the grid
 };
 
-// Byte offsets of one volume row: rowb = 4 Nz (one z-run), per-thread axial
-// offsets dk0 / dk1 of its two quads of rows.  The plan guarantees that a
-// volume is below 2 GiB and that 4 Nz and N^2 fit 24 bits, so the offsets
-// are formed with 24-bit multiplies and used as 32-bit offsets from the
-// (uniform) volume base.
-struct RowGeom {
-    uint32_t rowb, dk0, dk1;
-};
-
-__device__ __forceinline__ RowGeom row_geom(int kb, int Nz)
-{
-    RowGeom r;
-    r.rowb = 4u * (uint32_t)Nz;
-    r.dk0 = 4u * (uint32_t)max(min(kb, Nz - 4), 0);
-    r.dk1 = 4u * (uint32_t)max(min(kb + 4, Nz - 4), 0);
-    return r;
-}
-
 // Bilinear footprint of point (X, Y) in an N x N slice of z-runs.
 __device__ __forceinline__ Corners corners(float X, float Y, int N, uint32_t rowb)
 {
@@ -174,6 +156,88 @@ __device__ __forceinline__ const T &at_byte(const float *base, uint32_t off)
     return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
 }
 
+// Third descriptor word of a raw (unswizzled, unformatted) buffer resource on
+// gfx9-family GPUs.
+constexpr int kBufferDword3 = 0x00020000;
+// A byte offset past the end of every object volume a plan accepts (below
+// 2^29 voxels, 2 GiB): a raw buffer load there returns zeros.
+constexpr int kVolPastEnd = (int)0x80000000u;
+
+// Bilinear corners of one sample: weights and byte offsets of the corners'
+// z-runs (plus the lane's row offset dk), for raw buffer loads over the
+// volume.  Such a load returns zeros past the end of the volume, and at
+// "negative" offsets, which are above 2^31 as unsigned; so a corner with x
+// outside [0, N) needs no test (its offset falls outside the volume for every
+// sample of a rotated grid, |X - c| <= sqrt(2) c), while a corner with y
+// outside [0, N) would alias a neighbouring column and gets the
+// past-the-end offset.  Corners outside the grid thus read zeros and keep
+// their weights.
+struct FCorner {
+    float w[4];
+    int o[4];
+};
+
+__device__ __forceinline__ FCorner fcorners(float X, float Y, int N, uint32_t rowb, uint32_t colb, uint32_t dk)
+{
+    const float xf = floorf(X), yf = floorf(Y);
+    const int x0 = (int)xf, y0 = (int)yf;
+    const float fx = X - xf, fy = Y - yf;
+    const float gx = 1.f - fx, gy = 1.f - fy;
+    FCorner r;
+    r.w[0] = gx * gy;
+    r.w[1] = fx * gy;
+    r.w[2] = gx * fy;
+    r.w[3] = fx * fy;
+    const uint32_t base = (uint32_t)(x0 * N + y0) * rowb + dk;
+    const bool vy0 = (unsigned)y0 < (unsigned)N, vy1 = (unsigned)(y0 + 1) < (unsigned)N;
+    r.o[0] = vy0 ? (int)base : kVolPastEnd;
+    r.o[1] = vy0 ? (int)(base + colb) : kVolPastEnd;
+    r.o[2] = vy1 ? (int)(base + rowb) : kVolPastEnd;
+    r.o[3] = vy1 ? (int)(base + colb + rowb) : kVolPastEnd;
+    return r;
+}
+
+// The lane's rows kb .. kb+7 of the four corners: two 16-byte loads per
+// corner (vector path, row offset in the corner offsets; rows past Nz read
+// the next column or zeros) or one load per row at the clamped offsets dks.
+template <bool VEC>
+__device__ __forceinline__ void fload8(__amdgpu_buffer_rsrc_t rs, const FCorner &c, const int (&dks)[8],
+                                       float4 (&v)[4][2])
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if constexpr (VEC) {
+            v[j][0] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, c.o[j], 0, 0));
+            v[j][1] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                     rs, (int)((uint32_t)c.o[j] + 16u), 0, 0));
+        } else {
+            float t[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                t[r] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                     rs, (int)((uint32_t)c.o[j] + (uint32_t)dks[r]), 0, 0));
+            v[j][0] = make_float4(t[0], t[1], t[2], t[3]);
+            v[j][1] = make_float4(t[4], t[5], t[6], t[7]);
+        }
+    }
+}
+
+// Bilinear combination of 8 rows; rows at or past Nz give 0.
+__device__ __forceinline__ void fcombine8(const FCorner &c, const float4 (&v)[4][2], int kb, int Nz, float (&m)[8])
+{
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+        m[4 * hh + 0] = fmaf(c.w[3], v[3][hh].x, fmaf(c.w[2], v[2][hh].x, fmaf(c.w[1], v[1][hh].x, c.w[0] * v[0][hh].x)));
+        m[4 * hh + 1] = fmaf(c.w[3], v[3][hh].y, fmaf(c.w[2], v[2][hh].y, fmaf(c.w[1], v[1][hh].y, c.w[0] * v[0][hh].y)));
+        m[4 * hh + 2] = fmaf(c.w[3], v[3][hh].z, fmaf(c.w[2], v[2][hh].z, fmaf(c.w[1], v[1][hh].z, c.w[0] * v[0][hh].z)));
+        m[4 * hh + 3] = fmaf(c.w[3], v[3][hh].w, fmaf(c.w[2], v[2][hh].w, fmaf(c.w[1], v[1][hh].w, c.w[0] * v[0][hh].w)));
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+        if (kb + r >= Nz) m[r] = 0.f;
+}
+
+
 // The attenuation table is streamed: a pass reads (or the sensitivity pass
 // writes) every entry once, and the next pass to touch it comes after other
 // kernels.  The forward's reads and the sensitivity pass's writes are
@@ -199,110 +263,6 @@ __device__ __forceinline__ void stream_store_f4(float *p, float a, float b, floa
 __device__ __forceinline__ void stream_store_f2(float *p, float a, float b)
 {
     __builtin_nontemporal_store(f2_t{a, b}, reinterpret_cast<f2_t *>(p));
-}
-
-// Raw corner values of ROWS axial rows starting at kb: v[corner][row] for the
-// corners (x0,y0), (x0+1,y0), (x0,y0+1), (x0+1,y0+1).  Rows past Nz read a
-// clamped, valid address and are zeroed when combined.  Vector path:
-// Nz % 4 == 0 and a 16-byte aligned volume.
-struct Raw {
-    float v[4][ROWS];
-};
-
-// A corner whose bilinear weight is 0 (outside the grid) is not loaded and
-// reads as 0, so the samples of a rotated grid that fall outside the object
-// (up to 17 % of them, at 45 degrees) cost no gathered loads; the loads of
-// the other corners are all issued before any is used.
-template <bool VEC>
-__device__ __forceinline__ void load_raw(const float *__restrict__ vol, const Corners &c, const RowGeom &rg, int kb,
-                                         int Nz, Raw &r)
-{
-    const uint32_t o[4] = {c.b00, c.b10, c.b01, c.b11};
-    const float wt[4] = {c.w00, c.w10, c.w01, c.w11};
-    if constexpr (VEC) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            float4 t0 = make_float4(0.f, 0.f, 0.f, 0.f), t1 = t0;
-            if (wt[j] != 0.f) {
-                t0 = at_byte<float4>(vol, o[j] + rg.dk0);
-                t1 = at_byte<float4>(vol, o[j] + rg.dk1);
-            }
-            r.v[j][0] = t0.x;
-            r.v[j][1] = t0.y;
-            r.v[j][2] = t0.z;
-            r.v[j][3] = t0.w;
-            r.v[j][4] = t1.x;
-            r.v[j][5] = t1.y;
-            r.v[j][6] = t1.z;
-            r.v[j][7] = t1.w;
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-#pragma unroll
-            for (int rr = 0; rr < ROWS; ++rr) r.v[j][rr] = 0.f;
-            if (wt[j] != 0.f) {
-#pragma unroll
-                for (int rr = 0; rr < ROWS; ++rr)
-                    r.v[j][rr] = at_byte<float>(vol, o[j] + 4u * (uint32_t)min(kb + rr, Nz - 1));
-            }
-        }
-    }
-}
-
-// Bilinear combination of raw corner values; rows >= Nz give 0.
-__device__ __forceinline__ void combine(const Raw &r, const Corners &c, int kb, int Nz, float (&v)[ROWS],
-                                        bool full = false)
-{
-#pragma unroll
-    for (int rr = 0; rr < ROWS; ++rr)
-        v[rr] = fmaf(c.w11, r.v[3][rr], fmaf(c.w01, r.v[2][rr], fmaf(c.w10, r.v[1][rr], c.w00 * r.v[0][rr])));
-    if (!full) {
-#pragma unroll
-        for (int rr = 0; rr < ROWS; ++rr)
-            if (kb + rr >= Nz) v[rr] = 0.f;
-    }
-}
-
-// Every corner loaded unconditionally (the attenuation pre-pass, which keeps
-// two depths of loads in flight: masking its loads would raise it from 60 to
-// 97 VGPRs).
-template <bool VEC>
-__device__ __forceinline__ void load_raw_all(const float *__restrict__ vol, const Corners &c, const RowGeom &rg,
-                                             int kb, int Nz, Raw &r)
-{
-    const uint32_t o[4] = {c.b00, c.b10, c.b01, c.b11};
-    if constexpr (VEC) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const float4 t0 = at_byte<float4>(vol, o[j] + rg.dk0);
-            const float4 t1 = at_byte<float4>(vol, o[j] + rg.dk1);
-            r.v[j][0] = t0.x;
-            r.v[j][1] = t0.y;
-            r.v[j][2] = t0.z;
-            r.v[j][3] = t0.w;
-            r.v[j][4] = t1.x;
-            r.v[j][5] = t1.y;
-            r.v[j][6] = t1.z;
-            r.v[j][7] = t1.w;
-        }
-    } else {
-#pragma unroll
-        for (int rr = 0; rr < ROWS; ++rr) {
-            const uint32_t k = 4u * (uint32_t)min(kb + rr, Nz - 1);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) r.v[j][rr] = at_byte<float>(vol, o[j] + k);
-        }
-    }
-}
-
-template <bool VEC>
-__device__ __forceinline__ void sample_rows(const float *__restrict__ vol, const Corners &c, const RowGeom &rg,
-                                            int kb, int Nz, float (&v)[ROWS])
-{
-    Raw r;
-    load_raw_all<VEC>(vol, c, rg, kb, Nz, r);
-    combine(r, c, kb, Nz, v);
 }
 
 // Attenuation factors for one depth: exp(-dx (mu/2 + sum beyond)), then add
@@ -361,10 +321,11 @@ struct KSwitch {
 // U = g0 W(j') + sum_m g_m (W(j'-m) + W(j'+m)); i0/i1 index the thread's two
 // float4 of row j' in the row buffer (row stride 2 float4), so every read
 // uses an immediate offset.
-template <int K>
-__device__ __forceinline__ void blur_bins(const float4 *__restrict__ wb, int i0, int i1, const float (&gk)[K + 1],
+template <int K, int G>
+__device__ __forceinline__ void blur_bins(const float4 *__restrict__ wb, int i0, int i1, const float (&gk)[G],
                                           const float (&self)[ROWS], float (&u)[ROWS])
 {
+    static_assert(K < G, "taps past the radius");
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) u[r] = gk[0] * self[r];
 #pragma unroll
@@ -385,36 +346,37 @@ __device__ __forceinline__ void blur_bins(const float4 *__restrict__ wb, int i0,
 // The plan's tables (radii, taps, tap sums) never change once built, so the
 // kernels read them through the constant address space: uniform reads are
 // then scalar loads even in loops that also store to global memory.
-template <int K>
-__device__ __forceinline__ void load_taps(const float *__restrict__ g, float (&gk)[K + 1])
+template <int KMC>
+__device__ __forceinline__ void load_taps_all(const float *__restrict__ g, float (&gz)[KMC + 1])
 {
     ConstMem<float> *cg = as_const(g);
 #pragma unroll
-    for (int m = 0; m <= K; ++m) gk[m] = cg[m];
+    for (int m = 0; m <= KMC; ++m) gz[m] = cg[m];
 }
 
-// Adjoint, bin-axis blur of the row buffer.
+// Adjoint, bin-axis blur of the row buffer (taps gz in registers).
+template <int KMC>
 struct BackBlur {
     const float (&v)[ROWS];
     float (&u)[ROWS];
     const float4 *wb;
     int i0, i1;
-    const float *g;
+    const float (&gz)[KMC + 1];
     template <int K>
     __device__ __forceinline__ void go()
     {
-        float gk[K + 1];
-        load_taps<K>(g, gk);
-        blur_bins<K>(wb, i0, i1, gk, v, u);
+        blur_bins<K>(wb, i0, i1, gz, v, u);
     }
 };
 
 // Axial blur as a gather from a column of LDS values: col[base - K + t] is
-// axial row kb - K + t; out[s] = sum_l g(|l|) win[s + K - l].
+// axial row kb - K + t; out[s] = sum_l g(|l|) win[s + K - l] (taps gz in
+// registers).
+template <int KMC>
 struct ZGather {
     const float *col;
     int base;
-    const float *g;
+    const float (&gz)[KMC + 1];
     float (&out)[ROWS];
     template <int K>
     __device__ __forceinline__ void go()
@@ -423,13 +385,11 @@ struct ZGather {
         float v[ROWS + 2 * K];
 #pragma unroll
         for (int t = 0; t < ROWS + 2 * K; ++t) v[t] = win[t];
-        float gk[K + 1];
-        load_taps<K>(g, gk);
 #pragma unroll
         for (int s = 0; s < ROWS; ++s) {
-            float a = gk[0] * v[s + K];
+            float a = gz[0] * v[s + K];
 #pragma unroll
-            for (int l = 1; l <= K; ++l) a = fmaf(gk[l], v[s + K - l] + v[s + K + l], a);
+            for (int l = 1; l <= K; ++l) a = fmaf(gz[l], v[s + K - l] + v[s + K + l], a);
             out[s] = a;
         }
     }
@@ -467,12 +427,20 @@ __global__ __launch_bounds__(256) void tau_prepass(TauArgs a)
     for (int r = 0; r < ROWS; ++r) S[r] = 0.f;
     int ihi, ilo;
     chunk_range(a.g, a.cbset, a.nchunk, ang, ch, ihi, ilo);
-    const RowGeom rg = row_geom(kb, Nz);
+    const uint32_t rowb = 4u * (uint32_t)Nz, colb = rowb * (uint32_t)N;
+    int dks[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) dks[r] = 4 * min(kb + r, Nz - 1);
+    const __amdgpu_buffer_rsrc_t rm = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(a.mu), (short)0,
+                                                                        (int)(colb * (uint32_t)N), kBufferDword3);
 #pragma unroll 2
     for (int ip = ihi; ip >= ilo; --ip) {
-        const Corners c = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, rg.rowb);
+        const FCorner c = fcorners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, rowb, colb,
+                                   VEC ? 4u * (uint32_t)kb : 0u);
+        float4 v[4][2];
+        fload8<VEC>(rm, c, dks, v);
         float m[ROWS];
-        sample_rows<VEC>(a.mu, c, rg, kb, Nz, m);
+        fcombine8(c, v, kb, Nz, m);
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) S[r] += m[r];
     }
@@ -510,13 +478,6 @@ __device__ __forceinline__ void chunk_start(const float *__restrict__ tau, int a
 constexpr int FQ = 4;
 constexpr int FR = SLAB / FQ;
 
-// Third descriptor word of a raw (unswizzled, unformatted) buffer resource on
-// gfx9-family GPUs.
-constexpr int kBufferDword3 = 0x00020000;
-// A byte offset past the end of every object volume a plan accepts (below
-// 2^29 voxels, 2 GiB): a raw buffer load there returns zeros.
-constexpr int kVolPastEnd = (int)0x80000000u;
-
 struct FwdArgs {
     DevGeom g;
     AngleList L;
@@ -540,40 +501,6 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// Bilinear corners of one sample: weights and byte offsets of the corners'
-// z-runs (plus the lane's row offset dk), for raw buffer loads over the
-// volume.  Such a load returns zeros past the end of the volume, and at
-// "negative" offsets, which are above 2^31 as unsigned; so a corner with x
-// outside [0, N) needs no test (its offset falls outside the volume for every
-// sample of a rotated grid, |X - c| <= sqrt(2) c), while a corner with y
-// outside [0, N) would alias a neighbouring column and gets the
-// past-the-end offset.  Corners outside the grid thus read zeros and keep
-// their weights.
-struct FCorner {
-    float w[4];
-    int o[4];
-};
-
-__device__ __forceinline__ FCorner fcorners(float X, float Y, int N, uint32_t rowb, uint32_t colb, uint32_t dk)
-{
-    const float xf = floorf(X), yf = floorf(Y);
-    const int x0 = (int)xf, y0 = (int)yf;
-    const float fx = X - xf, fy = Y - yf;
-    const float gx = 1.f - fx, gy = 1.f - fy;
-    FCorner r;
-    r.w[0] = gx * gy;
-    r.w[1] = fx * gy;
-    r.w[2] = gx * fy;
-    r.w[3] = fx * fy;
-    const uint32_t base = (uint32_t)(x0 * N + y0) * rowb + dk;
-    const bool vy0 = (unsigned)y0 < (unsigned)N, vy1 = (unsigned)(y0 + 1) < (unsigned)N;
-    r.o[0] = vy0 ? (int)base : kVolPastEnd;
-    r.o[1] = vy0 ? (int)(base + colb) : kVolPastEnd;
-    r.o[2] = vy1 ? (int)(base + rowb) : kVolPastEnd;
-    r.o[3] = vy1 ? (int)(base + colb + rowb) : kVolPastEnd;
-    return r;
 }
 
 // The lane's 4 rows of each corner.  Vector path: one 16-byte load per
@@ -737,11 +664,7 @@ struct FwdWalk {
         // when a batched member's radius class is below KMC; the guards never
         // use them)
         float gz[KMC + 1];
-        {
-            ConstMem<float> *cg = as_const(taps + (size_t)ip * TS);
-#pragma unroll
-            for (int l = 0; l <= KMC; ++l) gz[l] = cg[l];
-        }
+        load_taps_all<KMC>(taps + (size_t)ip * TS, gz);
         lds_barrier();
         if (active) {
             float u[FR];
@@ -968,7 +891,6 @@ __device__ __forceinline__ void back_body(const Args &a, int slab, int chunk, in
     const int nrows = N + 2 * KMC;
     const int k0 = slab * SLAB;
     const int kb = k0 + h * ROWS;
-    const bool full = k0 + SLAB <= Nz;  // no rows past Nz in this slab
     constexpr int R = SLAB + 2 * KMC;
     constexpr int YP = R + 1;
     float *ybuf = reinterpret_cast<float *>(smem + 2 * 2 * nrows * 2);
@@ -998,7 +920,17 @@ __device__ __forceinline__ void back_body(const Args &a, int slab, int chunk, in
     int ihi, ilo;
     chunk_range(a.g, a.cbset, a.nchunk, ang, chunk, ihi, ilo);
     ConstMem<int> *kd = as_const(a.g.kdep + (size_t)ang * N);
-    const RowGeom rg = row_geom(kb, Nz);
+    const float *taps = a.g.taps + (size_t)ang * N * a.g.TS;
+    // mu corners: raw buffer loads over the map (see fcorners); the vector
+    // path reads the lane's 8 rows as two 16-byte loads per corner (rows past
+    // Nz read the next column or zeros, and are zeroed below)
+    const uint32_t rowb = 4u * (uint32_t)Nz, colb = rowb * (uint32_t)N;
+    const uint32_t dk8 = 4u * (uint32_t)kb;
+    int dks[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) dks[r] = 4 * min(kb + r, Nz - 1);
+    const __amdgpu_buffer_rsrc_t rm = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float *>(MU ? a.mu : a.y), (short)0, MU ? (int)(colb * (uint32_t)N) : 0, kBufferDword3);
     // table and rotated-frame bricks: uniform base of this (angle, slab) + per-thread offset
     const size_t wg0 = brick_offset(al, a.nslab, slab, N, 0, 0);
     const uint32_t toff = 4u * (uint32_t)(jp * SLAB + h * ROWS);
@@ -1006,35 +938,39 @@ __device__ __forceinline__ void back_body(const Args &a, int slab, int chunk, in
     __syncthreads();
     for (int ip = ihi; ip >= ilo; --ip) {
         const int K = kd[ip];
-        const float *gt = a.g.taps + ((size_t)ang * N + ip) * a.g.TS;
+        float gz[KMC + 1];
+        load_taps_all<KMC>(taps + (size_t)ip * a.g.TS, gz);
         float v[ROWS];
-        Corners cn;
-        Raw rm;
+        FCorner cn;
+        float4 mc[4][2];
         float4 t0, t1;
         const size_t row0 = wg0 + (size_t)ip * N * SLAB;
         if (active) {
-            // attenuation samples (or factors) of this depth, in flight during the blur
-            if (MU) {
-                cn = corners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, rg.rowb);
-                load_raw<VEC>(a.mu, cn, rg, kb, Nz, rm);
-            }
+            // attenuation factors of this depth, in flight during the blur
             if (ATT == ATT_READ) {
                 t0 = at_byte<float4>(a.att + row0, toff);
                 t1 = at_byte<float4>(a.att + row0, toff + 16);
             }
-            ZGather zg{ycol, h * ROWS + KMC, gt, v};
+            ZGather<KMC> zg{ycol, h * ROWS + KMC, gz, v};
             KSwitch<0, KMC>::run(K, zg);
             smem[wb_index(buf, 0, jp + KMC, h, nrows)] = make_float4(v[0], v[1], v[2], v[3]);
             smem[wb_index(buf, 1, jp + KMC, h, nrows)] = make_float4(v[4], v[5], v[6], v[7]);
+            // attenuation samples of this depth, in flight during the bin blur
+            if (MU) {
+                cn = fcorners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, rowb, colb,
+                              VEC ? dk8 : 0u);
+                fload8<VEC>(rm, cn, dks, mc);
+            }
         }
-        __syncthreads();
+        lds_barrier();
         if (active) {
             float u[ROWS];
-            BackBlur bb{v, u, smem, wb_index(buf, 0, jp + KMC, h, nrows), wb_index(buf, 1, jp + KMC, h, nrows), gt};
+            BackBlur<KMC> bb{v, u, smem, wb_index(buf, 0, jp + KMC, h, nrows), wb_index(buf, 1, jp + KMC, h, nrows),
+                             gz};
             KSwitch<0, KMC>::run(K, bb);
             if (MU) {
                 float m[ROWS], att[ROWS];
-                combine(rm, cn, kb, Nz, m, full);
+                fcombine8(cn, mc, kb, Nz, m);
                 attenuate(m, S, a.g.tau_scale, att);
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r) u[r] *= att[r];
