@@ -330,7 +330,18 @@ int osem_subset_step(const spect_plan *plan, float *f, const float *mu, const fl
  * initial image on entry (the paper leaves it open; 1 everywhere is the usual
  * choice) and the reconstruction on return; g, s_add, mu as in
  * osem_subset_step.  The workspace (SPECT_OP_RECON, n_idx = n_subsets) also
- * holds the M sensitivity volumes.  n_iters >= 0. */
+ * holds the M sensitivity volumes.  n_iters >= 0.
+ *
+ * Graph replay: the launches depend only on the plan and the arguments, so
+ * the plan captures them into a HIP graph on the second call with the same
+ * arguments (f, mu, g, s_add, ws and ws_bytes, n_iters, n_subsets) and
+ * replays that graph on `stream` in later calls with the same arguments;
+ * the arrays' contents are read at run time, so they may change between
+ * calls.  Replays give bitwise the result of eager launches.  The first call
+ * with new arguments, and every call while kernel timing
+ * (spect_profile_enable) is on, launches eagerly.  A plan keeps its 8 most
+ * recently used graphs until spect_plan_destroy, and guards them with a
+ * lock, so calls from several host threads may share a plan. */
 int osem_reconstruct(const spect_plan *plan, float *f, const float *mu, const float *g,
                      const float *s_add, int32_t n_iters, int32_t n_subsets, void *ws,
                      size_t ws_bytes, void *stream);
@@ -372,7 +383,9 @@ int bsrem_subset_step(const spect_plan *plan, float *f, const float *mu, const f
  * m = 0 .. n_subsets-1 with alpha = relaxation[k] in iteration k (relaxation:
  * host array of n_iters values > 0, or NULL for 1 / (1 + k), a reading: the
  * paper leaves the sequence open).  The paper's SPECT examples use beta = 0.3,
- * gamma = 2.  Workspace: SPECT_OP_BSREM with n_idx = n_subsets. */
+ * gamma = 2.  Workspace: SPECT_OP_BSREM with n_idx = n_subsets.  Graph
+ * replay as in osem_reconstruct; beta, gamma and the relaxation values are
+ * part of the arguments that select a graph. */
 int bsrem_reconstruct(const spect_plan *plan, float *f, const float *mu, const float *g,
                       const float *s_add, int32_t n_iters, int32_t n_subsets, float beta,
                       float gamma, const float *relaxation, void *ws, size_t ws_bytes,

@@ -46,6 +46,28 @@ struct spect_plan {
     int cap = 1;
     std::vector<double> wpre[2];       // [A][N + 1]
     std::vector<double> chunk_cost[2]; // [cap + 1]
+    // whole reconstructions replayed as HIP graphs (see recon_graph)
+    struct GraphKey {
+        const void *f, *mu, *g, *s_add, *ws;
+        size_t ws_bytes;
+        int iters, subsets, bsrem;
+        float beta, gamma;
+        std::vector<float> relax;
+        bool operator==(const GraphKey &o) const
+        {
+            return f == o.f && mu == o.mu && g == o.g && s_add == o.s_add && ws == o.ws && ws_bytes == o.ws_bytes &&
+                   iters == o.iters && subsets == o.subsets && bsrem == o.bsrem && beta == o.beta &&
+                   gamma == o.gamma && relax == o.relax;
+        }
+    };
+    struct CachedGraph {
+        GraphKey key;
+        hipGraphExec_t exec;
+    };
+    mutable std::mutex graph_mu;
+    mutable std::vector<CachedGraph> graphs;  // most recently used last
+    mutable std::vector<GraphKey> seen;       // keys run eagerly once
+    mutable hipStream_t capture_stream = nullptr;
 };
 
 namespace {
@@ -70,6 +92,7 @@ struct ProfRec {
 
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+thread_local bool t_capturing = false;  // this thread is capturing a graph
 std::vector<ProfRec> g_prof;
 
 struct ProfScope {
@@ -81,7 +104,7 @@ struct ProfScope {
     ProfScope(int k, hipStream_t s, bool allowed = true) : kernel(k), st(s)
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
-        on = g_prof_on && allowed;
+        on = g_prof_on && allowed && !t_capturing;
         if (!on) return;
         if (hipEventCreate(&a) != hipSuccess) {
             on = false;
@@ -974,6 +997,8 @@ int spect_plan_destroy(spect_plan *plan)
 {
     if (!plan) return ok();
     if (plan->dmem) (void)hipFree(plan->dmem);
+    for (auto &c : plan->graphs) (void)hipGraphExecDestroy(c.exec);
+    if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
     delete plan;
     return ok();
 }
@@ -1220,6 +1245,75 @@ int osem_subset_step(const spect_plan *plan, float *f, const float *mu, const fl
 
 namespace {
 
+// Whole reconstructions as HIP graphs.  A reconstruction's launches depend
+// only on the plan and on its arguments, so the second call with the same
+// arguments (array addresses, workspace, iteration and subset counts, BSREM
+// parameters) captures them into a graph on the plan's capture stream, and
+// later calls replay it on the caller's stream: one submission instead of
+// four or five kernel launches per subiteration.  Calls with new arguments
+// launch eagerly, as do all calls while kernel timing is on.  The plan keeps
+// the kGraphs most recently used graphs.
+constexpr size_t kGraphs = 8;
+
+template <class Launch>
+int recon_graph(const spect_plan *plan, const spect_plan::GraphKey &key, Launch &launch_all, hipStream_t s)
+{
+    bool timing;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        timing = g_prof_on;
+    }
+    if (timing) return launch_all(s);  // (the launches take g_prof_mu themselves)
+    std::lock_guard<std::mutex> lk(plan->graph_mu);
+    auto &G = plan->graphs;
+    for (size_t i = 0; i < G.size(); ++i) {
+        if (!(G[i].key == key)) continue;
+        std::rotate(G.begin() + i, G.begin() + i + 1, G.end());
+        const hipError_t e = hipGraphLaunch(G.back().exec, s);
+        return e == hipSuccess ? ok() : hip_fail(e, "reconstruction graph launch");
+    }
+    auto &seen = plan->seen;
+    const auto it = std::find(seen.begin(), seen.end(), key);
+    if (it == seen.end()) {
+        if (seen.size() >= kGraphs) seen.erase(seen.begin());
+        seen.push_back(key);
+        return launch_all(s);
+    }
+    seen.erase(it);
+    if (!plan->capture_stream && hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        plan->capture_stream = nullptr;
+        (void)hipGetLastError();
+        return launch_all(s);
+    }
+    if (hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        (void)hipGetLastError();
+        return launch_all(s);
+    }
+    t_capturing = true;
+    const int st = launch_all(plan->capture_stream);
+    t_capturing = false;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(plan->capture_stream, &graph);
+    if (st) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess && graph) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess || !exec) {
+        (void)hipGetLastError();
+        return launch_all(s);
+    }
+    if (G.size() >= kGraphs) {
+        (void)hipGraphExecDestroy(G.front().exec);
+        G.erase(G.begin());
+    }
+    G.push_back({key, exec});
+    e = hipGraphLaunch(exec, s);
+    return e == hipSuccess ? ok() : hip_fail(e, "reconstruction graph launch");
+}
+
 // BSREM parameters of a whole reconstruction (nullptr: OSEM).
 struct BsremSpec {
     float beta, gamma;
@@ -1257,61 +1351,66 @@ int reconstruct(const spect_plan *plan, float *f, const float *mu, const float *
     const size_t vb = vol_bytes(plan);
     const size_t extra = bs ? 2 * vb : 0;
     if ((st = check_ws(ws, ws_bytes, recon_ws(plan, M, mu != nullptr) + extra))) return st;
-    const bool vec = want_vec(plan, {f, mu});
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    char *w = static_cast<char *>(ws);
-    const bool table = use_table(plan, M, mu != nullptr);
-    const int att = table ? ATT_READ : att_of(mu != nullptr);
-    std::vector<float *> sens(M), per(M, nullptr);  // per subset: attenuation table or chunk offsets
-    for (int m = 0; m < M; ++m) sens[m] = reinterpret_cast<float *>(w + (size_t)m * vb);
-    float *sens_all = bs ? reinterpret_cast<float *>(w + (size_t)M * vb) : nullptr;
-    float *prior = bs ? reinterpret_cast<float *>(w + (size_t)M * vb + vb) : nullptr;
-    size_t off = (size_t)M * vb + extra;
-    std::vector<AngleList> lists(M);
-    for (int m = 0; m < M; ++m) {
-        std::vector<int> list;
-        for (int n = m; n < plan->A; n += M) list.push_back(n);
-        lists[m] = to_list(list.data(), (int)list.size());
-        const size_t tb = recon_tau_bytes(plan, M, m, mu != nullptr);
-        if (tb) per[m] = reinterpret_cast<float *>(w + off);
-        if (tb && !table) launch_tau(plan, lists[m], tune(plan, lists[m].n, ATT_SAMPLE, T_BOTH), mu, per[m], vec, s);
-        off += tb;
-    }
-    float *q = reinterpret_cast<float *>(w + off);
-    const size_t qb = osem_q_bytes(plan, M);
-    char *rest = w + off + qb;
-    const size_t avail = ws_bytes - off - qb;
-    // subset sensitivities H_m^T 1; with a table this pass also fills it
-    for (int m = 0; m < M; ++m) {
-        if (table)
-            st = run_back(plan, nullptr, 0, 1, mu, ATT_WRITE, per[m], lists[m], rest, avail, nullptr, 0, sens[m],
-                          nullptr, vec, T_BACK, s);
-        else
-            st = run_back(plan, nullptr, 0, 1, mu, att, nullptr, lists[m], rest, avail, per[m], 0, sens[m], nullptr,
-                          vec, T_BOTH, s);
-        if (st) return st;
-    }
-    if (bs && (st = launch_sum(plan, sens[0], vb / sizeof(float), M, sens_all, s))) return st;
-    for (int it = 0; it < n_iters; ++it)
+    spect_plan::GraphKey key{f, mu, g, s_add, ws, ws_bytes, n_iters, n_subsets, bs ? (bs->relax ? 2 : 1) : 0,
+                             bs ? bs->beta : 0.f, bs ? bs->gamma : 0.f, {}};
+    if (bs && bs->relax) key.relax.assign(bs->relax, bs->relax + n_iters);
+    auto launch_all = [&](hipStream_t s) -> int {
+        const bool vec = want_vec(plan, {f, mu});
+        char *w = static_cast<char *>(ws);
+        const bool table = use_table(plan, M, mu != nullptr);
+        const int att = table ? ATT_READ : att_of(mu != nullptr);
+        std::vector<float *> sens(M), per(M, nullptr);  // per subset: attenuation table or chunk offsets
+        for (int m = 0; m < M; ++m) sens[m] = reinterpret_cast<float *>(w + (size_t)m * vb);
+        float *sens_all = bs ? reinterpret_cast<float *>(w + (size_t)M * vb) : nullptr;
+        float *prior = bs ? reinterpret_cast<float *>(w + (size_t)M * vb + vb) : nullptr;
+        size_t off = (size_t)M * vb + extra;
+        std::vector<AngleList> lists(M);
         for (int m = 0; m < M; ++m) {
-            float *tab = table ? per[m] : nullptr;
-            const float *tau = table ? nullptr : per[m];
-            BsremTerms bt{sens_all, prior, 0.f, 0.f};
-            if (bs) {
-                const float c = (float)lists[m].n / (float)plan->A;
-                const float alpha = bs->relax ? bs->relax[it] : 1.f / (1.f + (float)it);
-                bt.a_over_c = alpha / c;
-                bt.c_beta = c * bs->beta;
-                if ((st = launch_rdp(plan, f, prior, bs->gamma, s))) return st;
-            }
-            if ((st = run_forward(plan, f, mu, att, tab, lists[m], rest, avail, tau, 1, nullptr, g, s_add, q, vec,
-                                  T_BOTH, s)))
-                return st;
-            if ((st = run_back(plan, q, 1, 0, mu, att, tab, lists[m], rest, avail, tau, bs ? 3 : 2, f, sens[m], vec,
-                               T_BOTH, s, bs ? &bt : nullptr)))
-                return st;
+            std::vector<int> list;
+            for (int n = m; n < plan->A; n += M) list.push_back(n);
+            lists[m] = to_list(list.data(), (int)list.size());
+            const size_t tb = recon_tau_bytes(plan, M, m, mu != nullptr);
+            if (tb) per[m] = reinterpret_cast<float *>(w + off);
+            if (tb && !table) launch_tau(plan, lists[m], tune(plan, lists[m].n, ATT_SAMPLE, T_BOTH), mu, per[m], vec, s);
+            off += tb;
         }
-    return ok();
+        float *q = reinterpret_cast<float *>(w + off);
+        const size_t qb = osem_q_bytes(plan, M);
+        char *rest = w + off + qb;
+        const size_t avail = ws_bytes - off - qb;
+        // subset sensitivities H_m^T 1; with a table this pass also fills it
+        for (int m = 0; m < M; ++m) {
+            if (table)
+                st = run_back(plan, nullptr, 0, 1, mu, ATT_WRITE, per[m], lists[m], rest, avail, nullptr, 0, sens[m],
+                              nullptr, vec, T_BACK, s);
+            else
+                st = run_back(plan, nullptr, 0, 1, mu, att, nullptr, lists[m], rest, avail, per[m], 0, sens[m], nullptr,
+                              vec, T_BOTH, s);
+            if (st) return st;
+        }
+        if (bs && (st = launch_sum(plan, sens[0], vb / sizeof(float), M, sens_all, s))) return st;
+        for (int it = 0; it < n_iters; ++it)
+            for (int m = 0; m < M; ++m) {
+                float *tab = table ? per[m] : nullptr;
+                const float *tau = table ? nullptr : per[m];
+                BsremTerms bt{sens_all, prior, 0.f, 0.f};
+                if (bs) {
+                    const float c = (float)lists[m].n / (float)plan->A;
+                    const float alpha = bs->relax ? bs->relax[it] : 1.f / (1.f + (float)it);
+                    bt.a_over_c = alpha / c;
+                    bt.c_beta = c * bs->beta;
+                    if ((st = launch_rdp(plan, f, prior, bs->gamma, s))) return st;
+                }
+                if ((st = run_forward(plan, f, mu, att, tab, lists[m], rest, avail, tau, 1, nullptr, g, s_add, q, vec,
+                                      T_BOTH, s)))
+                    return st;
+                if ((st = run_back(plan, q, 1, 0, mu, att, tab, lists[m], rest, avail, tau, bs ? 3 : 2, f, sens[m], vec,
+                                   T_BOTH, s, bs ? &bt : nullptr)))
+                    return st;
+            }
+        return ok();
+    };
+    return recon_graph(plan, key, launch_all, static_cast<hipStream_t>(stream));
 }
 
 }  // namespace

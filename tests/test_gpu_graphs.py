@@ -1,0 +1,146 @@
+"""Whole reconstructions replayed as HIP graphs.
+
+osem_reconstruct and bsrem_reconstruct launch eagerly on the first call with
+a set of arguments, capture a graph on the second and replay it on later
+calls.  Every replay must give bitwise the result of an eager call (kernel
+timing on forces eager launches) with the same inputs, also after the
+inputs' contents change between replays, with eager work and host
+synchronisations in between, and the first replay's result must meet the
+oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+import paper_2309_01977_amd as S
+from paper_2309_01977_amd import phantoms as P
+
+pytestmark = pytest.mark.gpu
+
+OSEM_TOL = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    O.build(force=False)
+    S.load_library()
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel_l2(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def eager(fn):
+    """fn() with kernel timing on: the library launches eagerly."""
+    with S.KernelTimer():
+        out = fn()
+        torch.cuda.synchronize()
+    return out
+
+
+def problem(seed, n, nz, A, mu_max, counts):
+    r = np.random.default_rng(seed)
+    og = O.Geometry(n, nz, A, 0.48, 0.03, 0.1)
+    f_true = P.random_object(og.object_shape, r) + 0.2
+    mu = P.random_mu(og.object_shape, r, mu_max) if mu_max else None
+    g = P.poisson_counts(O.forward(og, f_true.astype(np.float64), None if mu is None else mu.astype(np.float64)),
+                         counts, r)
+    return og, mu, g
+
+
+@pytest.mark.parametrize("with_mu", [False, True])
+def test_osem_replays_equal_eager_calls_and_the_oracle(with_mu):
+    og, mu, g = problem(300 + with_mu, 48, 40, 36, 0.15 if with_mu else 0.0, 3e5)
+    say(f"  {og.object_shape} x {og.n_angles}, mu {with_mu}: 2 it x 6 subsets")
+    plan = S.Plan(48, 40, 36, 0.48, 0.03, 0.1)
+    gd = dev(g)
+    mud = dev(mu) if with_mu else None
+    f = torch.empty(og.object_shape, device="cuda")
+    ref_eager = host(eager(lambda: S.osem(plan, gd, 2, 6, mud, out=f)).clone())
+    oracle = O.osem(og, g.astype(np.float64), None if mu is None else mu.astype(np.float64), 2, 6)
+    e = rel_l2(ref_eager, oracle)
+    say(f"  eager vs oracle {e:.2e}")
+    assert e <= OSEM_TOL
+    # first call with these arguments: eager; second: captured; then replays
+    for call in range(5):
+        got = host(S.osem(plan, gd, 2, 6, mud, out=f))
+        np.testing.assert_array_equal(got, ref_eager, err_msg=f"call {call}")
+        # eager work of the program between replays
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        del junk
+    # new data in the same arrays: the replay reads the current contents
+    gd.mul_(1.5)
+    got = host(S.osem(plan, gd, 2, 6, mud, out=f))
+    ref2 = host(eager(lambda: S.osem(plan, gd, 2, 6, mud, out=f)).clone())
+    np.testing.assert_array_equal(got, ref2)
+    got = host(S.osem(plan, gd, 2, 6, mud, out=f))
+    np.testing.assert_array_equal(got, ref2)
+    # other arguments (iteration count) are another graph, not a stale replay
+    ref3 = host(eager(lambda: S.osem(plan, gd, 1, 6, mud, out=f)).clone())
+    for _ in range(3):
+        np.testing.assert_array_equal(host(S.osem(plan, gd, 1, 6, mud, out=f)), ref3)
+    plan.close()
+
+
+def test_osem_replay_on_a_side_stream_waits_for_the_callers_work():
+    og, mu, g = problem(310, 40, 32, 30, 0.1, 2e5)
+    plan = S.Plan(40, 32, 30, 0.48, 0.03, 0.1)
+    gd, mud = dev(g), dev(mu)
+    f = torch.empty(og.object_shape, device="cuda")
+    ref = host(eager(lambda: S.osem(plan, gd, 2, 5, mud, out=f)).clone())
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        for _ in range(4):
+            # the initial image comes from a chain of ops on the same stream
+            f.fill_(3.0)
+            for _ in range(20):
+                f.mul_(0.5).add_(0.5)
+            f.fill_(1.0)
+            plan.reconstruct(gd, 2, 5, mud, f=f)
+            side.synchronize()
+            np.testing.assert_array_equal(f.cpu().numpy().astype(np.float64), ref)
+    plan.close()
+
+
+def test_bsrem_replays_equal_eager_calls():
+    og, mu, g = problem(320, 32, 24, 24, 0.15, 2e5)
+    plan = S.Plan(32, 24, 24, 0.48, 0.03, 0.1)
+    gd, mud = dev(g), dev(mu)
+    relax = [1.0 / (1.0 + 0.5 * k) for k in range(4)]
+
+    def run(rel):
+        return plan.bsrem(gd, 4, 4, mud, beta=0.3, gamma=2.0, relaxation=rel, f=f.fill_(1.0))
+
+    f = torch.empty(og.object_shape, device="cuda")
+    ref = host(eager(lambda: run(relax)).clone())
+    oracle = O.bsrem(og, g.astype(np.float64), mu.astype(np.float64), 4, 4, 0.3, 2.0,
+                     relaxation=lambda k: relax[k])
+    assert rel_l2(ref, oracle) <= OSEM_TOL
+    for call in range(4):
+        np.testing.assert_array_equal(host(run(relax)), ref, err_msg=f"call {call}")
+    # new relaxation values are a new graph
+    relax2 = [0.8 / (1.0 + k) for k in range(4)]
+    ref2 = host(eager(lambda: run(relax2)).clone())
+    for call in range(3):
+        np.testing.assert_array_equal(host(run(relax2)), ref2, err_msg=f"relaxation 2, call {call}")
+    plan.close()
