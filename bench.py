@@ -1,7 +1,7 @@
 """Benchmark of the SPECT OSEM hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
-                    [--recon-only] [--workload osem|unrolled|bsrem|batched|serving]
+                    [--recon-only] [--pair-only] [--workload osem|unrolled|bsrem|batched|serving]
                     [--serve-seconds S]
 
 Default workload: the 128^3 voxel, 120-angle acquisition (0.48 cm voxels,
@@ -309,6 +309,20 @@ def small_workload(cpu):
         out["oracle_osem_s"] = time.perf_counter() - t0
         out["rel_l2_vs_oracle"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     return out
+
+
+def bench_pair(args):
+    """The metric of record alone: the whole-angle forward and back
+    projection of the default workload's phantom with its attenuation map
+    (no data, no reconstruction, no oracle), for profiler runs."""
+    w = P.C2
+    plan = S.Plan.for_workload(w)
+    f_true, mu_np = P.make_phantom(w)
+    pair = pair_metric(w, plan, torch.from_numpy(f_true).cuda(), torch.from_numpy(mu_np).cuda())
+    log(f"fwd {pair['fwd_ms']:.3f} ms, adj {pair['adj_ms']:.3f} ms (medians of {PAIR_REPS}): "
+        f"{pair['voxel_angles_per_s']:.3e} voxel-angles/s")
+    print(json.dumps({"metric": "voxel-angle projections/s (fwd+adj), pair-only run",
+                      "value": pair["voxel_angles_per_s"], "projector_pair": pair}), flush=True)
 
 
 def bench_osem(args):
@@ -779,6 +793,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--recon-only", action="store_true")
+    ap.add_argument("--pair-only", action="store_true",
+                    help="time only the whole-angle projector pair of the default workload (for profiling)")
     ap.add_argument("--workload", choices=("osem", "unrolled", "bsrem", "batched", "serving"), default="osem")
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--oracle-sample", default=None, help=argparse.SUPPRESS)
@@ -809,6 +825,8 @@ def main():
         print(json.dumps(bench_batched(args)), flush=True)
     elif args.workload == "serving":
         bench_serving(args)
+    elif args.pair_only:
+        bench_pair(args)
     else:
         bench_osem(args)
 

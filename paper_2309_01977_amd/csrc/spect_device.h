@@ -109,12 +109,19 @@ struct DevGeom {
 // whose time hardly depends on the blur radius, and the passes that share
 // attenuation offsets), set 1 balances the blur work of the rotated-frame
 // pass (about 10 + K per depth).
+// A value every lane of the wave holds (workgroup coordinates, plan table
+// entries they select), moved to a scalar register: loops and radius
+// dispatch that depend on it then run as scalar branches, and the loads it
+// addresses (radii, taps) as scalar loads, instead of being treated as
+// per-lane values.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 template <class G>
 __device__ __forceinline__ void chunk_range(const G &g, int set, int nchunk, int ang, int chunk, int &ihi, int &ilo)
 {
     ConstMem<int> *cb = as_const(g.cbnd + (((size_t)set * g.cap + nchunk - 1) * g.A + ang) * (g.cap + 1));
-    ihi = cb[chunk] - 1;
-    ilo = cb[chunk + 1];
+    ihi = uniform(cb[chunk] - 1);
+    ilo = uniform(cb[chunk + 1]);
 }
 
 // --------------------------------------------------------------- helpers --
@@ -418,7 +425,7 @@ __global__ __launch_bounds__(256) void tau_prepass(TauArgs a)
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N * ngrp) return;
     const int ch = blockIdx.y, al = blockIdx.z;
-    const int ang = a.L.idx[al];
+    const int ang = uniform(a.L.idx[al]);
     const int jp = t / ngrp, kb = (t % ngrp) * ROWS;
     const float2 cs = a.g.cs[ang];
     const float2 o = a.g.xy0[(size_t)ang * N + jp];
@@ -685,7 +692,7 @@ __device__ __forceinline__ void fwd_body(const Args &a, int slab, int chunk, int
     extern __shared__ float4 smem[];
     FwdWalk<ATT, KMC, VEC> w;
     const int N = a.g.N, Nz = a.g.Nz;
-    const int ang = a.L.idx[al];
+    const int ang = uniform(a.L.idx[al]);
     w.smem = smem;
     w.N = N;
     w.Nz = Nz;
@@ -742,7 +749,7 @@ __device__ __forceinline__ void fwd_body(const Args &a, int slab, int chunk, int
     w.buf = 0;
     if (ATT == ATT_READ && w.active && ihi >= ilo) w.tload(ihi);
     __syncthreads();
-    for (int ip = ihi; ip >= ilo; --ip) w.depth(ip, kd[ip]);
+    for (int ip = ihi; ip >= ilo; --ip) w.depth(ip, uniform(kd[ip]));
 
     // merge the four lanes of each bin in LDS ([N][R], lane q's row t is the
     // slab's partial row 4q + t; lanes added in order q = 0..3), then store
@@ -815,7 +822,7 @@ __device__ __forceinline__ void reduce_body(const Args &a, int blk, int al)
     const int N = a.N, Nz = a.Nz;
     const int t = blk * blockDim.x + threadIdx.x;
     if (t >= N * Nz) return;
-    const int ang = a.L.idx[al];
+    const int ang = uniform(a.L.idx[al]);
     const int r = t / Nz, k = t % Nz;
     const int R = SLAB + 2 * a.kmc;
     const int slo = max(0, (k + a.kmc - R + 4 * SLAB) / SLAB - 3);  // floor((k + kmc - R) / 16) + 1
@@ -885,7 +892,7 @@ __device__ __forceinline__ void back_body(const Args &a, int slab, int chunk, in
     constexpr bool MU = ATT == ATT_SAMPLE || ATT == ATT_WRITE;
     extern __shared__ float4 smem[];
     const int N = a.g.N, Nz = a.g.Nz;
-    const int ang = a.L.idx[al];
+    const int ang = uniform(a.L.idx[al]);
     const int jp = threadIdx.x >> 1, h = threadIdx.x & 1;
     const bool active = jp < N;
     const int nrows = N + 2 * KMC;
@@ -937,7 +944,7 @@ __device__ __forceinline__ void back_body(const Args &a, int slab, int chunk, in
     int buf = 0;
     __syncthreads();
     for (int ip = ihi; ip >= ilo; --ip) {
-        const int K = kd[ip];
+        const int K = uniform(kd[ip]);
         float gz[KMC + 1];
         load_taps_all<KMC>(taps + (size_t)ip * a.g.TS, gz);
         float v[ROWS];
@@ -1047,7 +1054,7 @@ __device__ __forceinline__ void sensl_body(const Args &a, int blk, int slab, int
     const int N = a.g.N;
     const int t = blk * SL_THREADS + threadIdx.x;
     const int jp = t >> 3, rp = t & 7;
-    const int ang = a.L.idx[al];
+    const int ang = uniform(a.L.idx[al]);
     // this angle's running tap sums C[i'][m] in LDS: the per-lane lookups of
     // the in-range sums then use the LDS pipe, not the vector-memory return
     // path that the mu samples need (dynamic LDS of N * TS floats)
@@ -1110,7 +1117,7 @@ __device__ __forceinline__ void sensl_walk(const Args &a, int jp, int rp, int sl
     float S0 = 0.f, S1 = 0.f;
     // one depth from the samples in sp (loaded one depth earlier)
     auto step = [&](int ip, const Samp &sp) {
-        const int K = kd[ip];
+        const int K = uniform(kd[ip]);
         const float *ct = ctl + ip * TS;
         const float g0 = ct[0], cK = ct[K];
         // in-range tap sums across bins and rows; an interior slab (both
@@ -1266,7 +1273,7 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
     };
     auto window = [&](int al) {
         Win w;
-        const int ang = a.L.idx[al];
+        const int ang = uniform(a.L.idx[al]);
         w.cs = a.g.cs[ang];
         const float wdw = fabsf(w.cs.x) + fabsf(w.cs.y) + 1e-3f;
         const float ic = c + w.cs.x * xx + w.cs.y * yy;
