@@ -614,10 +614,21 @@ struct FwdWalk {
     float S[FR];       // running attenuation sums (mu sampled)
     float4 vt;         // attenuation factors of the current depth (table)
     int buf;
+    FCorner cn;        // bilinear corners of the depth whose loads are in flight
+    float4 vf[4], vm[4];
 
     __device__ __forceinline__ void tload(int ip)
     {
         vt = live ? stream_f4(tab + (size_t)ip * N * SLAB, 0u) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+
+    // issue the corner loads of depth ip (activity, and mu when sampled);
+    // they are consumed one depth later
+    __device__ __forceinline__ void cload(int ip)
+    {
+        cn = fcorners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, rowb, colb, VEC ? dk : 0u);
+        fload<VEC>(rf, cn, dks, vf);
+        if (MU) fload<VEC>(rm, cn, dks, vm);
     }
 
     __device__ __forceinline__ float4 zero_past_nz(float4 v) const
@@ -631,27 +642,23 @@ struct FwdWalk {
         return v;
     }
 
-    // depth ip of radius K
+    // depth ip of radius K (its corner loads were issued one depth earlier)
     __device__ __forceinline__ void depth(int ip, int K)
     {
         float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
         if (active) {
-            const FCorner cn = fcorners(fmaf((float)ip, cs.x, o.x), fmaf((float)ip, cs.y, o.y), N, rowb, colb,
-                                        VEC ? dk : 0u);
-            float4 vf[4], vm[4];
-            fload<VEC>(rf, cn, dks, vf);
-            if (MU) fload<VEC>(rm, cn, dks, vm);
             w = zero_past_nz(fcombine(cn, vf));
+            const float4 m = MU ? zero_past_nz(fcombine(cn, vm)) : w;
+            // the next depth's corners (and factors), in flight during this blur
+            if (ip > ilo) cload(ip - 1);
             if (ATT == ATT_READ) {
                 w.x *= vt.x;
                 w.y *= vt.y;
                 w.z *= vt.z;
                 w.w *= vt.w;
-                // the next depth's factors, in flight during this blur
                 if (ip > ilo) tload(ip - 1);
             }
             if (MU) {
-                const float4 m = zero_past_nz(fcombine(cn, vm));
                 const float mm[FR] = {m.x, m.y, m.z, m.w};
                 float at[FR];
 #pragma unroll
@@ -748,6 +755,7 @@ __device__ __forceinline__ void fwd_body(const Args &a, int slab, int chunk, int
     w.tab = ATT == ATT_READ && w.live ? a.att + brick_offset(al, a.nslab, slab, N, 0, w.jp) + w.q * FR : nullptr;
     w.buf = 0;
     if (ATT == ATT_READ && w.active && ihi >= ilo) w.tload(ihi);
+    if (w.active && ihi >= ilo) w.cload(ihi);
     __syncthreads();
     for (int ip = ihi; ip >= ilo; --ip) w.depth(ip, uniform(kd[ip]));
 
