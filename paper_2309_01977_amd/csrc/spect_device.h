@@ -1226,18 +1226,19 @@ struct GatherArgs {
 // max(0, 1 - |X_P - x|) max(0, 1 - |Y_P - y|), with X_P, Y_P computed by the
 // forward's own FP32 expression, so the weights equal the forward's to within
 // one rounding.  Lane q of a column evaluates the three candidates of window
-// column q (lane 3 none) and the quad shares weights and brick offsets through
-// DPP quad permutes; the two slabs use the same weights.  Zero-weight
-// candidates are not loaded: the data-return path, not arithmetic, bounds
-// this kernel.
+// column q (lane 3 none) and writes their weights and brick offsets to the
+// quad's nine-entry table in LDS; the quad then loads only the candidates of
+// non-zero weight, in window order, through at most GC slots (a rotated unit
+// lattice puts at most five samples strictly inside the 2 x 2 box around a
+// column; a general loop takes any further ones).  The data-return path,
+// which spends the same cycles on a wave load whatever its lane mask, bounds
+// this kernel, so the load count is what matters; the two slabs use the same
+// weights.
 constexpr int GT = 8;  // gather tile edge
 constexpr int GS = 2;  // slabs per gather workgroup
+constexpr int GC = 5;  // candidate load slots per angle
 
 #ifdef SPECT_HOST_TU
-// A byte offset of kPastEnd lies beyond every rotated-frame buffer the gather
-// reads (at most two 4 MiB planes), so a raw buffer load there returns zeros.
-constexpr int kPastEnd = 0x40000000;
-
 // Value of lane `src` of this lane's quad (all four lanes active).
 template <int SRC>
 __device__ __forceinline__ int quad_bcast(int v)
@@ -1293,11 +1294,16 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
     };
     Win nxt;
     if (a.L.n > 0) nxt = window(0);
-    float4 vv[GS][9];  // candidate bricks, kept across angles (see below)
+    // the quad's candidate table: entry 3 q + di = (weight, byte offset) of
+    // window row di, column q
+    __shared__ float2 ctab[256 / 4][9];
+    float2 *qt = ctab[threadIdx.x >> 2];
+    // loaded candidate bricks, kept across angles (see below)
+    float4 vv[GS][GC];
 #pragma unroll
     for (int sl = 0; sl < GS; ++sl)
 #pragma unroll
-        for (int d = 0; d < 9; ++d) vv[sl][d] = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int k = 0; k < GC; ++k) vv[sl][k] = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int al = 0; al < a.L.n; ++al) {
         const Win cur = nxt;
         if (al + 1 < a.L.n) nxt = window(al + 1);
@@ -1310,42 +1316,72 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
         const int jp = cur.jlo + q;
         const bool jin = q < 3 && (unsigned)jp < (unsigned)N;
         const uint32_t jb = (uint32_t)jp * (SLAB * 4);
-        float wo[3];
-        int oo[3];
+        int mq = 0;  // bit di: row di of this window column has a non-zero weight
 #pragma unroll
         for (int di = 0; di < 3; ++di) {
             const int ip = cur.ilo + di;
             const bool inr = jin && (unsigned)ip < (unsigned)N;
             const float X = fmaf((float)ip, cur.cs.x, cur.o.x), Y = fmaf((float)ip, cur.cs.y, cur.o.y);
             const float wx = fmaxf(0.f, 1.f - fabsf(X - fxv)), wy = fmaxf(0.f, 1.f - fabsf(Y - fyv));
-            wo[di] = inr ? wx * wy : 0.f;
-            oo[di] = wo[di] > 0.f ? (int)((uint32_t)ip * rowb + jb) : kPastEnd;
+            const float wt = inr ? wx * wy : 0.f;
+            if (q < 3) qt[3 * q + di] = make_float2(wt, __int_as_float((int)((uint32_t)ip * rowb + jb)));
+            mq |= (wt > 0.f ? 1 : 0) << di;
         }
-        // candidate d = 3 di + dj lives in lane dj of the quad.  Only
-        // candidates with a non-zero weight are loaded (the weight is the
-        // quad's, so whole quads drop out and return no data); a skipped
-        // candidate multiplies its weight 0 with what the register held: zero
-        // or a value this lane loaded earlier with a positive weight into the
-        // same row sums, so the product is 0 unless that row's sum is already
-        // non-finite.
-#define SPECT_CAND(di, dj)                                                                          \
-    {                                                                                               \
-        constexpr int d = 3 * (di) + (dj);                                                          \
-        const float wt = quad_bcast<dj>(wo[di]);                                                    \
-        const int off = quad_bcast<dj>(oo[di]) + qoff;                                              \
-        _Pragma("unroll") for (int sl = 0; sl < GS; ++sl)                                           \
-        {                                                                                           \
-            if (wt > 0.f) vv[sl][d] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(zr, off + sl * planeb, 0, 0)); \
-            acc[sl][0] = fmaf(wt, vv[sl][d].x, acc[sl][0]);                                         \
-            acc[sl][1] = fmaf(wt, vv[sl][d].y, acc[sl][1]);                                         \
-            acc[sl][2] = fmaf(wt, vv[sl][d].z, acc[sl][2]);                                         \
-            acc[sl][3] = fmaf(wt, vv[sl][d].w, acc[sl][3]);                                         \
-        }                                                                                           \
-    }
-        SPECT_CAND(0, 0) SPECT_CAND(0, 1) SPECT_CAND(0, 2)
-        SPECT_CAND(1, 0) SPECT_CAND(1, 1) SPECT_CAND(1, 2)
-        SPECT_CAND(2, 0) SPECT_CAND(2, 1) SPECT_CAND(2, 2)
-#undef SPECT_CAND
+        // the quad's non-zero candidates, bit 3 q + di
+        int m = quad_bcast<0>(mq) | (quad_bcast<1>(mq) << 3) | (quad_bcast<2>(mq) << 6);
+        // the table entries are written and read by lanes of this wave only
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+        // slot k takes the k-th non-zero candidate.  A quad with fewer
+        // candidates leaves the slot's registers as they are and gives it
+        // weight 0: they hold zero or a value this lane loaded earlier with a
+        // positive weight into the same row sums, so the product is 0 unless
+        // that row's sum is already non-finite.
+        // the slots' table reads are issued together, then their loads
+        bool hk[GC];
+        float2 ek[GC];
+#pragma unroll
+        for (int k = 0; k < GC; ++k) {
+            hk[k] = m != 0;
+            ek[k] = qt[hk[k] ? __builtin_ctz(m) : 0];
+            m &= m - 1;
+        }
+        float wk[GC];
+#pragma unroll
+        for (int k = 0; k < GC; ++k) {
+            wk[k] = hk[k] ? ek[k].x : 0.f;
+            if (hk[k]) {
+                const int off = __float_as_int(ek[k].y) + qoff;
+#pragma unroll
+                for (int sl = 0; sl < GS; ++sl)
+                    vv[sl][k] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(zr, off + sl * planeb, 0, 0));
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < GC; ++k) {
+#pragma unroll
+            for (int sl = 0; sl < GS; ++sl) {
+                acc[sl][0] = fmaf(wk[k], vv[sl][k].x, acc[sl][0]);
+                acc[sl][1] = fmaf(wk[k], vv[sl][k].y, acc[sl][1]);
+                acc[sl][2] = fmaf(wk[k], vv[sl][k].z, acc[sl][2]);
+                acc[sl][3] = fmaf(wk[k], vv[sl][k].w, acc[sl][3]);
+            }
+        }
+        // candidates beyond the slots (not expected; kept for any geometry)
+        while (m != 0) {
+            const float2 e = qt[__builtin_ctz(m)];
+            m &= m - 1;
+            const int off = __float_as_int(e.y) + qoff;
+#pragma unroll
+            for (int sl = 0; sl < GS; ++sl) {
+                const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(zr, off + sl * planeb, 0, 0));
+                acc[sl][0] = fmaf(e.x, v.x, acc[sl][0]);
+                acc[sl][1] = fmaf(e.x, v.y, acc[sl][1]);
+                acc[sl][2] = fmaf(e.x, v.z, acc[sl][2]);
+                acc[sl][3] = fmaf(e.x, v.w, acc[sl][3]);
+            }
+        }
     }
     const size_t base = ((size_t)x * N + y) * Nz;
 #pragma unroll
