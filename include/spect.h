@@ -76,6 +76,8 @@ extern "C" {
 #define SPECT_OP_RECON 4
 #define SPECT_OP_BSREM_STEP 5
 #define SPECT_OP_BSREM 6
+#define SPECT_OP_STEP 7        /* osem_list_step, n_idx = list length */
+#define SPECT_OP_STEP_VJP 8    /* osem_list_step_vjp, n_idx = list length */
 
 /* with_mu value of spect_workspace_size for the attenuation-table calls. */
 #define SPECT_ATT_TABLE 2
@@ -316,6 +318,41 @@ int spect_back_table(const spect_plan *plan, const float *proj, const float *tab
 int osem_subset_step(const spect_plan *plan, float *f, const float *mu, const float *g,
                      const float *s_add, const float *sens_m, int32_t m, int32_t n_subsets,
                      void *ws, size_t ws_bytes, void *stream);
+
+/* The subiteration of osem_subset_step over an explicit angle list S (1 to
+ * 128 distinct angles; angle_idx NULL = all angles), out of place, with the
+ * attenuation from mu or from a table that spect_sensitivity_table wrote for
+ * the same list in the same order (at most one of mu and table; both NULL:
+ * none):
+ *     f_out = f * H_S^T(g / (H_S f + s)) / sens   where sens > 0, f elsewhere,
+ * the ratio taken as 0 where H_S f + s <= 0 (Eq. 5 with Table 1).  f, f_out,
+ * sens: device (N, N, Nz), f_out == f updates in place, otherwise they must
+ * not overlap; sens = H_S^T 1.  g, s_add as in osem_subset_step.  Workspace:
+ * SPECT_OP_STEP with n_idx = the list length and with_mu 0, 1 or
+ * SPECT_ATT_TABLE.  Errors: SPECT_EINVAL (empty list, an angle listed twice,
+ * both mu and table), SPECT_EUNSUPPORTED (more than 128 angles). */
+int osem_list_step(const spect_plan *plan, const float *f, float *f_out, const float *mu,
+                   const float *table, const float *g, const float *s_add, const float *sens,
+                   const int32_t *angle_idx, int32_t n_idx, void *ws, size_t ws_bytes, void *stream);
+
+/* Vector-Jacobian product of osem_list_step in f, for differentiating
+ * unrolled reconstructions (the paper's projectors inside learned
+ * reconstruction, Section 1):
+ *     grad_f = (d f_out / d f)^T grad_out
+ *            = u + H_S^T( -g / e^2 * H_S(grad_out * f / sens) )   (e > 0 rows),
+ *     e = H_S f + s,  u = grad_out * H_S^T(g / e) / sens  (grad_out where sens = 0),
+ * with the branches of the ratio and of sens = 0 differentiated as written
+ * (no gradient through a row with e <= 0 or a voxel with sens = 0 other than
+ * the identity).  g, s_add and sens are data (not differentiated).  The call
+ * recomputes e and the back projection from f (nothing is kept between the
+ * step and its product), 4 projector passes over the list.  grad_f may equal
+ * grad_out; it must not overlap f.  Workspace: SPECT_OP_STEP_VJP (n_idx and
+ * with_mu as for SPECT_OP_STEP).  Other arguments and errors as in
+ * osem_list_step. */
+int osem_list_step_vjp(const spect_plan *plan, const float *f, const float *mu, const float *table,
+                       const float *g, const float *s_add, const float *sens,
+                       const int32_t *angle_idx, int32_t n_idx, const float *grad_out, float *grad_f,
+                       void *ws, size_t ws_bytes, void *stream);
 
 /* A whole OSEM reconstruction f = A(L) (Section 2.1.3, Eq. 4 and Eq. 5 with
  * the Table 1 OSEM preconditioner and Poisson gradient): computes the subset

@@ -22,11 +22,13 @@ SPECT_ENOMEM = -2
 SPECT_EHIP = -3
 SPECT_EUNSUPPORTED = -4
 OP_FWD, OP_BACK, OP_SENS, OP_OSEM, OP_RECON, OP_BSREM_STEP, OP_BSREM = 0, 1, 2, 3, 4, 5, 6
+OP_STEP, OP_STEP_VJP = 7, 8
 ATT_TABLE = 2   # with_mu code of the attenuation-table calls
 
 EXPORTS = ("spect_plan_create", "spect_plan_destroy", "spect_workspace_size", "spect_fwd", "spect_fwd_static",
            "spect_back", "spect_sensitivity", "spect_table_size", "spect_sensitivity_table",
-           "spect_fwd_table", "spect_back_table", "osem_subset_step", "osem_reconstruct",
+           "spect_fwd_table", "spect_back_table", "osem_subset_step", "osem_list_step", "osem_list_step_vjp",
+           "osem_reconstruct",
            "spect_rdp_gradient", "bsrem_subset_step", "bsrem_reconstruct", "spect_batch_create",
            "spect_batch_destroy", "spect_batch_workspace_size", "osem_batch_reconstruct", "osem_batch_autotune",
            "spect_batch_schedule", "spect_batch_set_schedule", "spect_server_create", "spect_server_destroy",
@@ -79,6 +81,8 @@ def load_library(path: Optional[str] = None):
     lib.spect_back_table.argtypes = [vp, vp, vp, vp, i32p, i32, ctypes.c_int, vp, sz, vp]
     lib.osem_subset_step.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, vp, sz, vp]
     lib.osem_reconstruct.argtypes = [vp, vp, vp, vp, vp, i32, i32, vp, sz, vp]
+    lib.osem_list_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i32p, i32, vp, sz, vp]
+    lib.osem_list_step_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32p, i32, vp, vp, vp, sz, vp]
     f32 = ctypes.c_float
     lib.spect_rdp_gradient.argtypes = [vp, vp, vp, f32, vp]
     lib.bsrem_subset_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, i32, f32, f32, f32, vp, sz, vp]
@@ -332,6 +336,54 @@ class Plan:
             _ptr(sens_m, self.object_shape, "sens_m"), int(m), int(n_subsets),
             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
         return f
+
+
+def _step_att(mu, table):
+    """with_mu code of the subiteration calls: a table, a map or neither."""
+    if mu is not None and table is not None:
+        raise ValueError("pass an attenuation map or a table, not both")
+    return ATT_TABLE if table is not None else int(mu is not None)
+
+
+def _osem_list_step(self, f: torch.Tensor, g: torch.Tensor, sens: torch.Tensor, idx,
+                    mu: Optional[torch.Tensor] = None, table: Optional[torch.Tensor] = None,
+                    s_add: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """One OSEM subiteration over the angle list idx (osem_list_step): returns
+    out = f * H^T(g / (H f + s)) / sens (f where sens = 0); out may be f."""
+    if out is None:
+        out = torch.empty(self.object_shape, dtype=torch.float32, device=f.device)
+    arr, n = self._idx(idx)
+    code = _step_att(mu, table)
+    ws = self.workspace(OP_STEP, max(n, 1), code)
+    _check(load_library().osem_list_step(
+        self._h, _ptr(f, self.object_shape, "f"), _ptr(out, self.object_shape, "f_out"),
+        _ptr(mu, self.object_shape, "mu"), None if table is None else self._table(table, n),
+        _ptr(g, self.proj_shape, "g"), _ptr(s_add, self.proj_shape, "s_add"),
+        _ptr(sens, self.object_shape, "sens"), arr, n, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return out
+
+
+def _osem_list_step_vjp(self, f: torch.Tensor, g: torch.Tensor, sens: torch.Tensor, idx,
+                        grad_out: torch.Tensor, mu: Optional[torch.Tensor] = None,
+                        table: Optional[torch.Tensor] = None, s_add: Optional[torch.Tensor] = None,
+                        out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """(d osem_list_step / d f)^T grad_out (osem_list_step_vjp); out may be grad_out."""
+    if out is None:
+        out = torch.empty(self.object_shape, dtype=torch.float32, device=f.device)
+    arr, n = self._idx(idx)
+    code = _step_att(mu, table)
+    ws = self.workspace(OP_STEP_VJP, max(n, 1), code)
+    _check(load_library().osem_list_step_vjp(
+        self._h, _ptr(f, self.object_shape, "f"), _ptr(mu, self.object_shape, "mu"),
+        None if table is None else self._table(table, n), _ptr(g, self.proj_shape, "g"),
+        _ptr(s_add, self.proj_shape, "s_add"), _ptr(sens, self.object_shape, "sens"), arr, n,
+        _ptr(grad_out, self.object_shape, "grad_out"), _ptr(out, self.object_shape, "grad_f"),
+        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return out
+
+
+Plan.osem_list_step = _osem_list_step
+Plan.osem_list_step_vjp = _osem_list_step_vjp
 
 
 class KernelTimer:

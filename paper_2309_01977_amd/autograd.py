@@ -19,15 +19,16 @@ by the batch, or None.  mu is not differentiated.
 
 ``unrolled_osem`` differentiates K OSEM subiterations (Eq. 5 with the Table 1
 preconditioner, in the multiplicative form) with respect to the initial
-image; each subiteration can be recomputed in the backward pass instead of
-stored (torch.utils.checkpoint).
+image.  A subiteration is one library call (osem_list_step: the ratio and
+the update are fused into the projector kernels) and its gradient another
+(osem_list_step_vjp), which recomputes the projections from the saved input
+image; no arithmetic of the update runs in PyTorch.
 """
 from __future__ import annotations
 
 from typing import List, Optional, Sequence
 
 import torch
-from torch.utils.checkpoint import checkpoint
 
 from ._binding import Plan, subset_angles
 
@@ -98,78 +99,61 @@ def back_project(p: torch.Tensor, plan: Plan, mu: Optional[torch.Tensor] = None,
     return _Pair.apply(p, plan, mu, table, None if idx is None else list(idx), True)
 
 
-def _safe_div(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
-    """a / b where b > 0, else 0 (the 0/0 reading of the ratio)."""
-    pos = b > 0
-    return torch.where(pos, a / torch.where(pos, b, torch.ones_like(b)), torch.zeros_like(a))
+class _Subset:
+    """What one subiteration needs besides the image, as the library calls
+    take it: the angle list, the measured data and additive term (full
+    projection arrays; the calls read the listed rows) and sens = H_S^T 1."""
+
+    def __init__(self, g, sens_m, idx, s_add):
+        self.idx = list(idx)
+        self.g, self.s, self.sens = g, s_add, sens_m
 
 
-def _rows_apply(plan: Plan, x, mu, table, idx, rows, adjoint: bool):
-    """adjoint=False: the rows idx of H x as a compact (..., len(idx), N, Nz)
-    tensor; adjoint=True: H^T of such compact rows.  The full projection
-    buffer the calls take is left unfilled outside the rows idx: the forward
-    writes and the back projection reads no other row."""
-    batched = x.dim() == 4
-    x = x.contiguous()
-    lead = (x.shape[0],) if batched else ()
-    full = torch.empty(lead + plan.proj_shape, dtype=torch.float32, device=x.device)
-    if adjoint:
-        full.index_copy_(-3, rows, x)
-        out = torch.empty(lead + plan.object_shape, dtype=torch.float32, device=x.device)
-        for b in range(x.shape[0] if batched else 1):
-            _back(plan, full[b] if batched else full, _member(mu, b, batched, 3), _member(table, b, batched, 1),
-                  idx, out[b] if batched else out)
-        return out
-    for b, xb in enumerate(_members(x, 3)):
-        _fwd(plan, xb, _member(mu, b, batched, 3), _member(table, b, batched, 1), idx,
-             full[b] if batched else full)
-    return full.index_select(-3, rows)
-
-
-class _Rows(torch.autograd.Function):
-    """Compact-row form of the pair (see _rows_apply); the backward applies
-    the other operator."""
+class _OsemStep(torch.autograd.Function):
+    """One OSEM subiteration f * H_S^T(g / (H_S f + s)) / sens (Eq. 5 with the
+    Table 1 preconditioner; osem_list_step), differentiable in f.  The
+    backward is osem_list_step_vjp: it recomputes the subset's projections
+    from the saved input image, so each subiteration keeps only that image
+    (the recomputation that checkpointing would otherwise arrange)."""
 
     @staticmethod
-    def forward(ctx, x, plan: Plan, mu, table, idx, rows, adjoint: bool):
-        ctx.args = (plan, mu, table, idx, rows, adjoint)
-        return _rows_apply(plan, x, mu, table, idx, rows, adjoint)
+    def forward(ctx, f, plan: Plan, sub: _Subset, mu, table):
+        batched = f.dim() == 4
+        f = f.contiguous()
+        out = torch.empty_like(f)
+        for b in range(f.shape[0] if batched else 1):
+            plan.osem_list_step(f[b] if batched else f, _member(sub.g, b, batched, 3),
+                                _member(sub.sens, b, batched, 3), sub.idx, _member(mu, b, batched, 3),
+                                _member(table, b, batched, 1), _member(sub.s, b, batched, 3),
+                                out=out[b] if batched else out)
+        ctx.save_for_backward(f)
+        ctx.args = (plan, sub, mu, table)
+        return out
 
     @staticmethod
     def backward(ctx, gy):
-        plan, mu, table, idx, rows, adjoint = ctx.args
-        return _rows_apply(plan, gy, mu, table, idx, rows, not adjoint), None, None, None, None, None, None
-
-
-class _Subset:
-    """What one subiteration needs that does not depend on the image: the
-    subset's rows, the measured (and additive) rows, where sens_m > 0 and
-    sens_m with 1 where it is 0."""
-
-    def __init__(self, g, sens_m, idx, s_add, device):
-        self.idx = list(idx)
-        self.rows = torch.as_tensor(self.idx, dtype=torch.long, device=device)
-        self.g = g.index_select(-3, self.rows)
-        self.s = None if s_add is None else s_add.index_select(-3, self.rows)
-        self.pos = sens_m > 0
-        self.sens = torch.where(self.pos, sens_m, torch.ones_like(sens_m))
-
-
-def _osem_step(f, sub: _Subset, plan: Plan, mu, table):
-    gh = _Rows.apply(f, plan, mu, table, sub.idx, sub.rows, False)
-    if sub.s is not None:
-        gh = gh + sub.s
-    b = _Rows.apply(_safe_div(sub.g, gh), plan, mu, table, sub.idx, sub.rows, True)
-    return torch.where(sub.pos, f * b / sub.sens, f)
+        (f,) = ctx.saved_tensors
+        plan, sub, mu, table = ctx.args
+        batched = f.dim() == 4
+        gy = gy.contiguous()
+        gf = torch.empty_like(f)
+        for b in range(f.shape[0] if batched else 1):
+            plan.osem_list_step_vjp(f[b] if batched else f, _member(sub.g, b, batched, 3),
+                                    _member(sub.sens, b, batched, 3), sub.idx, gy[b] if batched else gy,
+                                    _member(mu, b, batched, 3), _member(table, b, batched, 1),
+                                    _member(sub.s, b, batched, 3), out=gf[b] if batched else gf)
+        return gf, None, None, None, None
 
 
 def osem_update(f: torch.Tensor, g: torch.Tensor, sens_m: torch.Tensor, plan: Plan, idx,
                 mu: Optional[torch.Tensor] = None, s_add: Optional[torch.Tensor] = None,
                 table: Optional[torch.Tensor] = None) -> torch.Tensor:
     """One OSEM subiteration on the angles idx, differentiable in f:
-    f * H_m^T(g / (H_m f + s)) / sens_m (f where sens_m = 0).  The ratio is
-    formed on the rows idx only: H_m^T reads no other row."""
-    return _osem_step(f, _Subset(g, sens_m, idx, s_add, f.device), plan, mu, table)
+    f * H_m^T(g / (H_m f + s)) / sens_m (f where sens_m = 0; the ratio 0 where
+    H_m f + s <= 0).  The update and its gradient run in the library's
+    kernels (osem_list_step, osem_list_step_vjp)."""
+    # a table replaces the attenuation map (the library call takes one of the two)
+    return _OsemStep.apply(f, plan, _Subset(g, sens_m, idx, s_add), None if table is not None else mu, table)
 
 
 def subset_sensitivities(plan: Plan, n_subsets: int, mu: Optional[torch.Tensor] = None,
@@ -203,21 +187,22 @@ def unrolled_osem(plan: Plan, g: torch.Tensor, f0: torch.Tensor, n_steps: int, n
                   sens: Optional[List[torch.Tensor]] = None, tables: Optional[List[torch.Tensor]] = None,
                   checkpointing: bool = True) -> torch.Tensor:
     """f_K after K = n_steps subiterations from f0 (subset k mod M), differentiable in
-    f0.  With checkpointing each subiteration keeps only its input image and is
-    recomputed during the backward pass.  ``sens`` / ``tables`` as returned by
+    f0.  Every subiteration keeps only its input image and recomputes its
+    projections in the backward pass (osem_list_step_vjp), which is what
+    checkpointing asks for; ``checkpointing`` is accepted for compatibility
+    and changes nothing.  ``sens`` / ``tables`` as returned by
     subset_sensitivities (tables optional: with them every projection reads
     the attenuation factors instead of resampling mu)."""
+    del checkpointing
     batch = f0.shape[0] if f0.dim() == 4 else None
     if sens is None:
         sens = subset_sensitivities(plan, n_subsets, mu, batch)
-    subs = [_Subset(g, sens[m], subset_angles(plan.n_angles, n_subsets, m), s_add, f0.device)
+    subs = [_Subset(g, sens[m], subset_angles(plan.n_angles, n_subsets, m), s_add)
             for m in range(min(n_subsets, n_steps))]
     f = f0
     for k in range(n_steps):
         m = k % n_subsets
+        # with a table the attenuation map is not passed (the call takes one or the other)
         tab = None if tables is None else tables[m]
-        if checkpointing:
-            f = checkpoint(_osem_step, f, subs[m], plan, mu, tab, use_reentrant=False)
-        else:
-            f = _osem_step(f, subs[m], plan, mu, tab)
+        f = _OsemStep.apply(f, plan, subs[m], None if tab is not None else mu, tab)
     return f

@@ -405,6 +405,26 @@ size_t osem_ws(const spect_plan *p, int M, bool mu)
     return osem_q_bytes(p, M) + b;
 }
 
+// ---------------------------------------- subiteration over an angle list --
+// Workspace of osem_list_step: [q: projection rows of the list][scratch of
+// one forward and one back projection of the list sharing a tuning (and the
+// attenuation offsets, when mu is sampled)]; osem_list_step_vjp adds the
+// rows of Hf + s and one volume in front: [e][q][volume][scratch].
+size_t list_rows_bytes(const spect_plan *p, int nl) { return align256(sizeof(float) * (size_t)nl * p->N * p->Nz); }
+
+size_t list_scratch(const spect_plan *p, int nl, int att)
+{
+    const Tuning t = tune(p, nl, att, T_BOTH);
+    return tau_bytes(p, t, nl, att) + std::max(part_bytes(p, t, nl), z_bytes(p, t, nl));
+}
+
+size_t step_ws(const spect_plan *p, int nl, int att) { return list_rows_bytes(p, nl) + list_scratch(p, nl, att); }
+
+size_t step_vjp_ws(const spect_plan *p, int nl, int att)
+{
+    return 2 * list_rows_bytes(p, nl) + vol_bytes(p) + list_scratch(p, nl, att);
+}
+
 KernelFn fwd_kernel(int att, int kmc, bool vec)
 {
     switch (kmc) {
@@ -574,7 +594,8 @@ void launch_tau(const spect_plan *p, const AngleList &L, const Tuning &t, const 
 // already computed for the same list (the tau region is then skipped).
 int run_forward(const spect_plan *p, const float *f, const float *mu, int att, const float *table,
                 const AngleList &L, char *ws, size_t ws_avail, const float *tau_given, int mode, float *proj,
-                const float *g, const float *s_add, float *q, bool vec, int which, hipStream_t st)
+                const float *g, const float *s_add, float *q, bool vec, int which, hipStream_t st,
+                float *e_rows = nullptr)
 {
     const Tuning t = tune(p, L.n, att, which);
     if (fwd_need(p, L.n, att, which) > ws_avail)
@@ -610,7 +631,7 @@ int run_forward(const spect_plan *p, const float *f, const float *mu, int att, c
         ProfScope ps(K_FWD, st);
         hipLaunchKernelGGL(fk, dim3(t.nslab, t.nchunk, L.n), dim3(fwd_threads(p->N)), fwd_smem(p), st, a);
     }
-    ReduceArgs r;
+    ReduceArgs r{};
     r.L = L;
     r.part = part;
     r.N = p->N;
@@ -623,6 +644,7 @@ int run_forward(const spect_plan *p, const float *f, const float *mu, int att, c
     r.g = g;
     r.s_add = s_add;
     r.q = q;
+    r.e = e_rows;
     {
         ProfScope ps(K_REDUCE, st);
         hipLaunchKernelGGL(fwd_reduce, dim3((p->N * p->Nz + 255) / 256, L.n), dim3(256), 0, st, r);
@@ -637,7 +659,8 @@ int run_forward(const spect_plan *p, const float *f, const float *mu, int att, c
 // ATT_READ (from table).  ws holds [tau][z]; tau_given as in run_forward.
 int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const float *mu, int att,
              float *table, const AngleList &L, char *ws, size_t ws_avail, const float *tau_given, int mode,
-             float *out, const float *sens, bool vec, int which, hipStream_t st, const BsremTerms *bt = nullptr)
+             float *out, const float *sens, bool vec, int which, hipStream_t st, const BsremTerms *bt = nullptr,
+             const StepTerms *stt = nullptr)
 {
     const Tuning t = tune(p, L.n, att, which);
     if (back_need(p, L.n, att, which) > ws_avail)
@@ -693,7 +716,7 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
         ProfScope ps(K_BACK_ROT, st);
         hipLaunchKernelGGL(bk, dim3(t.nslab, t.nchunk, L.n), dim3(block_threads(p->N)), back_smem(p), st, b);
     }
-    GatherArgs gg;
+    GatherArgs gg{};
     gg.g = p->g;
     gg.L = L;
     gg.z = z;
@@ -702,6 +725,7 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
     gg.out = out;
     gg.sens = sens;
     gg.bt = bt ? *bt : BsremTerms{nullptr, nullptr, 0.f, 0.f};
+    gg.st = stt ? *stt : StepTerms{nullptr, nullptr, nullptr};
     const int tiles = (p->N + GT - 1) / GT;
     {
         ProfScope ps(K_GATHER, st);
@@ -1011,8 +1035,10 @@ int spect_workspace_size(const spect_plan *plan, int op, int32_t n_idx, int with
     if (with_mu < 0 || with_mu > SPECT_ATT_TABLE) return fail(SPECT_EINVAL, "with_mu = %d outside [0, 2]", with_mu);
     const bool mu = with_mu != 0;
     const bool tab = with_mu == SPECT_ATT_TABLE;
-    if (tab && op != SPECT_OP_FWD && op != SPECT_OP_BACK && op != SPECT_OP_SENS)
-        return fail(SPECT_EINVAL, "with_mu = SPECT_ATT_TABLE applies to SPECT_OP_FWD, _BACK and _SENS only");
+    if (tab && op != SPECT_OP_FWD && op != SPECT_OP_BACK && op != SPECT_OP_SENS && op != SPECT_OP_STEP &&
+        op != SPECT_OP_STEP_VJP)
+        return fail(SPECT_EINVAL,
+                    "with_mu = SPECT_ATT_TABLE applies to SPECT_OP_FWD, _BACK, _SENS, _STEP and _STEP_VJP only");
     switch (op) {
     case SPECT_OP_FWD: *bytes = fwd_ws(plan, n_idx, tab ? ATT_READ : att_of(mu)); break;
     case SPECT_OP_BACK: *bytes = back_ws(plan, n_idx, tab ? ATT_READ : att_of(mu)); break;
@@ -1033,6 +1059,13 @@ int spect_workspace_size(const spect_plan *plan, int op, int32_t n_idx, int with
         if (n_idx > plan->A) return fail(SPECT_EINVAL, "n_subsets %d exceeds n_angles %d", n_idx, plan->A);
         *bytes = recon_ws(plan, n_idx, mu) + 2 * vol_bytes(plan);
         break;
+    case SPECT_OP_STEP:
+    case SPECT_OP_STEP_VJP: {
+        if (n_idx > MAXL) return fail(SPECT_EUNSUPPORTED, "a subiteration over more than %d angles", MAXL);
+        const int att = tab ? ATT_READ : att_of(mu);
+        *bytes = op == SPECT_OP_STEP ? step_ws(plan, n_idx, att) : step_vjp_ws(plan, n_idx, att);
+        break;
+    }
     default: return fail(SPECT_EINVAL, "unknown op %d", op);
     }
     return ok();
@@ -1128,6 +1161,31 @@ int check_table(const float *table)
 {
     if (!table) return fail(SPECT_EINVAL, "table is NULL");
     if ((uintptr_t)table & 15) return fail(SPECT_EINVAL, "table is not 16-byte aligned");
+    return SPECT_OK;
+}
+
+// The angle list of a subiteration: 1 to MAXL distinct angles.
+int step_list(const spect_plan *p, const int32_t *idx, int32_t n_idx, std::vector<int> *list)
+{
+    int st;
+    if ((st = make_list(p, idx, n_idx, list))) return st;
+    if (list->empty()) return fail(SPECT_EINVAL, "the angle list is empty");
+    if ((int)list->size() > MAXL) return fail(SPECT_EUNSUPPORTED, "a subiteration over more than %d angles", MAXL);
+    std::vector<char> seen(p->A, 0);
+    for (int n : *list)
+        if (seen[n]++) return fail(SPECT_EINVAL, "angle %d is listed twice", n);
+    return SPECT_OK;
+}
+
+// Attenuation of a subiteration call: at most one of mu and table.
+int step_att(const float *mu, const float *table, int *att)
+{
+    if (mu && table) return fail(SPECT_EINVAL, "pass an attenuation map or a table, not both");
+    if (table) {
+        const int st = check_table(table);
+        if (st) return st;
+    }
+    *att = table ? ATT_READ : att_of(mu != nullptr);
     return SPECT_OK;
 }
 
@@ -1416,6 +1474,84 @@ int reconstruct(const spect_plan *plan, float *f, const float *mu, const float *
 }  // namespace
 
 extern "C" {
+
+int osem_list_step(const spect_plan *plan, const float *f, float *f_out, const float *mu, const float *table,
+                   const float *g, const float *s_add, const float *sens, const int32_t *angle_idx, int32_t n_idx,
+                   void *ws, size_t ws_bytes, void *stream)
+{
+    int st, att;
+    if ((st = check_plan(plan))) return st;
+    if ((st = check_ptr(f, "f", false)) || (st = check_ptr(f_out, "f_out", false)) || (st = check_ptr(mu, "mu", true)) ||
+        (st = check_ptr(g, "g", false)) || (st = check_ptr(s_add, "s_add", true)) ||
+        (st = check_ptr(sens, "sens", false)))
+        return st;
+    if ((st = step_att(mu, table, &att))) return st;
+    std::vector<int> list;
+    if ((st = step_list(plan, angle_idx, n_idx, &list))) return st;
+    const int nl = (int)list.size();
+    if ((st = check_ws(ws, ws_bytes, step_ws(plan, nl, att)))) return st;
+    const AngleList L = to_list(list.data(), nl);
+    const bool vec = want_vec(plan, {f, mu});
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    float *q = reinterpret_cast<float *>(w);
+    char *rest = w + list_rows_bytes(plan, nl);
+    const size_t avail = ws_bytes - list_rows_bytes(plan, nl);
+    if ((st = run_forward(plan, f, mu, att, table, L, rest, avail, nullptr, 1, nullptr, g, s_add, q, vec, T_BOTH, s)))
+        return st;
+    const StepTerms stt{f_out == f ? nullptr : f, nullptr, nullptr};
+    if ((st = run_back(plan, q, 1, 0, mu, att, const_cast<float *>(table), L, rest, avail,
+                       reinterpret_cast<const float *>(rest), 2, f_out, sens, vec, T_BOTH, s, nullptr, &stt)))
+        return st;
+    return ok();
+}
+
+int osem_list_step_vjp(const spect_plan *plan, const float *f, const float *mu, const float *table, const float *g,
+                       const float *s_add, const float *sens, const int32_t *angle_idx, int32_t n_idx,
+                       const float *grad_out, float *grad_f, void *ws, size_t ws_bytes, void *stream)
+{
+    int st, att;
+    if ((st = check_plan(plan))) return st;
+    if ((st = check_ptr(f, "f", false)) || (st = check_ptr(mu, "mu", true)) || (st = check_ptr(g, "g", false)) ||
+        (st = check_ptr(s_add, "s_add", true)) || (st = check_ptr(sens, "sens", false)) ||
+        (st = check_ptr(grad_out, "grad_out", false)) || (st = check_ptr(grad_f, "grad_f", false)))
+        return st;
+    if (grad_f == f) return fail(SPECT_EINVAL, "grad_f must not be f");
+    if ((st = step_att(mu, table, &att))) return st;
+    std::vector<int> list;
+    if ((st = step_list(plan, angle_idx, n_idx, &list))) return st;
+    const int nl = (int)list.size();
+    if ((st = check_ws(ws, ws_bytes, step_vjp_ws(plan, nl, att)))) return st;
+    const AngleList L = to_list(list.data(), nl);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // workspace [e][q][gb][scratch]
+    char *w = static_cast<char *>(ws);
+    const size_t rb = list_rows_bytes(plan, nl);
+    float *e = reinterpret_cast<float *>(w);
+    float *q = reinterpret_cast<float *>(w + rb);
+    float *gb = reinterpret_cast<float *>(w + 2 * rb);
+    char *rest = w + 2 * rb + vol_bytes(plan);
+    const size_t avail = ws_bytes - (2 * rb + vol_bytes(plan));
+    const float *tau = reinterpret_cast<const float *>(rest);  // offsets of the first pass, when mu is sampled
+    // e = H f + s and q = g / e on the listed rows
+    if ((st = run_forward(plan, f, mu, att, table, L, rest, avail, nullptr, 2, nullptr, g, s_add, q,
+                          want_vec(plan, {f, mu}), T_BOTH, s, e)))
+        return st;
+    // b = H^T q; grad_f = direct term of the update, gb = gradient in b
+    const StepTerms stt{f, grad_out, gb};
+    if ((st = run_back(plan, q, 1, 0, mu, att, const_cast<float *>(table), L, rest, avail, tau, 4, grad_f, sens,
+                       want_vec(plan, {mu}), T_BOTH, s, nullptr, &stt)))
+        return st;
+    // gradient in e: -g / e^2 (H gb) where e > 0
+    if ((st = run_forward(plan, gb, mu, att, table, L, rest, avail, tau, 3, nullptr, g, nullptr, q,
+                          want_vec(plan, {gb, mu}), T_BOTH, s, e)))
+        return st;
+    // grad_f += H^T of it
+    if ((st = run_back(plan, q, 1, 0, mu, att, const_cast<float *>(table), L, rest, avail, tau, 1, grad_f, nullptr,
+                       want_vec(plan, {mu}), T_BOTH, s)))
+        return st;
+    return ok();
+}
 
 int osem_reconstruct(const spect_plan *plan, float *f, const float *mu, const float *g, const float *s_add,
                      int32_t n_iters, int32_t n_subsets, void *ws, size_t ws_bytes, void *stream)

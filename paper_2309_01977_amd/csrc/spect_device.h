@@ -600,6 +600,10 @@ __device__ __forceinline__ void fzscatter(float (&acc)[FR + 2 * KMC], const floa
 template <int ATT, int KMC, bool VEC>
 struct FwdWalk {
     static constexpr bool MU = ATT == ATT_SAMPLE;
+    // the next depth's corner loads are issued before the current depth's
+    // blur; the widest blur classes keep their registers for the partial
+    // rows instead (the prefetch would make them spill)
+    static constexpr bool PREFETCH = KMC <= (MU ? 20 : 24);
     float4 *smem;
     const float *taps;  // this angle's taps, TS per depth
     int TS, N, Nz, jp, q, kb, nrows, ilo;
@@ -642,15 +646,17 @@ struct FwdWalk {
         return v;
     }
 
-    // depth ip of radius K (its corner loads were issued one depth earlier)
+    // depth ip of radius K (with PREFETCH its corner loads were issued one
+    // depth earlier)
     __device__ __forceinline__ void depth(int ip, int K)
     {
         float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
         if (active) {
+            if (!PREFETCH) cload(ip);
             w = zero_past_nz(fcombine(cn, vf));
             const float4 m = MU ? zero_past_nz(fcombine(cn, vm)) : w;
             // the next depth's corners (and factors), in flight during this blur
-            if (ip > ilo) cload(ip - 1);
+            if (PREFETCH && ip > ilo) cload(ip - 1);
             if (ATT == ATT_READ) {
                 w.x *= vt.x;
                 w.y *= vt.y;
@@ -755,7 +761,7 @@ __device__ __forceinline__ void fwd_body(const Args &a, int slab, int chunk, int
     w.tab = ATT == ATT_READ && w.live ? a.att + brick_offset(al, a.nslab, slab, N, 0, w.jp) + w.q * FR : nullptr;
     w.buf = 0;
     if (ATT == ATT_READ && w.active && ihi >= ilo) w.tload(ihi);
-    if (w.active && ihi >= ilo) w.cload(ihi);
+    if (w.PREFETCH && w.active && ihi >= ilo) w.cload(ihi);
     __syncthreads();
     for (int ip = ihi; ip >= ilo; --ip) w.depth(ip, uniform(kd[ip]));
 
@@ -809,11 +815,13 @@ struct ReduceArgs {
     AngleList L;
     const float *part;
     int N, Nz, nslab, nchunk, kmc;
-    int mode;           // 0: write projection rows; 1: OSEM ratio into q
+    int mode;           // 0: write projection rows; 1: OSEM ratio into q; 2: ratio into q and
+                        // e = Hf + s into e; 3: ratio derivative into q (see reduce_body)
     float *proj;        // mode 0: (A, N, Nz)
-    const float *g;     // mode 1: measured data (A, N, Nz)
-    const float *s_add; // mode 1: additive term or nullptr
-    float *q;           // mode 1: [L][N][Nz]
+    const float *g;     // modes 1-3: measured data (A, N, Nz)
+    const float *s_add; // modes 1, 2: additive term or nullptr
+    float *q;           // modes 1-3: [L][N][Nz]
+    float *e;           // mode 2 writes, mode 3 reads: [L][N][Nz]
 };
 
 #ifdef SPECT_HOST_TU
@@ -856,11 +864,21 @@ __device__ __forceinline__ void reduce_body(const Args &a, int blk, int al)
             if (ok[i]) sum += v[i];
     }
     const size_t o = ((size_t)ang * N + r) * Nz + k;
-    if (a.mode == 0) {
+    const size_t oc = ((size_t)al * N + r) * Nz + k;
+    const int mode = a.mode;
+    float *const q = a.q, *const ev = a.e;
+    const float *const gd = a.g, *const sa = a.s_add;
+    if (mode == 0) {
         a.proj[o] = sum;
+    } else if (mode != 3) {
+        const float e = sa ? sum + sa[o] : sum;
+        q[oc] = e > 0.f ? gd[o] / e : 0.f;
+        if (mode == 2) ev[oc] = e;
     } else {
-        const float e = a.s_add ? sum + a.s_add[o] : sum;
-        a.q[((size_t)al * N + r) * Nz + k] = e > 0.f ? a.g[o] / e : 0.f;
+        // sum = (H v)_o for the gradient v of the ratio q = g / e; its
+        // derivative in e is -g / e^2 where e > 0 and 0 elsewhere
+        const float e = ev[oc];
+        q[oc] = e > 0.f ? -sum * gd[o] / (e * e) : 0.f;
     }
 }
 
@@ -1206,15 +1224,29 @@ struct BsremTerms {
     float c_beta;           // subset share * prior weight
 };
 
+// Terms of the OSEM update and of its vector-Jacobian product (gather modes 2
+// and 4).  Mode 2 reads the image from fin when it is given (out-of-place
+// update) and from out otherwise.  Mode 4, with b the gathered sum:
+//     out = gout * b / sens,  gb = gout * fin / sens   where sens > 0,
+//     out = gout,             gb = 0                   elsewhere,
+// the derivatives of f' = f b / sens (f' = f where sens = 0) in f and in b.
+struct StepTerms {
+    const float *fin;
+    const float *gout;
+    float *gb;
+};
+
 struct GatherArgs {
     DevGeom g;
     AngleList L;
     const float *z;
     int nslab;
-    int mode;            // 0: out = sum; 1: out += sum; 2: OSEM update of out with sens; 3: BSREM update
+    int mode;            // 0: out = sum; 1: out += sum; 2: OSEM update of out with sens; 3: BSREM update;
+                         // 4: OSEM update derivative (StepTerms)
     float *out;
-    const float *sens;   // modes 2, 3: subset sensitivity H_m^T 1
+    const float *sens;   // modes 2-4: subset sensitivity H_m^T 1
     BsremTerms bt;       // mode 3
+    StepTerms st;        // modes 2, 4
 };
 
 // Transpose of the bilinear rotation, as a gather.  Workgroup = 8 x 8 object
@@ -1397,7 +1429,16 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
                 *p += acc[sl][r];
             } else if (a.mode == 2) {
                 const float sv = a.sens[base + k];
-                if (sv > 0.f) *p = *p * acc[sl][r] / sv;
+                if (a.st.fin) {
+                    const float fv = a.st.fin[base + k];
+                    *p = sv > 0.f ? fv * acc[sl][r] / sv : fv;
+                } else if (sv > 0.f) {
+                    *p = *p * acc[sl][r] / sv;
+                }
+            } else if (a.mode == 4) {
+                const float sv = a.sens[base + k], go = a.st.gout[base + k];
+                *p = sv > 0.f ? go * acc[sl][r] / sv : go;
+                a.st.gb[base + k] = sv > 0.f ? go * a.st.fin[base + k] / sv : 0.f;
             } else {
                 const float sa = a.bt.sens_all[base + k];
                 if (sa > 0.f) {

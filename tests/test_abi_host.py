@@ -85,6 +85,11 @@ def test_null_arguments_are_rejected_before_any_device_call():
     assert lib.spect_sensitivity(None, None, None, None, 0, None, 0, None) == B.SPECT_EINVAL
     assert lib.osem_subset_step(None, None, None, None, None, None, 0, 1, None, 0, None) == B.SPECT_EINVAL
     assert lib.osem_reconstruct(None, None, None, None, None, 1, 1, None, 0, None) == B.SPECT_EINVAL
+    assert lib.osem_list_step(None, None, None, None, None, None, None, None, None, 0, None, 0,
+                              None) == B.SPECT_EINVAL
+    assert lib.osem_list_step_vjp(None, None, None, None, None, None, None, None, 0, None, None, None, 0,
+                                  None) == B.SPECT_EINVAL
+    assert lib.spect_workspace_size(None, B.OP_STEP_VJP, 1, 2, ctypes.byref(sz)) == B.SPECT_EINVAL
     assert "plan is NULL" in lib.spect_last_error().decode()
     assert lib.spect_plan_destroy(None) == B.SPECT_OK
     assert lib.spect_last_error().decode() == ""

@@ -4,7 +4,11 @@ Checks, through the C ABI: the gradient of a projection is the oracle's
 transpose (and the gradient of a back projection its forward projection);
 the gradient of the loss of 10 unrolled OSEM subiterations with respect to
 the initial image matches the FP64 oracle's reverse recursion and central
-finite differences (eps 1e-3); checkpointing and batching change nothing.
+finite differences (eps 1e-3); checkpointing and batching change nothing; the
+fused subiteration over an angle list (osem_list_step) equals the subset
+subiteration bitwise and the oracle's step, and its vector-Jacobian product
+(osem_list_step_vjp) matches the oracle's reverse step and central
+differences; invalid lists are refused.
 Bar: projections within 1e-5 relative L2 (the projector bar); the unrolled
 loss and its gradient within 1e-4 relative L2 (the OSEM bar: the gradient
 applies the same FP32 projectors as the OSEM run, twice as often).
@@ -202,3 +206,124 @@ def test_batch_of_eight_at_128cube_matches_the_oracle():
     say(f"  member 0: loss rel err {el:.2e}, gradient rel L2 {eg:.2e}")
     assert el <= GRAD_TOL and eg <= GRAD_TOL
     assert np.isfinite(host(f.grad)).all()
+
+
+def _oracle_step(og, f, g, mu, idx, s=None):
+    """The oracle's OSEM subiteration over the angles idx (0/0 readings as in
+    osem_list_step), composed from its forward and back projections."""
+    ghat = O.forward(og, f, mu, idx)
+    if s is not None:
+        ghat[idx] += s[idx]
+    q = np.zeros(og.proj_shape)
+    rows = np.zeros(og.proj_shape, dtype=bool)
+    rows[idx] = ghat[idx] > 0
+    q[rows] = g[rows] / ghat[rows]
+    b = O.back(og, q, mu, idx)
+    sens = O.back(og, np.ones(og.proj_shape), mu, idx)
+    out = f.copy()
+    pos = sens > 0
+    out[pos] = f[pos] * b[pos] / sens[pos]
+    return out
+
+
+@pytest.mark.parametrize("with_s", [False, True])
+def test_list_step_equals_the_subset_step(with_s):
+    og, plan, f_true, mu, g, s = small_problem(50, with_s=with_s)
+    M, m = 4, 1
+    idx = list(range(m, og.n_angles, M))
+    mud, gd, sd = dev(mu), dev(g), None if s is None else dev(s)
+    sens = plan.sensitivity(mud, idx)
+    f0 = dev(f_true * 0.5 + 0.3)
+    ref = f0.clone()
+    plan.osem_subset_step(ref, gd, sens, m, M, mud, sd)
+    out = plan.osem_list_step(f0, gd, sens, idx, mu=mud, s_add=sd)
+    inplace = f0.clone()
+    plan.osem_list_step(inplace, gd, sens, idx, mu=mud, s_add=sd, out=inplace)
+    np.testing.assert_array_equal(host(out), host(ref))
+    np.testing.assert_array_equal(host(inplace), host(ref))
+    # the subset's attenuation table in place of the map
+    sens_t, table = plan.sensitivity_table(mud, idx)
+    out_t = plan.osem_list_step(f0, gd, sens_t, idx, table=table, s_add=sd)
+    e = rel_l2(host(out_t), host(ref))
+    say(f"  s={'yes' if with_s else 'no'}: table vs map {e:.2e}")
+    assert e <= 1e-5
+
+
+@pytest.mark.parametrize("variant", ["map", "map+s", "table", "none"])
+def test_list_step_product_matches_the_oracle_reverse_step(variant):
+    """One subiteration followed by the loss mean((f1 - target)^2): the
+    product of osem_list_step_vjp with 2 (f1 - target) / n is the oracle's
+    dL/df0 for n_steps = 1."""
+    og, plan, f_true, mu, g, s = small_problem(51, with_s=variant == "map+s")
+    M = 3
+    idx = list(range(0, og.n_angles, M))
+    mu_o = None if variant == "none" else mu.astype(np.float64)
+    if variant == "none":
+        g = P.poisson_counts(O.forward(og, f_true.astype(np.float64)), 2e5, np.random.default_rng(52))
+    r = np.random.default_rng(53)
+    f0 = (P.random_object(og.object_shape, r) + 0.5).astype(np.float32)
+    loss_ref, grad_ref = O.unrolled_osem_grad(og, g.astype(np.float64), f0.astype(np.float64),
+                                              f_true.astype(np.float64), 1, M, mu_o,
+                                              None if s is None else s.astype(np.float64))
+    mud = None if variant == "none" else dev(mu)
+    gd, sd = dev(g), None if s is None else dev(s)
+    kw = dict(mu=mud, s_add=sd)
+    if variant == "table":
+        sens, table = plan.sensitivity_table(mud, idx)
+        kw = dict(table=table)
+    else:
+        sens = plan.sensitivity(mud, idx)
+    fd = dev(f0)
+    f1 = plan.osem_list_step(fd, gd, sens, idx, **kw)
+    gout = 2.0 * (f1 - dev(f_true)) / f1.numel()
+    grad = plan.osem_list_step_vjp(fd, gd, sens, idx, gout, **kw)
+    # the gradient may overwrite grad_out
+    grad2 = plan.osem_list_step_vjp(fd, gd, sens, idx, gout, out=gout, **kw)
+    eg = rel_l2(host(grad), grad_ref)
+    say(f"  {variant}: gradient rel L2 {eg:.2e}")
+    assert eg <= GRAD_TOL
+    np.testing.assert_array_equal(host(grad2), host(grad))
+
+
+def test_list_step_on_an_arbitrary_list_matches_the_oracle_and_central_differences():
+    og, plan, f_true, mu, g, s = small_problem(54, with_s=True)
+    idx = [2, 3, 9, 10, 11, 19]
+    mud, gd, sd = dev(mu), dev(g), dev(s)
+    sens = plan.sensitivity(mud, idx)
+    r = np.random.default_rng(55)
+    f0 = (P.random_object(og.object_shape, r) + 0.5).astype(np.float32)
+    out = plan.osem_list_step(dev(f0), gd, sens, idx, mu=mud, s_add=sd)
+    ref = _oracle_step(og, f0.astype(np.float64), g.astype(np.float64), mu.astype(np.float64), idx,
+                       s.astype(np.float64))
+    e = rel_l2(host(out), ref)
+    say(f"  step vs oracle: {e:.2e}")
+    assert e <= GRAD_TOL
+    w = dev(r.standard_normal(og.object_shape))
+    grad = plan.osem_list_step_vjp(dev(f0), gd, sens, idx, w, mu=mud, s_add=sd).double()
+    eps = 1e-3
+    for t in range(3):
+        v = dev(r.standard_normal(og.object_shape))
+        fp = plan.osem_list_step(dev(f0) + eps * v, gd, sens, idx, mu=mud, s_add=sd).double()
+        fm = plan.osem_list_step(dev(f0) - eps * v, gd, sens, idx, mu=mud, s_add=sd).double()
+        fdd = ((fp - fm) * w.double()).sum().item() / (2 * eps)
+        an = (grad * v.double()).sum().item()
+        say(f"  direction {t}: central difference {fdd:.6e}, product {an:.6e}")
+        assert abs(fdd - an) <= 1e-2 * abs(an)
+
+
+def test_list_step_refuses_invalid_lists():
+    og, plan, f_true, mu, g, _ = small_problem(56)
+    mud, gd, fd = dev(mu), dev(g), dev(f_true)
+    sens = plan.sensitivity(mud, [0, 1])
+    with pytest.raises(S.SpectError, match="listed twice"):
+        plan.osem_list_step(fd, gd, sens, [0, 1, 0], mu=mud)
+    with pytest.raises(S.SpectError, match="empty"):
+        plan.osem_list_step(fd, gd, sens, [], mu=mud)
+    _, table = plan.sensitivity_table(mud, [0, 1])
+    with pytest.raises(ValueError, match="not both"):
+        plan.osem_list_step(fd, gd, sens, [0, 1], mu=mud, table=table)
+    big = S.Plan(8, 4, 130, 0.48)
+    f8 = torch.ones(big.object_shape, device="cuda")
+    g8 = torch.ones(big.proj_shape, device="cuda")
+    with pytest.raises(S.SpectError, match="more than 128"):
+        big.osem_list_step(f8, g8, f8, None)
