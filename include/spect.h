@@ -226,35 +226,48 @@ int osem_batch_autotune(spect_batch *batch, float *const *f, const float *const 
 int spect_batch_schedule(const spect_batch *batch, int32_t *schedule, double *candidate_ms);
 int spect_batch_set_schedule(spect_batch *batch, int32_t schedule);
 
-/* Reconstruction server: continuous admission of whole OSEM reconstructions
- * (osem_reconstruct) as they arrive, for serving many studies (Section 4).
+/* Reconstruction server with continuous batching: OSEM reconstructions of
+ * many studies (Section 4) admitted as they arrive and advanced together.
  *
- * The server owns pool_bytes of device memory and n_slots HIP streams
- * (default priority).  spect_server_submit queues a request in arrival order;
- * the head of the queue is admitted as soon as a slot is idle and the pool
+ * A request is a whole reconstruction (the computation of osem_reconstruct):
+ * the sensitivity pass of each subset (with an attenuation map it also fills
+ * the subset's attenuation-factor table), then n_iters x n_subsets
+ * subiterations; each of these is one step.  A scheduler thread owned by the
+ * server launches ticks back to back on the server's stream (default
+ * priority); a tick takes the next step of every resident request, whatever
+ * its geometry, subset or iteration, and runs them together as one launch
+ * per stage (sensitivity pass, forward projection with the ratio, the
+ * rotated-frame adjoint, gather with the update; the forward and adjoint
+ * stages once per blur-radius class).  At every tick boundary the head of
+ * the arrival-order queue is admitted when fewer than n_slots requests are
+ * resident and the pool (pool_bytes of device memory owned by the server)
  * holds a free block of the request's workspace (spect_workspace_size with
- * SPECT_OP_RECON), so requests arriving while others run start at once and
- * their kernels overlap on the device; a request that does not fit waits (and
- * so do the ones behind it) until running requests free their memory.
- * Finished requests are retired by spect_server_progress (non-blocking: it
- * polls completion events, then admits) or spect_server_wait (blocks).  The
- * caller owns f (the initial image on submission, the reconstruction once the
- * request is SPECT_REQ_DONE), mu, g, s_add, and keeps them alive and
- * untouched until then.  Results equal osem_reconstruct alone.  Not
- * thread-safe: one host thread drives a server.
+ * SPECT_OP_RECON); a head that does not fit waits, and so do the requests
+ * behind it.  A request retires, freeing its block, once the tick holding
+ * its last step has finished.  Its state lives in its block, laid out as
+ * osem_reconstruct's workspace, and its steps use osem_reconstruct's launch
+ * arguments: the result equals osem_reconstruct alone, bitwise, whatever
+ * shares its ticks.  With an attenuation map the tables of all subsets must
+ * fit in 32 GiB (SPECT_EUNSUPPORTED otherwise).
  *
- * Ordering: spect_server_submit records an event on `stream` (the caller's
- * HIP stream; NULL = the null stream), and the request's kernels wait for it
- * on the device, so f, mu, g and s_add may still be being written by work
- * the caller queued on that stream before the call.  A request is finished
- * once spect_server_wait returns or its state reads SPECT_REQ_DONE; the
- * caller may then read f on any stream.
+ * The caller owns f (the initial image on submission, the reconstruction
+ * once the request is SPECT_REQ_DONE), mu, g, s_add, and keeps them alive
+ * and untouched until then.  Ordering: spect_server_submit records an event
+ * on `stream` (the caller's HIP stream; NULL = the null stream) and the
+ * request's first tick waits for it on the device, so f, mu, g and s_add may
+ * still be being written by work the caller queued on that stream before the
+ * call.  A request is finished once spect_server_wait returns or its state
+ * reads SPECT_REQ_DONE; the caller may then read f on any stream.
  *
+ * The calls may come from any host thread (the server serialises them).
  * spect_server_submit fails with SPECT_EINVAL if the request's workspace can
- * never fit in the pool.  spect_server_status: *state = SPECT_REQ_*; a failed
- * request returns its error code and message.  spect_server_forget drops the
- * record of a finished request.  spect_server_destroy waits for all running
- * requests; queued ones are dropped. */
+ * never fit in the pool.  spect_server_progress reports the resident and
+ * queued counts (the scheduler thread does the work).  spect_server_status:
+ * *state = SPECT_REQ_*; a failed request returns its error code and message.
+ * spect_server_wait blocks until the request is done or failed.
+ * spect_server_forget drops the record of a finished request.
+ * spect_server_destroy finishes every resident request; queued ones are
+ * dropped. */
 #define SPECT_REQ_QUEUED 0
 #define SPECT_REQ_RUNNING 1
 #define SPECT_REQ_DONE 2
@@ -270,8 +283,8 @@ int spect_server_progress(spect_server *server, int32_t *n_running, int32_t *n_q
 int spect_server_status(spect_server *server, int64_t request_id, int32_t *state);
 int spect_server_wait(spect_server *server, int64_t request_id);
 int spect_server_forget(spect_server *server, int64_t request_id);
-/* Running and queued counts, the largest number of requests ever running at
- * once, and the pool bytes in use. */
+/* Resident and queued counts, the largest number of requests ever resident
+ * at once, and the pool bytes in use. */
 int spect_server_stats(const spect_server *server, int32_t *n_running, int32_t *n_queued,
                        int32_t *peak_running, size_t *pool_in_use);
 

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "spect.h"
+#include "spect_internal.h"
 
 using namespace spectk;
 
@@ -2272,3 +2273,332 @@ int osem_batch_autotune(spect_batch *b, float *const *f, const float *const *mu,
 }
 
 }  // extern "C"
+
+// ============================================= iteration-level batching ===
+//
+// The engine behind the reconstruction server: every call launches one
+// "tick" in which each listed request advances by one step, either one
+// subset's sensitivity pass (which also fills that subset's attenuation
+// table) or one OSEM subiteration, through the work-list kernels, all
+// requests together: one launch per stage (and per blur class for the
+// forward and rotated-frame kernels).  A request's state lives in its own
+// region laid out as osem_reconstruct's workspace, and its launch arguments
+// and tuning are the ones osem_reconstruct uses, so a request advanced tick
+// by tick ends with osem_reconstruct's result bitwise, whatever else shares
+// its ticks.
+
+namespace spect_internal {
+
+struct TickTables {
+    std::vector<char> blob;
+    struct Launch {
+        int kind;  // 0 sensitivity, 1 forward, 2 reduce, 3 rotated-frame, 4 gather
+        const void *fn;
+        int threads;
+        size_t smem;
+        size_t args, tasks;  // blob offsets
+        int ntasks;
+    };
+    std::vector<Launch> launches;
+};
+
+namespace {
+
+struct ItemLayout {
+    float *sens, *table, *q;
+    char *rest;
+};
+
+ItemLayout item_layout(const TickItem &it)
+{
+    const spect_plan *p = it.plan;
+    const int M = it.n_subsets;
+    const bool mu = it.mu != nullptr;
+    const size_t vb = vol_bytes(p);
+    ItemLayout l;
+    l.sens = reinterpret_cast<float *>(it.region + (size_t)it.subset * vb);
+    size_t off = (size_t)M * vb;
+    l.table = nullptr;
+    for (int m = 0; m < M; ++m) {
+        if (m == it.subset && mu) l.table = reinterpret_cast<float *>(it.region + off);
+        off += recon_tau_bytes(p, M, m, mu);
+    }
+    l.q = reinterpret_cast<float *>(it.region + off);
+    l.rest = it.region + off + osem_q_bytes(p, M);
+    return l;
+}
+
+AngleList subset_list(const spect_plan *p, int M, int m)
+{
+    std::vector<int> list;
+    for (int n = m; n < p->A; n += M) list.push_back(n);
+    return to_list(list.data(), (int)list.size());
+}
+
+}  // namespace
+
+int tick_region_bytes(const spect_plan *p, int n_subsets, bool mu, size_t *bytes)
+{
+    int st;
+    if ((st = check_plan(p))) return st;
+    if (n_subsets < 1 || n_subsets > p->A)
+        return fail(SPECT_EINVAL, "n_subsets = %d outside [1, %d]", n_subsets, p->A);
+    if ((p->A + n_subsets - 1) / n_subsets > MAXL)
+        return fail(SPECT_EUNSUPPORTED, "subsets of more than %d angles", MAXL);
+    if (mu && !use_table(p, n_subsets, true))
+        return fail(SPECT_EUNSUPPORTED, "the attenuation tables of this request exceed %zu bytes", kMaxTableBytes);
+    *bytes = recon_ws(p, n_subsets, mu);
+    return SPECT_OK;
+}
+
+double step_work(const spect_plan *p, int n_subsets)
+{
+    return (double)p->N * p->N * p->Nz * ((p->A + n_subsets - 1) / std::max(1, n_subsets));
+}
+
+TickTables *tick_build(const TickItem *items, int n, int *status)
+{
+    auto *T = new TickTables();
+    // launch groups: sensitivity passes by kernel variant; forward and
+    // rotated-frame passes by blur class and load width
+    struct Group {
+        std::vector<FwdArgs> fa;
+        std::vector<BackRotArgs> ba;
+        std::vector<std::pair<long, Task>> ft, bt;
+        int nmax = 0;
+    };
+    struct SensGroup {
+        std::vector<BackRotArgs> sa;
+        std::vector<Task> st;
+        size_t smem = 0;
+    };
+    std::vector<std::pair<std::pair<int, int>, Group>> groups;   // (kmc, vec)
+    std::vector<std::pair<int, SensGroup>> sgroups;               // variant: 0 none, 1 write, 2 write (pairs)
+    std::vector<ReduceArgs> ra;
+    std::vector<Task> rt;
+    std::vector<GatherArgs> ga;
+    std::vector<Task> gt;
+    auto group = [&](int kmc, int vec) -> std::pair<int, Group &> {
+        for (size_t i = 0; i < groups.size(); ++i)
+            if (groups[i].first == std::make_pair(kmc, vec)) return {(int)i, groups[i].second};
+        groups.push_back({{kmc, vec}, Group()});
+        return {(int)groups.size() - 1, groups.back().second};
+    };
+    for (int i = 0; i < n; ++i) {
+        const TickItem &it = items[i];
+        const spect_plan *p = it.plan;
+        const int M = it.n_subsets, m = it.subset;
+        const bool mu = it.mu != nullptr;
+        const ItemLayout lay = item_layout(it);
+        const AngleList L = subset_list(p, M, m);
+        const bool vec = want_vec(p, {it.f, it.mu});
+        const int tiles = (p->N + GT - 1) / GT;
+        if (it.sens) {
+            // the sensitivity pass of osem_reconstruct (run_back with a
+            // constant projection: one depth chunk, tap sums, mu sampled and
+            // its factors stored in the subset's table)
+            const Tuning t = tune(p, L.n, mu ? ATT_WRITE : ATT_NONE, mu ? T_BACK : T_BOTH);
+            const bool v2 = mu && p->Nz % 2 == 0 && aligned8(it.mu);
+            const int var = !mu ? 0 : (v2 ? 2 : 1);
+            size_t si = 0;
+            while (si < sgroups.size() && sgroups[si].first != var) ++si;
+            if (si == sgroups.size()) sgroups.push_back({var, SensGroup()});
+            SensGroup &sg = sgroups[si].second;
+            BackRotArgs sb{};
+            sb.g = p->g;
+            sb.L = L;
+            sb.ones = 1;
+            sb.mu = it.mu;
+            sb.att = lay.table;
+            sb.z = reinterpret_cast<float *>(lay.rest);
+            sb.nslab = t.nslab;
+            sb.nchunk = 1;
+            sb.cbset = 0;
+            sb.vec = vec;
+            const int li = (int)sg.sa.size();
+            sg.sa.push_back(sb);
+            sg.smem = std::max(sg.smem, sens_smem(p->N, p->TS));
+            const int sblk = (p->N * (SLAB / 2) + SL_THREADS - 1) / SL_THREADS;
+            for (int al = 0; al < L.n; ++al)
+                for (int sl = 0; sl < t.nslab; ++sl)
+                    for (int k = 0; k < sblk; ++k) sg.st.push_back(Task{li, k, sl, al});
+            GatherArgs gg{};
+            gg.g = p->g;
+            gg.L = L;
+            gg.z = reinterpret_cast<float *>(lay.rest);
+            gg.nslab = t.nslab;
+            gg.mode = 0;
+            gg.out = lay.sens;
+            const int gi = (int)ga.size();
+            ga.push_back(gg);
+            for (int sp = 0; sp < (t.nslab + GS - 1) / GS; ++sp)
+                for (int k = 0; k < tiles * tiles; ++k) gt.push_back(Task{gi, k, sp, 0});
+            continue;
+        }
+        // one subiteration, as osem_reconstruct runs it (run_forward with the
+        // fused ratio, run_back with the fused update, shared tuning)
+        const int att = mu ? ATT_READ : ATT_NONE;
+        const Tuning t = tune(p, L.n, att, T_BOTH);
+        auto gr = group(p->kmc, vec ? 1 : 0);
+        Group &G = gr.second;
+        G.nmax = std::max(G.nmax, p->N);
+        float *scr = reinterpret_cast<float *>(lay.rest);
+        FwdArgs a{};
+        a.g = p->g;
+        a.L = L;
+        a.f = it.f;
+        a.att = lay.table;
+        a.part = scr;
+        a.nslab = t.nslab;
+        a.nchunk = t.nchunk;
+        a.cbset = 0;
+        a.vec = vec;
+        const int fi = (int)G.fa.size();
+        G.fa.push_back(a);
+        ReduceArgs rr{};
+        rr.L = L;
+        rr.part = scr;
+        rr.N = p->N;
+        rr.Nz = p->Nz;
+        rr.nslab = t.nslab;
+        rr.nchunk = t.nchunk;
+        rr.kmc = p->kmc;
+        rr.mode = 1;
+        rr.g = it.g;
+        rr.s_add = it.s_add;
+        rr.q = lay.q;
+        const int ri = (int)ra.size();
+        ra.push_back(rr);
+        BackRotArgs bb{};
+        bb.g = p->g;
+        bb.L = L;
+        bb.y = lay.q;
+        bb.y_compact = 1;
+        bb.att = lay.table;
+        bb.z = scr;
+        bb.nslab = t.nslab;
+        bb.nchunk = t.nchunk;
+        bb.cbset = back_set(att);
+        bb.vec = vec;
+        G.ba.push_back(bb);
+        GatherArgs gg{};
+        gg.g = p->g;
+        gg.L = L;
+        gg.z = scr;
+        gg.nslab = t.nslab;
+        gg.mode = 2;
+        gg.out = it.f;
+        gg.sens = lay.sens;
+        const int gi = (int)ga.size();
+        ga.push_back(gg);
+        for (int al = 0; al < L.n; ++al)
+            for (int c = 0; c < t.nchunk; ++c) {
+                const long fc = (long)(chunk_work(p, 0, t.nchunk, L.idx[al], c) * p->N);
+                const long bc = (long)(chunk_work(p, bb.cbset, t.nchunk, L.idx[al], c) * p->N);
+                for (int sl = 0; sl < t.nslab; ++sl) {
+                    G.ft.push_back({fc, Task{fi, sl, c, al}});
+                    G.bt.push_back({bc, Task{fi, sl, c, al}});
+                }
+            }
+        const int blocks = (p->N * p->Nz + 255) / 256;
+        for (int al = 0; al < L.n; ++al)
+            for (int k = 0; k < blocks; ++k) rt.push_back(Task{ri, k, 0, al});
+        for (int sp = 0; sp < (t.nslab + GS - 1) / GS; ++sp)
+            for (int k = 0; k < tiles * tiles; ++k) gt.push_back(Task{gi, k, sp, 0});
+    }
+    auto by_cost = [](const std::pair<long, Task> &x, const std::pair<long, Task> &y) { return x.first > y.first; };
+    auto add = [&](int kind, const void *fn, int threads, size_t smem, size_t args, size_t tasks, int ntasks) {
+        if (ntasks > 0) T->launches.push_back(TickTables::Launch{kind, fn, threads, smem, args, tasks, ntasks});
+    };
+    // stage order: sensitivity passes, forward, reduction, rotated-frame, gather
+    for (auto &sg : sgroups) {
+        const void *fn = sg.first == 0   ? reinterpret_cast<const void *>(sensl_batch<ATT_NONE, false>)
+                         : sg.first == 2 ? reinterpret_cast<const void *>(sensl_batch<ATT_WRITE, true>)
+                                         : reinterpret_cast<const void *>(sensl_batch<ATT_WRITE, false>);
+        const size_t ao = put(T->blob, sg.second.sa), to = put(T->blob, sg.second.st);
+        add(0, fn, SL_THREADS, sg.second.smem, ao, to, (int)sg.second.st.size());
+    }
+    std::vector<size_t> bo(groups.size()), bto(groups.size());
+    std::vector<int> bn(groups.size());
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        Group &G = groups[gi].second;
+        const int kmc = groups[gi].first.first, vec = groups[gi].first.second;
+        std::stable_sort(G.ft.begin(), G.ft.end(), by_cost);
+        std::stable_sort(G.bt.begin(), G.bt.end(), by_cost);
+        std::vector<Task> ftv, btv;
+        for (auto &x : G.ft) ftv.push_back(x.second);
+        for (auto &x : G.bt) btv.push_back(x.second);
+        const int att = G.fa[0].att ? ATT_READ : ATT_NONE;
+        const size_t ao = put(T->blob, G.fa), to = put(T->blob, ftv);
+        add(1, reinterpret_cast<const void *>(fwd_batch_kernel(att, kmc, vec, false)), fwd_threads(G.nmax),
+            fwd_smem(G.nmax, kmc), ao, to, (int)ftv.size());
+        bo[gi] = put(T->blob, G.ba);
+        bto[gi] = put(T->blob, btv);
+        bn[gi] = (int)btv.size();
+    }
+    {
+        const size_t ao = put(T->blob, ra), to = put(T->blob, rt);
+        add(2, reinterpret_cast<const void *>(reduce_batch), 256, 0, ao, to, (int)rt.size());
+    }
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        Group &G = groups[gi].second;
+        const int kmc = groups[gi].first.first, vec = groups[gi].first.second;
+        const int att = G.fa[0].att ? ATT_READ : ATT_NONE;
+        add(3, reinterpret_cast<const void *>(back_batch_kernel(att, kmc, vec, false)), block_threads(G.nmax),
+            back_smem(G.nmax, kmc), bo[gi], bto[gi], bn[gi]);
+    }
+    {
+        const size_t ao = put(T->blob, ga), to = put(T->blob, gt);
+        add(4, reinterpret_cast<const void *>(gather_batch), 256, 0, ao, to, (int)gt.size());
+    }
+    *status = SPECT_OK;
+    return T;
+}
+
+size_t tick_bytes(const TickTables *T) { return T->blob.size(); }
+
+int tick_launch(TickTables *T, char *host, char *dev, hipStream_t st)
+{
+    if (!T->blob.empty()) {
+        std::memcpy(host, T->blob.data(), T->blob.size());
+        const hipError_t e = hipMemcpyAsync(dev, host, T->blob.size(), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "tick table upload");
+    }
+    for (const TickTables::Launch &l : T->launches) {
+        static const int prof[5] = {K_SENS, K_FWD_B, K_REDUCE_B, K_BACK_B, K_GATHER_B};
+        allow_smem(l.fn, l.smem);
+        ProfScope ps(prof[l.kind], st);
+        const Task *tasks = reinterpret_cast<const Task *>(dev + l.tasks);
+        switch (l.kind) {
+        case 0:
+        case 3: {
+            BatchList<BackRotArgs> b{reinterpret_cast<const BackRotArgs *>(dev + l.args), tasks, l.ntasks};
+            hipLaunchKernelGGL(reinterpret_cast<void (*)(BatchList<BackRotArgs>)>(const_cast<void *>(l.fn)),
+                               dim3(l.ntasks), dim3(l.threads), l.smem, st, b);
+            break;
+        }
+        case 1: {
+            BatchList<FwdArgs> b{reinterpret_cast<const FwdArgs *>(dev + l.args), tasks, l.ntasks};
+            hipLaunchKernelGGL(reinterpret_cast<void (*)(BatchList<FwdArgs>)>(const_cast<void *>(l.fn)),
+                               dim3(l.ntasks), dim3(l.threads), l.smem, st, b);
+            break;
+        }
+        case 2: {
+            BatchList<ReduceArgs> b{reinterpret_cast<const ReduceArgs *>(dev + l.args), tasks, l.ntasks};
+            hipLaunchKernelGGL(reduce_batch, dim3(l.ntasks), dim3(256), 0, st, b);
+            break;
+        }
+        default: {
+            BatchList<GatherArgs> b{reinterpret_cast<const GatherArgs *>(dev + l.args), tasks, l.ntasks};
+            hipLaunchKernelGGL(gather_batch, dim3(l.ntasks), dim3(256), 0, st, b);
+            break;
+        }
+        }
+    }
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SPECT_OK : hip_fail(e, "tick launch");
+}
+
+void tick_free(TickTables *T) { delete T; }
+
+}  // namespace spect_internal

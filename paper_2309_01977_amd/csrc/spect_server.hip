@@ -1,24 +1,35 @@
-// spect_server.hip - reconstruction server: continuous admission of OSEM
-// requests onto concurrent HIP streams, with workspaces carved from one
-// device memory pool (admission by memory footprint).
+// spect_server.hip - reconstruction server with continuous (iteration-level)
+// batching: requests are admitted as they arrive, by resident count and
+// memory footprint, and every resident request advances together, one step
+// per tick, through the work-list kernels.
 //
-// A request is a whole reconstruction (osem_reconstruct).  Requests queue in
-// arrival order; the head of the queue is admitted as soon as a slot (a HIP
-// stream) is idle and the pool has a free block of the request's workspace
-// size, so requests that arrive while others run start without waiting for
-// them, and their kernels overlap on the device.  Completion is detected by
-// polling an event recorded after the request's launches.  A request's
-// launches wait (on the device) for an event recorded on the caller's stream
-// when it was submitted, so inputs the caller produced asynchronously are
-// complete before the reconstruction reads them.
+// A request is a whole OSEM reconstruction (the computation of
+// osem_reconstruct): the sensitivity pass of each subset (which also fills
+// the subset's attenuation table), then n_iters x n_subsets subiterations.
+// Each of these is one step.  A scheduler thread launches ticks back to back
+// on up to four lanes (streams, which run concurrently): a lane's tick takes
+// the next step of each of the lane's resident requests (requests at
+// different subsets, iterations and geometries alike) and runs them as one
+// launch per stage (see tick_build).  Requests queue in arrival order; at
+// every tick boundary the head of the queue is admitted, to the lane with
+// the least work left, as soon as fewer than n_slots requests are resident
+// and the pool holds a free block of its workspace; a request retires once
+// the tick holding its last step has finished, freeing its block.  A request's state lives in its
+// block laid out as osem_reconstruct's workspace and its steps use
+// osem_reconstruct's launch arguments, so its result is osem_reconstruct's,
+// bitwise, whatever shares its ticks.  The first tick of a request waits (on
+// the device) for an event recorded on the caller's stream at submission.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <deque>
+#include <map>
+#include <mutex>
 #include <string>
-#include <unordered_map>
+#include <thread>
 #include <vector>
 
 #include "spect.h"
@@ -37,7 +48,8 @@ struct Request {
     size_t ws = 0, off = 0;
     hipEvent_t ready = nullptr;  // recorded on the caller's stream at submission
     int state = SPECT_REQ_QUEUED;
-    int slot = -1;
+    int steps = 0, issued = 0;   // steps of the request, steps launched so far
+    double step_work = 0;        // voxel-angles of one step
     int err = SPECT_OK;
     std::string msg;
 };
@@ -45,6 +57,16 @@ struct Request {
 struct Block {
     size_t off, size;
 };
+
+// Buffers of one tick's launch tables; reused once the tick has finished.
+struct TickSlot {
+    char *host = nullptr, *dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    std::vector<int64_t> finishing;  // requests whose last step is in this tick
+};
+
+constexpr int kRing = 3;
 
 size_t round256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -61,18 +83,36 @@ int failf(int code, const char *fmt, ...)
 
 }  // namespace
 
+// A lane: a stream with its own ticks over its own resident requests.
+// Lanes run concurrently, so the kernels of different lanes overlap on the
+// device; within a lane every tick advances all of its requests together.
+struct Lane {
+    hipStream_t stream = nullptr;
+    std::vector<int64_t> resident;  // admitted and unfinished, in admission order
+    TickSlot ring[kRing];
+    std::deque<int> inflight;       // ring slots in launch order
+    std::deque<long> seq;           // global launch number of each in-flight tick
+};
+
+constexpr int kMaxLanes = 4;
+
 struct spect_server {
     int device = 0;
-    std::vector<hipStream_t> slots;
-    std::vector<hipEvent_t> done;
-    std::vector<int64_t> busy;  // request per slot, -1 when idle
+    int max_resident = 1;
+    std::vector<Lane> lanes;
     char *pool = nullptr;
     size_t pool_bytes = 0, in_use = 0;
     std::vector<Block> free_list;  // sorted by offset, coalesced
     std::deque<int64_t> queue;
-    std::unordered_map<int64_t, Request> reqs;
+    std::map<int64_t, Request> reqs;
     int64_t next_id = 1;
     int peak_running = 0;
+    long ticks = 0;  // ticks launched
+    std::mutex mu;
+    std::condition_variable wake;   // submissions and shutdown, for the scheduler
+    std::condition_variable done;   // retirements, for waiting callers
+    bool stop = false;
+    std::thread worker;
 
     bool alloc(size_t n, size_t *off)
     {
@@ -114,66 +154,200 @@ struct spect_server {
     int running() const
     {
         int n = 0;
-        for (int64_t r : busy) n += r >= 0;
+        for (const Lane &l : lanes) n += (int)l.resident.size();
         return n;
     }
 
-    // Retire finished requests, then admit from the head of the queue.
-    void progress()
+    // A resident request leaves: its block returns to the pool.  Called once
+    // the stream has passed every tick that used the block.
+    void retire(Lane &ln, int64_t id, int state, int err, const std::string &msg)
     {
-        for (size_t k = 0; k < slots.size(); ++k) {
-            if (busy[k] < 0) continue;
-            const hipError_t e = hipEventQuery(done[k]);
-            if (e == hipErrorNotReady) continue;
-            Request &r = reqs[busy[k]];
-            if (e == hipSuccess) {
-                r.state = SPECT_REQ_DONE;
-            } else {
-                r.state = SPECT_REQ_FAILED;
-                r.err = SPECT_EHIP;
-                r.msg = hipGetErrorString(e);
-            }
-            release(r.off, r.ws);
-            drop_ready(r);
-            r.slot = -1;
-            busy[k] = -1;
+        Request &r = reqs[id];
+        r.state = state;
+        r.err = err;
+        r.msg = msg;
+        release(r.off, r.ws);
+        drop_ready(r);
+        ln.resident.erase(std::remove(ln.resident.begin(), ln.resident.end(), id), ln.resident.end());
+    }
+
+    // work a lane still has to launch: steps left x voxel-angles per step
+    double lane_load(const Lane &ln)
+    {
+        double n = 0;
+        for (int64_t id : ln.resident) {
+            const Request &r = reqs[id];
+            n += (double)(r.steps - r.issued) * r.step_work;
         }
-        while (!queue.empty()) {
-            int k = -1;
-            for (size_t i = 0; i < slots.size(); ++i)
-                if (busy[i] < 0) {
-                    k = (int)i;
-                    break;
-                }
-            if (k < 0) break;
+        return n;
+    }
+
+    // Admit from the head of the queue while a resident place and a pool
+    // block are free (arrival order is kept: a head that does not fit waits).
+    void admit()
+    {
+        while (!queue.empty() && running() < max_resident) {
             Request &r = reqs[queue.front()];
             size_t off = 0;
-            if (!alloc(r.ws, &off)) break;  // the head waits for memory; arrival order is kept
+            if (!alloc(r.ws, &off)) break;
             const int64_t id = queue.front();
             queue.pop_front();
-            int st = SPECT_OK;
-            if (hipStreamWaitEvent(slots[k], r.ready, 0) != hipSuccess) {
-                st = set_error(SPECT_EHIP, "slot stream could not wait for the submission event");
-            } else {
-                st = osem_reconstruct(r.plan, r.f, r.mu, r.g, r.s, r.iters, r.subsets, pool + off, r.ws, slots[k]);
-                if (st == SPECT_OK && hipEventRecord(done[k], slots[k]) != hipSuccess) st = SPECT_EHIP;
-            }
-            if (st != SPECT_OK) {
-                r.state = SPECT_REQ_FAILED;
-                r.err = st;
-                r.msg = spect_last_error();
+            r.off = off;
+            r.issued = 0;
+            if (r.iters == 0) {
+                // nothing changes f (osem_reconstruct with zero iterations)
+                r.state = SPECT_REQ_DONE;
                 release(off, r.ws);
-                // the slot stream may hold the wait on the event: destroy it
-                // only once the stream has drained
-                (void)hipStreamSynchronize(slots[k]);
                 drop_ready(r);
+                done.notify_all();
                 continue;
             }
-            r.off = off;
-            r.slot = k;
             r.state = SPECT_REQ_RUNNING;
-            busy[k] = id;
+            // the lane with the fewest steps left
+            Lane *best = &lanes[0];
+            for (Lane &ln : lanes)
+                if (lane_load(ln) < lane_load(*best)) best = &ln;
+            best->resident.push_back(id);
             peak_running = std::max(peak_running, running());
+        }
+    }
+
+    // Retire the requests of lane ln's oldest tick if it has finished
+    // (block: wait for it first).  Called with the lock held; waits without it.
+    void finish_oldest(Lane &ln, std::unique_lock<std::mutex> &lk, bool block)
+    {
+        if (ln.inflight.empty()) return;
+        TickSlot &ts = ln.ring[ln.inflight.front()];
+        hipError_t e = hipEventQuery(ts.done);
+        if (e == hipErrorNotReady) {
+            if (!block) return;
+            const hipEvent_t ev = ts.done;
+            lk.unlock();
+            e = hipEventSynchronize(ev);
+            lk.lock();
+        }
+        ln.inflight.pop_front();
+        ln.seq.pop_front();
+        for (int64_t id : ts.finishing) {
+            if (e == hipSuccess)
+                retire(ln, id, SPECT_REQ_DONE, SPECT_OK, "");
+            else
+                retire(ln, id, SPECT_REQ_FAILED, SPECT_EHIP, hipGetErrorString(e));
+        }
+        ts.finishing.clear();
+        if (e != hipSuccess) fail_resident(ln, SPECT_EHIP, hipGetErrorString(e));
+        done.notify_all();
+    }
+
+    // A launch or runtime error: every resident request of the lane fails
+    // once its stream has drained.
+    void fail_resident(Lane &ln, int err, const std::string &msg)
+    {
+        (void)hipStreamSynchronize(ln.stream);
+        ln.inflight.clear();
+        ln.seq.clear();
+        for (TickSlot &ts : ln.ring) ts.finishing.clear();
+        std::vector<int64_t> ids = ln.resident;
+        for (int64_t id : ids) retire(ln, id, SPECT_REQ_FAILED, err, msg);
+        done.notify_all();
+    }
+
+    // Launch lane ln's next tick: the next step of each of its resident
+    // requests with steps left.  Returns false if there was nothing to launch.
+    bool launch_tick(Lane &ln, std::unique_lock<std::mutex> &lk)
+    {
+        std::vector<spect_internal::TickItem> items;
+        std::vector<int64_t> ids, first, last;
+        for (int64_t id : ln.resident) {
+            Request &r = reqs[id];
+            if (r.issued >= r.steps) continue;
+            const int k = r.issued, M = r.subsets;
+            spect_internal::TickItem it{r.plan, r.f, r.mu, r.g, r.s, pool + r.off, M, k < M ? 1 : 0,
+                                        k < M ? k : (k - M) % M};
+            items.push_back(it);
+            ids.push_back(id);
+            if (k == 0) first.push_back(id);
+            if (k + 1 == r.steps) last.push_back(id);
+        }
+        if (items.empty()) return false;
+        int slot = -1;
+        for (int k = 0; k < kRing; ++k)
+            if (std::find(ln.inflight.begin(), ln.inflight.end(), k) == ln.inflight.end()) {
+                slot = k;
+                break;
+            }
+        TickSlot &ts = ln.ring[slot];
+        std::vector<hipEvent_t> waits;
+        for (int64_t id : first) waits.push_back(reqs[id].ready);
+        lk.unlock();
+        // host work and launches without the lock: only this thread changes
+        // resident requests, the rings and the streams
+        int st = SPECT_OK;
+        std::string msg;
+        int bst = SPECT_OK;
+        spect_internal::TickTables *T = spect_internal::tick_build(items.data(), (int)items.size(), &bst);
+        const size_t need = spect_internal::tick_bytes(T);
+        if (need > ts.cap) {
+            if (ts.host) (void)hipHostFree(ts.host);
+            if (ts.dev) (void)hipFree(ts.dev);
+            ts.host = ts.dev = nullptr;
+            ts.cap = 0;
+            const size_t cap = std::max(need + need / 2, size_t(1) << 20);
+            if (hipHostMalloc(reinterpret_cast<void **>(&ts.host), cap) != hipSuccess ||
+                hipMalloc(reinterpret_cast<void **>(&ts.dev), cap) != hipSuccess) {
+                st = SPECT_ENOMEM;
+                msg = "tick table allocation failed";
+            } else {
+                ts.cap = cap;
+            }
+        }
+        for (hipEvent_t ev : waits)
+            if (st == SPECT_OK && hipStreamWaitEvent(ln.stream, ev, 0) != hipSuccess) {
+                st = SPECT_EHIP;
+                msg = "a lane stream could not wait for a submission event";
+            }
+        if (st == SPECT_OK) {
+            st = spect_internal::tick_launch(T, ts.host, ts.dev, ln.stream);
+            if (st != SPECT_OK) msg = spect_last_error();
+        }
+        if (st == SPECT_OK && hipEventRecord(ts.done, ln.stream) != hipSuccess) {
+            st = SPECT_EHIP;
+            msg = "tick event record failed";
+        }
+        spect_internal::tick_free(T);
+        lk.lock();
+        if (st != SPECT_OK) {
+            fail_resident(ln, st, msg);
+            return true;
+        }
+        for (int64_t id : ids) reqs[id].issued++;
+        ts.finishing = last;
+        ln.inflight.push_back(slot);
+        ln.seq.push_back(ticks++);
+        return true;
+    }
+
+    void run()
+    {
+        (void)hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            for (Lane &ln : lanes) finish_oldest(ln, lk, false);
+            if (!stop) admit();
+            bool launched = false;
+            for (Lane &ln : lanes)
+                if ((int)ln.inflight.size() < kRing && launch_tick(ln, lk)) launched = true;
+            if (launched) continue;
+            // wait for the oldest tick in flight on any lane
+            Lane *oldest = nullptr;
+            for (Lane &ln : lanes)
+                if (!ln.inflight.empty() && (!oldest || ln.seq.front() < oldest->seq.front())) oldest = &ln;
+            if (oldest) {
+                finish_oldest(*oldest, lk, true);
+                continue;
+            }
+            if (stop && running() == 0) break;
+            wake.wait(lk, [&] { return stop || !queue.empty(); });
         }
     }
 };
@@ -191,25 +365,25 @@ int spect_server_create(int32_t n_slots, size_t pool_bytes, spect_server **out)
         delete s;
         return set_error(SPECT_EHIP, "no HIP device");
     }
+    s->max_resident = n_slots;
     s->pool_bytes = pool_bytes & ~size_t(255);
     if (hipMalloc(reinterpret_cast<void **>(&s->pool), s->pool_bytes) != hipSuccess) {
         delete s;
         return failf(SPECT_ENOMEM, "hipMalloc of a %zu-byte pool failed", pool_bytes);
     }
     s->free_list.push_back(Block{0, s->pool_bytes});
-    for (int k = 0; k < n_slots; ++k) {
-        hipStream_t st = nullptr;
-        hipEvent_t ev = nullptr;
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-            if (st) (void)hipStreamDestroy(st);
-            spect_server_destroy(s);
-            return set_error(SPECT_EHIP, "stream or event creation failed");
-        }
-        s->slots.push_back(st);
-        s->done.push_back(ev);
-        s->busy.push_back(-1);
+    s->lanes.resize(std::min(n_slots, kMaxLanes));
+    bool okay = true;
+    for (Lane &ln : s->lanes) {
+        okay = okay && hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) == hipSuccess;
+        for (TickSlot &ts : ln.ring)
+            okay = okay && hipEventCreateWithFlags(&ts.done, hipEventDisableTiming) == hipSuccess;
     }
+    if (!okay) {
+        spect_server_destroy(s);
+        return set_error(SPECT_EHIP, "stream or event creation failed");
+    }
+    s->worker = std::thread([s] { s->run(); });
     *out = s;
     return clear_error();
 }
@@ -217,9 +391,27 @@ int spect_server_create(int32_t n_slots, size_t pool_bytes, spect_server **out)
 int spect_server_destroy(spect_server *s)
 {
     if (!s) return clear_error();
-    for (size_t k = 0; k < s->slots.size(); ++k) (void)hipStreamSynchronize(s->slots[k]);
-    for (hipStream_t st : s->slots) (void)hipStreamDestroy(st);
-    for (hipEvent_t ev : s->done) (void)hipEventDestroy(ev);
+    if (s->worker.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stop = true;
+            for (int64_t id : s->queue) spect_server::drop_ready(s->reqs[id]);
+            s->queue.clear();
+        }
+        s->wake.notify_all();
+        s->worker.join();
+    }
+    for (Lane &ln : s->lanes) {
+        if (ln.stream) {
+            (void)hipStreamSynchronize(ln.stream);
+            (void)hipStreamDestroy(ln.stream);
+        }
+        for (TickSlot &ts : ln.ring) {
+            if (ts.done) (void)hipEventDestroy(ts.done);
+            if (ts.host) (void)hipHostFree(ts.host);
+            if (ts.dev) (void)hipFree(ts.dev);
+        }
+    }
     for (auto &kv : s->reqs) spect_server::drop_ready(kv.second);
     if (s->pool) (void)hipFree(s->pool);
     delete s;
@@ -235,7 +427,7 @@ int spect_server_submit(spect_server *s, const spect_plan *plan, float *f, const
     if (!plan || !f || !g) return set_error(SPECT_EINVAL, "plan, f and g must not be NULL");
     if (n_iters < 0) return failf(SPECT_EINVAL, "n_iters = %d is negative", n_iters);
     size_t ws = 0;
-    int st = spect_workspace_size(plan, SPECT_OP_RECON, n_subsets, mu != nullptr, &ws);
+    int st = spect_internal::tick_region_bytes(plan, n_subsets, mu != nullptr, &ws);
     if (st) return st;
     ws = round256(std::max<size_t>(ws, 256));
     if (ws > s->pool_bytes)
@@ -248,6 +440,8 @@ int spect_server_submit(spect_server *s, const spect_plan *plan, float *f, const
     r.s = s_add;
     r.iters = n_iters;
     r.subsets = n_subsets;
+    r.steps = n_subsets * (1 + n_iters);
+    r.step_work = spect_internal::step_work(plan, n_subsets);
     r.ws = ws;
     if (hipEventCreateWithFlags(&r.ready, hipEventDisableTiming) != hipSuccess)
         return set_error(SPECT_EHIP, "event creation failed");
@@ -255,18 +449,21 @@ int spect_server_submit(spect_server *s, const spect_plan *plan, float *f, const
         (void)hipEventDestroy(r.ready);
         return set_error(SPECT_EHIP, "could not record the submission event on the caller's stream");
     }
-    const int64_t id = s->next_id++;
-    s->reqs[id] = r;
-    s->queue.push_back(id);
-    *request_id = id;
-    s->progress();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        const int64_t id = s->next_id++;
+        s->reqs[id] = r;
+        s->queue.push_back(id);
+        *request_id = id;
+    }
+    s->wake.notify_all();
     return clear_error();
 }
 
 int spect_server_progress(spect_server *s, int32_t *n_running, int32_t *n_queued)
 {
     if (!s) return set_error(SPECT_EINVAL, "server is NULL");
-    s->progress();
+    std::lock_guard<std::mutex> lk(s->mu);
     if (n_running) *n_running = s->running();
     if (n_queued) *n_queued = (int32_t)s->queue.size();
     return clear_error();
@@ -275,6 +472,7 @@ int spect_server_progress(spect_server *s, int32_t *n_running, int32_t *n_queued
 int spect_server_status(spect_server *s, int64_t request_id, int32_t *state)
 {
     if (!s || !state) return set_error(SPECT_EINVAL, "server and state must not be NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->reqs.find(request_id);
     if (it == s->reqs.end()) return failf(SPECT_EINVAL, "unknown request %lld", (long long)request_id);
     *state = it->second.state;
@@ -285,31 +483,23 @@ int spect_server_status(spect_server *s, int64_t request_id, int32_t *state)
 int spect_server_wait(spect_server *s, int64_t request_id)
 {
     if (!s) return set_error(SPECT_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->reqs.find(request_id);
     if (it == s->reqs.end()) return failf(SPECT_EINVAL, "unknown request %lld", (long long)request_id);
-    for (;;) {
-        s->progress();
-        const Request &r = s->reqs[request_id];
-        if (r.state == SPECT_REQ_DONE) return clear_error();
-        if (r.state == SPECT_REQ_FAILED) return set_error(r.err, r.msg.c_str());
-        // wait for the request itself, or for any running one to free its slot and memory
-        int k = r.slot;
-        if (k < 0)
-            for (size_t i = 0; i < s->busy.size(); ++i)
-                if (s->busy[i] >= 0) {
-                    k = (int)i;
-                    break;
-                }
-        if (k < 0) return set_error(SPECT_EINVAL, "request cannot be admitted: nothing running, head blocked");
-        const hipError_t e = hipEventSynchronize(s->done[k]);
-        if (e != hipSuccess && e != hipErrorNotReady) return failf(SPECT_EHIP, "wait: %s", hipGetErrorString(e));
-    }
+    s->done.wait(lk, [&] {
+        const int st = s->reqs[request_id].state;
+        return st == SPECT_REQ_DONE || st == SPECT_REQ_FAILED;
+    });
+    const Request &r = s->reqs[request_id];
+    if (r.state == SPECT_REQ_FAILED) return set_error(r.err, r.msg.c_str());
+    return clear_error();
 }
 
 int spect_server_stats(const spect_server *s, int32_t *n_running, int32_t *n_queued, int32_t *peak_running,
                        size_t *pool_in_use)
 {
     if (!s) return set_error(SPECT_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(const_cast<spect_server *>(s)->mu);
     if (n_running) *n_running = s->running();
     if (n_queued) *n_queued = (int32_t)s->queue.size();
     if (peak_running) *peak_running = s->peak_running;
@@ -320,6 +510,7 @@ int spect_server_stats(const spect_server *s, int32_t *n_running, int32_t *n_que
 int spect_server_forget(spect_server *s, int64_t request_id)
 {
     if (!s) return set_error(SPECT_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->reqs.find(request_id);
     if (it == s->reqs.end()) return failf(SPECT_EINVAL, "unknown request %lld", (long long)request_id);
     if (it->second.state != SPECT_REQ_DONE && it->second.state != SPECT_REQ_FAILED)

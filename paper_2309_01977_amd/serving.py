@@ -1,12 +1,14 @@
 """Serving driver: replay a stream of reconstruction requests through the
-native server (spect_server_*) and record per-request latency.
+native server (spect_server_*, continuous batching) or one at a time through
+plain osem_reconstruct calls, and record per-request latency.
 
 A trace is a list of (arrival time in seconds, request class); a request
 class bundles a plan, its data sets and the OSEM schedule.  The driver
 submits each request when the wall clock reaches its arrival time (the f of
 a request is a fresh image of ones), polls the server between arrivals, and
 records completion at the first poll that sees the request done.  Latency =
-completion - arrival.
+completion - arrival.  The one-at-a-time baseline runs each request when it
+has arrived and the previous one has finished.
 """
 from __future__ import annotations
 
@@ -95,6 +97,31 @@ def replay(server: Server, classes: Sequence[RequestClass], trace: Sequence[Tupl
             nxt = trace[i][0] if i < len(trace) else None
             if nxt is None or nxt - (time.perf_counter() - t0) > poll_sleep_s:
                 time.sleep(poll_sleep_s)
+    return served
+
+
+def replay_one_at_a_time(classes: Sequence[RequestClass], trace: Sequence[Tuple[float, int]],
+                         keep_images: bool = False) -> List[Served]:
+    """The baseline: each request is one osem_reconstruct call on the current
+    stream, started when it has arrived and the previous one has finished."""
+    served: List[Served] = []
+    counters = [0] * len(classes)
+    t0 = time.perf_counter()
+    for arrival, c in trace:
+        wait = arrival - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        rc = classes[c]
+        k = counters[c] % len(rc.data)
+        counters[c] += 1
+        f = torch.ones(rc.plan.object_shape, dtype=torch.float32, device="cuda")
+        rec = Served(c, arrival, time.perf_counter() - t0, f=f, data_index=k)
+        rc.plan.reconstruct(rc.data[k], rc.n_iters, rc.n_subsets, None if rc.mu is None else rc.mu[k], f=f)
+        torch.cuda.synchronize()
+        rec.done = time.perf_counter() - t0
+        if not keep_images:
+            rec.f = None
+        served.append(rec)
     return served
 
 

@@ -1,10 +1,12 @@
 """The reconstruction server (spect_server_*) on the GPU.
 
 Each result must be the same alone (osem_reconstruct on its own) and in the
-mix (admitted while other requests run, their kernels overlapping on the
-device): the bar is the OSEM bar, 1e-4 relative L2, and the same kernels on
-the same inputs make it bitwise in practice; one request per class is also
-checked against the FP64 oracle.  Admission follows the memory footprint.
+mix (admitted while other requests are resident, every tick advancing all of
+them together through shared launches): the bar is the OSEM bar, 1e-4
+relative L2, and the server's steps use osem_reconstruct's arguments, so the
+results are asserted bitwise; one request per class is also checked against
+the FP64 oracle.  Admission follows the memory footprint; a short request
+admitted beside a long one finishes first (iteration-level scheduling).
 """
 import sys
 
@@ -190,4 +192,35 @@ def test_requests_wait_for_inputs_written_on_the_callers_stream():
     e = rel_l2(got, ref)
     say(f"  inputs written on the caller's stream: vs alone {e:.2e}")
     assert e == 0.0
+    server.close()
+
+
+def test_short_requests_finish_first_beside_long_ones():
+    """A long reconstruction (3 iterations x 6 subsets at 40^2 x 20 with
+    attenuation) and, submitted after it, short ones (1 x 3 at 24^2 x 16):
+    all are resident together and every tick advances each of them by one
+    step, so the short requests finish while the long one still runs; all
+    results equal their reconstructions alone bitwise."""
+    cls = make_classes(86, per_class=3)
+    og_l, plan_l, gs_l, mus_l, _, _ = cls[2]
+    og_s, plan_s, gs_s, _, _, _ = cls[0]
+    server = S.Server(4, 1 << 30)
+    f_long = torch.ones(plan_l.object_shape, device="cuda")
+    rid_long = server.submit(plan_l, f_long, dev(gs_l[0]), 3, 6, dev(mus_l[0]))
+    shorts = []
+    for k in range(3):
+        f = torch.ones(plan_s.object_shape, device="cuda")
+        shorts.append((server.submit(plan_s, f, dev(gs_s[k]), 1, 3), f, k))
+    states = []
+    for rid, f, k in shorts:
+        server.wait(rid)
+        states.append(server.status(rid_long))
+    server.wait(rid_long)
+    peak = server.stats()[2]
+    say(f"  long request's state as each short one finished: {states}, peak resident {peak}")
+    assert peak == 4
+    assert states[-1] == S.REQ_RUNNING
+    for rid, f, k in shorts:
+        assert rel_l2(host(f), alone(plan_s, gs_s[k], None, 1, 3)) == 0.0
+    assert rel_l2(host(f_long), alone(plan_l, gs_l[0], mus_l[0], 3, 6)) == 0.0
     server.close()
