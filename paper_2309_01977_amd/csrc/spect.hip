@@ -35,6 +35,7 @@ struct spect_plan {
     int kmc;    // compile-time radius class (multiple of 4, <= 32)
     int TS;     // tap row stride
     int device;
+    int cus;            // compute units of the device
     int fwd_slots[4];   // resident forward workgroups on the device, per attenuation mode
     int back_slots[4];  // same for the rotated-frame back-projection kernel
     void *dmem;
@@ -704,13 +705,20 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
         else if (att == ATT_SAMPLE) sk = v2 ? sens_line<ATT_SAMPLE, true> : sens_line<ATT_SAMPLE, false>;
         else if (att == ATT_NONE) sk = sens_line<ATT_NONE, false>;
         if (!sk) return fail(SPECT_EINVAL, "no sensitivity pass for attenuation mode %d", att);
+        const int nblk = (p->N * (SLAB / 2) + SL_THREADS - 1) / SL_THREADS;
+        // without attenuation the depths are independent: split them into
+        // chunks until the launch fills the device (2 blocks per CU)
         b.nchunk = 1;
+        if (att == ATT_NONE) {
+            const long blocks = (long)nblk * t.nslab * L.n;
+            b.nchunk = (int)std::min<long>(std::max(1, p->N / 8), (2L * p->cus + blocks - 1) / blocks);
+            b.nchunk = std::max(1, b.nchunk);
+        }
         b.cbset = 0;
         const size_t smem = sens_smem(p->N, p->TS);
         allow_smem(reinterpret_cast<const void *>(sk), smem);
         ProfScope ps(K_SENS, st);
-        hipLaunchKernelGGL(sk, dim3((p->N * (SLAB / 2) + SL_THREADS - 1) / SL_THREADS, t.nslab, L.n),
-                           dim3(SL_THREADS), smem, st, b);
+        hipLaunchKernelGGL(sk, dim3(nblk * b.nchunk, t.nslab, L.n), dim3(SL_THREADS), smem, st, b);
     } else {
         BackFn bk = back_kernel(att, p->kmc, vec);
         allow_smem(reinterpret_cast<const void *>(bk), back_smem(p));
@@ -729,8 +737,13 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
     gg.st = stt ? *stt : StepTerms{nullptr, nullptr, nullptr};
     const int tiles = (p->N + GT - 1) / GT;
     {
+        // one slab per workgroup when two would leave the device under-filled
+        const bool one = (long)tiles * tiles * ((t.nslab + GS - 1) / GS) < 2L * p->cus;
         ProfScope ps(K_GATHER, st);
-        hipLaunchKernelGGL(back_gather, dim3(tiles * tiles, (t.nslab + GS - 1) / GS), dim3(256), 0, st, gg);
+        if (one)
+            hipLaunchKernelGGL(back_gather<1>, dim3(tiles * tiles, t.nslab), dim3(256), 0, st, gg);
+        else
+            hipLaunchKernelGGL(back_gather<GS>, dim3(tiles * tiles, (t.nslab + GS - 1) / GS), dim3(256), 0, st, gg);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "back projection launch");
@@ -995,6 +1008,7 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cus < 1)
         cus = 256;
+    p->cus = cus;
     for (int att = ATT_NONE; att <= ATT_READ; ++att) {
         int nb = 0;
         const void *fk = reinterpret_cast<const void *>(fwd_kernel(att == ATT_WRITE ? ATT_SAMPLE : att, p->kmc, true));

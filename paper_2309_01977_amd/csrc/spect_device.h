@@ -1072,12 +1072,18 @@ constexpr int SL_THREADS = 256;
 
 template <int ATT, bool V2, class Args>
 __device__ __forceinline__ void sensl_walk(const Args &a, int jp, int rp, int slab, int al, int ang,
-                                           const float *ctl);
+                                           const float *ctl, int chunk);
 
+// blk: thread block within the (slab, angle) and, without attenuation (no
+// running sum), depth chunk: blocks of chunk c are c * nblk .. c * nblk +
+// nblk - 1 for the nchunk equal depth chunks of the launch.
 template <int ATT, bool V2, class Args>
 __device__ __forceinline__ void sensl_body(const Args &a, int blk, int slab, int al)
 {
     const int N = a.g.N;
+    const int nblk = (N * (SLAB / 2) + SL_THREADS - 1) / SL_THREADS;
+    const int chunk = blk / nblk;
+    blk -= chunk * nblk;
     const int t = blk * SL_THREADS + threadIdx.x;
     const int jp = t >> 3, rp = t & 7;
     const int ang = uniform(a.L.idx[al]);
@@ -1092,7 +1098,7 @@ __device__ __forceinline__ void sensl_body(const Args &a, int blk, int slab, int
         for (int i = threadIdx.x; i < N * TS; i += SL_THREADS) ctl[i] = cta[i];
     }
     __syncthreads();
-    if (jp < N) sensl_walk<ATT, V2>(a, jp, rp, slab, al, ang, ctl);
+    if (jp < N) sensl_walk<ATT, V2>(a, jp, rp, slab, al, ang, ctl, chunk);
     __syncthreads();  // a batch's next task rewrites the sums
 }
 
@@ -1100,7 +1106,7 @@ __device__ __forceinline__ void sensl_body(const Args &a, int blk, int slab, int
 // ctl holds the angle's running tap sums, TS per depth.
 template <int ATT, bool V2, class Args>
 __device__ __forceinline__ void sensl_walk(const Args &a, int jp, int rp, int slab, int al, int ang,
-                                           const float *ctl)
+                                           const float *ctl, int chunk)
 {
     constexpr bool MU = ATT == ATT_SAMPLE || ATT == ATT_WRITE;
     const int N = a.g.N, Nz = a.g.Nz;
@@ -1173,10 +1179,17 @@ __device__ __forceinline__ void sensl_walk(const Args &a, int jp, int rp, int sl
         }
         *reinterpret_cast<float2 *>(a.z + e) = make_float2(u0, u1);
     };
+    Samp s0, s1, s2, s3;
+    if (!MU) {
+        // no attenuation: the depths are independent; this chunk's only
+        const int len = (N + a.nchunk - 1) / a.nchunk;
+        const int ihi = N - 1 - chunk * len, ilo = max(0, ihi - len + 1);
+        for (int ip = ihi; ip >= ilo; --ip) step(ip, s0);
+        return;
+    }
     // four sample buffers used in turn: the corners of the depth three
     // steps ahead are loaded before this depth is computed and stored, and
     // every load is waited for only where it is used (no register copies)
-    Samp s0, s1, s2, s3;
     if (MU) {
         sample(N - 1, s0);
         sample(max(N - 2, 0), s1);
@@ -1284,7 +1297,9 @@ __device__ __forceinline__ float quad_bcast(float v)
     return __int_as_float(quad_bcast<SRC>(__float_as_int(v)));
 }
 
-template <class Args>
+// NS slabs per workgroup: GS, or 1 for launches too small to fill the
+// device (the sums are formed in the same order either way).
+template <int NS, class Args>
 __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
 {
     const int N = a.g.N, Nz = a.g.Nz;
@@ -1294,12 +1309,12 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
     const int x = (tile / tiles) * GT + wave * 2 + (col >> 3);
     const int y = (tile % tiles) * GT + (col & 7);
     if (x >= N || y >= N) return;  // whole quads leave together
-    const int slab0 = pair * GS;
-    const int nsl = min(GS, a.nslab - slab0);  // slabs present in this pair
+    const int slab0 = pair * NS;
+    const int nsl = min(NS, a.nslab - slab0);  // slabs present in this pair
     const float c = 0.5f * (float)(N - 1);
     const float xx = (float)x - c, yy = (float)y - c;
     const float fxv = (float)x, fyv = (float)y;
-    float acc[GS][4] = {};
+    float acc[NS][4] = {};
     const size_t zstride = (size_t)a.nslab * N * N * SLAB;
     const float *zs = a.z + (size_t)slab0 * N * N * SLAB;
     const int qoff = 16 * q;
@@ -1331,9 +1346,9 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
     __shared__ float2 ctab[256 / 4][9];
     float2 *qt = ctab[threadIdx.x >> 2];
     // loaded candidate bricks, kept across angles (see below)
-    float4 vv[GS][GC];
+    float4 vv[NS][GC];
 #pragma unroll
-    for (int sl = 0; sl < GS; ++sl)
+    for (int sl = 0; sl < NS; ++sl)
 #pragma unroll
         for (int k = 0; k < GC; ++k) vv[sl][k] = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int al = 0; al < a.L.n; ++al) {
@@ -1386,14 +1401,14 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
             if (hk[k]) {
                 const int off = __float_as_int(ek[k].y) + qoff;
 #pragma unroll
-                for (int sl = 0; sl < GS; ++sl)
+                for (int sl = 0; sl < NS; ++sl)
                     vv[sl][k] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(zr, off + sl * planeb, 0, 0));
             }
         }
 #pragma unroll
         for (int k = 0; k < GC; ++k) {
 #pragma unroll
-            for (int sl = 0; sl < GS; ++sl) {
+            for (int sl = 0; sl < NS; ++sl) {
                 acc[sl][0] = fmaf(wk[k], vv[sl][k].x, acc[sl][0]);
                 acc[sl][1] = fmaf(wk[k], vv[sl][k].y, acc[sl][1]);
                 acc[sl][2] = fmaf(wk[k], vv[sl][k].z, acc[sl][2]);
@@ -1406,7 +1421,7 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
             m &= m - 1;
             const int off = __float_as_int(e.y) + qoff;
 #pragma unroll
-            for (int sl = 0; sl < GS; ++sl) {
+            for (int sl = 0; sl < NS; ++sl) {
                 const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(zr, off + sl * planeb, 0, 0));
                 acc[sl][0] = fmaf(e.x, v.x, acc[sl][0]);
                 acc[sl][1] = fmaf(e.x, v.y, acc[sl][1]);
@@ -1417,7 +1432,7 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
     }
     const size_t base = ((size_t)x * N + y) * Nz;
 #pragma unroll
-    for (int sl = 0; sl < GS; ++sl) {
+    for (int sl = 0; sl < NS; ++sl) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int k = (slab0 + sl) * SLAB + 4 * q + r;
@@ -1454,7 +1469,11 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
 #endif  // SPECT_HOST_TU
 
 #ifdef SPECT_HOST_TU
-__global__ __launch_bounds__(256) void back_gather(GatherArgs a) { gather_body(a, blockIdx.x, blockIdx.y); }
+template <int NS>
+__global__ __launch_bounds__(256) void back_gather(GatherArgs a)
+{
+    gather_body<NS>(a, blockIdx.x, blockIdx.y);
+}
 
 __global__ __launch_bounds__(256) void gather_batch(BatchList<GatherArgs> b)
 {
@@ -1462,7 +1481,7 @@ __global__ __launch_bounds__(256) void gather_batch(BatchList<GatherArgs> b)
     ConstMem<Task> *tasks = as_const(b.tasks);
     for (int t = blockIdx.x; t < b.ntasks; t += gridDim.x) {
         const int r = tasks[t].r, x = tasks[t].x, y = tasks[t].y;
-        gather_body(args[r], x, y);
+        gather_body<GS>(args[r], x, y);
     }
 }
 

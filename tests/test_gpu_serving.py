@@ -205,12 +205,18 @@ def test_short_requests_finish_first_beside_long_ones():
     og_l, plan_l, gs_l, mus_l, _, _ = cls[2]
     og_s, plan_s, gs_s, _, _, _ = cls[0]
     server = S.Server(4, 1 << 30)
+    g_long, mu_long = dev(gs_l[0]), dev(mus_l[0])
+    g_short = [dev(g) for g in gs_s]
     f_long = torch.ones(plan_l.object_shape, device="cuda")
-    rid_long = server.submit(plan_l, f_long, dev(gs_l[0]), 3, 6, dev(mus_l[0]))
-    shorts = []
-    for k in range(3):
-        f = torch.ones(plan_s.object_shape, device="cuda")
-        shorts.append((server.submit(plan_s, f, dev(gs_s[k]), 1, 3), f, k))
+    fs = [torch.ones(plan_s.object_shape, device="cuda") for _ in range(3)]
+    torch.cuda.synchronize()
+    # a dozen milliseconds of work on the caller's stream: every request's
+    # first step waits for it, so all of them start together
+    a = torch.randn(4096, 4096, device="cuda")
+    for _ in range(12):
+        a = torch.tanh(a @ a)
+    rid_long = server.submit(plan_l, f_long, g_long, 3, 6, mu_long)
+    shorts = [(server.submit(plan_s, fs[k], g_short[k], 1, 3), fs[k], k) for k in range(3)]
     states = []
     for rid, f, k in shorts:
         server.wait(rid)
