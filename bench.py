@@ -750,11 +750,11 @@ def bench_serving(args):
     def run(name, trace_):
         t0 = time.perf_counter()
         if name == "one_at_a_time":
-            served = serving.replay_one_at_a_time(classes, trace_)
+            served = serving.replay_one_at_a_time(classes, trace_, log_every_s=30.0)
             peak = 1
         else:
             server = S.Server(8, 64 << 30)
-            served = serving.replay(server, classes, trace_)
+            served = serving.replay(server, classes, trace_, log_every_s=30.0)
             peak = server.stats()[2]
             server.close()
         wall = time.perf_counter() - t0

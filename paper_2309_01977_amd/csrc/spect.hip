@@ -2571,11 +2571,13 @@ TickTables *tick_build(const TickItem *items, int n, int *status)
 
 size_t tick_bytes(const TickTables *T) { return T->blob.size(); }
 
-int tick_launch(TickTables *T, char *host, char *dev, hipStream_t st)
+int tick_launch(TickTables *T, char *host, char *dev, hipStream_t st, hipStream_t up, hipEvent_t uploaded)
 {
     if (!T->blob.empty()) {
         std::memcpy(host, T->blob.data(), T->blob.size());
-        const hipError_t e = hipMemcpyAsync(dev, host, T->blob.size(), hipMemcpyHostToDevice, st);
+        hipError_t e = hipMemcpyAsync(dev, host, T->blob.size(), hipMemcpyHostToDevice, up);
+        if (e == hipSuccess) e = hipEventRecord(uploaded, up);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, uploaded, 0);
         if (e != hipSuccess) return hip_fail(e, "tick table upload");
     }
     for (const TickTables::Launch &l : T->launches) {

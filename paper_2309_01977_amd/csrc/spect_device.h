@@ -169,6 +169,8 @@ constexpr int kBufferDword3 = 0x00020000;
 // A byte offset past the end of every object volume a plan accepts (below
 // 2^29 voxels, 2 GiB): a raw buffer load there returns zeros.
 constexpr int kVolPastEnd = (int)0x80000000u;
+// Cache-policy bits of a buffer load: non-temporal (the line is not kept).
+constexpr int kNonTemporal = 2;
 
 // Bilinear corners of one sample: weights and byte offsets of the corners'
 // z-runs (plus the lane's row offset dk), for raw buffer loads over the
@@ -613,7 +615,11 @@ struct FwdWalk {
     uint32_t rowb, colb, dk;
     float tau_scale;
     __amdgpu_buffer_rsrc_t rf, rm;
-    const float *tab;  // ATT_READ: the lane's 4 factors of depth 0
+    // ATT_READ: the (angle, slab) brick run of the table; the lane's 4
+    // factors of depth 0 at byte offset toff (past the brick run when the
+    // lane has no rows, so the load returns zeros), tstep bytes per depth
+    __amdgpu_buffer_rsrc_t rt;
+    uint32_t toff, tstep;
     float acc[FR + 2 * KMC];
     float S[FR];       // running attenuation sums (mu sampled)
     float4 vt;         // attenuation factors of the current depth (table)
@@ -621,9 +627,11 @@ struct FwdWalk {
     FCorner cn;        // bilinear corners of the depth whose loads are in flight
     float4 vf[4], vm[4];
 
+    // the factors of depth ip: one unconditional non-temporal buffer load
+    // (no branch on the lane, so the load stays in flight across the blur)
     __device__ __forceinline__ void tload(int ip)
     {
-        vt = live ? stream_f4(tab + (size_t)ip * N * SLAB, 0u) : make_float4(0.f, 0.f, 0.f, 0.f);
+        vt = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rt, toff + (uint32_t)ip * tstep, 0, kNonTemporal));
     }
 
     // issue the corner loads of depth ip (activity, and mu when sampled);
@@ -662,7 +670,10 @@ struct FwdWalk {
                 w.y *= vt.y;
                 w.z *= vt.z;
                 w.w *= vt.w;
-                if (ip > ilo) tload(ip - 1);
+                // unconditional (the last depth reloads its own factors): a
+                // skipped load would leave two values of vt to merge, and the
+                // merge waits for every load in flight
+                tload(max(ip - 1, ilo));
             }
             if (MU) {
                 const float mm[FR] = {m.x, m.y, m.z, m.w};
@@ -758,7 +769,12 @@ __device__ __forceinline__ void fwd_body(const Args &a, int slab, int chunk, int
     w.rm = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(MU ? a.mu : a.f), (short)0, vbytes, kBufferDword3);
     // attenuation table: the lane's rows in the 16-row brick of (angle, slab,
     // depth 0, bin j')
-    w.tab = ATT == ATT_READ && w.live ? a.att + brick_offset(al, a.nslab, slab, N, 0, w.jp) + w.q * FR : nullptr;
+    if constexpr (ATT == ATT_READ) {
+        w.tstep = 4u * (uint32_t)(N * SLAB);
+        w.rt = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(a.att + brick_offset(al, a.nslab, slab, N, 0, 0)),
+                                                 (short)0, (int)(w.tstep * (uint32_t)N), kBufferDword3);
+        w.toff = w.live ? 4u * (uint32_t)(w.jp * SLAB + w.q * FR) : (uint32_t)kVolPastEnd;
+    }
     w.buf = 0;
     if (ATT == ATT_READ && w.active && ihi >= ilo) w.tload(ihi);
     if (w.PREFETCH && w.active && ihi >= ilo) w.cload(ihi);

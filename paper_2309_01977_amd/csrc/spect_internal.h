@@ -39,8 +39,10 @@ struct TickTables;
 TickTables *tick_build(const TickItem *items, int n, int *status);
 size_t tick_bytes(const TickTables *t);
 // Copy the tables through host (pinned, tick_bytes) to dev (tick_bytes) on
-// st and launch the tick's kernels on st.  Both buffers stay in use until
-// the stream has passed the tick.
-int tick_launch(TickTables *t, char *host, char *dev, hipStream_t st);
+// the upload stream up, record the event uploaded there, and launch the
+// tick's kernels on st behind that event.  The copy thus runs beside the
+// kernels already queued on st instead of between them.  Both buffers stay
+// in use until st has passed the tick.
+int tick_launch(TickTables *t, char *host, char *dev, hipStream_t st, hipStream_t up, hipEvent_t uploaded);
 void tick_free(TickTables *t);
 }  // namespace spect_internal

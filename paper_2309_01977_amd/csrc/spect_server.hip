@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
@@ -62,11 +63,15 @@ struct Block {
 struct TickSlot {
     char *host = nullptr, *dev = nullptr;
     size_t cap = 0;
-    hipEvent_t done = nullptr;
+    hipEvent_t done = nullptr;      // recorded on the lane after the tick's kernels
+    hipEvent_t uploaded = nullptr;  // recorded on the upload stream after the table copy
     std::vector<int64_t> finishing;  // requests whose last step is in this tick
 };
 
 constexpr int kRing = 3;
+// Scheduler poll interval while ticks are in flight (submissions end a wait
+// early).
+constexpr int kPollUs = 20;
 
 size_t round256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -100,6 +105,7 @@ struct spect_server {
     int device = 0;
     int max_resident = 1;
     std::vector<Lane> lanes;
+    hipStream_t upload = nullptr;  // tick table copies, beside the lanes' kernels
     char *pool = nullptr;
     size_t pool_bytes = 0, in_use = 0;
     std::vector<Block> free_list;  // sorted by offset, coalesced
@@ -212,20 +218,14 @@ struct spect_server {
         }
     }
 
-    // Retire the requests of lane ln's oldest tick if it has finished
-    // (block: wait for it first).  Called with the lock held; waits without it.
-    void finish_oldest(Lane &ln, std::unique_lock<std::mutex> &lk, bool block)
+    // Retire the requests of lane ln's oldest tick if it has finished;
+    // returns whether it had.  Called with the lock held.
+    bool finish_oldest(Lane &ln)
     {
-        if (ln.inflight.empty()) return;
+        if (ln.inflight.empty()) return false;
         TickSlot &ts = ln.ring[ln.inflight.front()];
-        hipError_t e = hipEventQuery(ts.done);
-        if (e == hipErrorNotReady) {
-            if (!block) return;
-            const hipEvent_t ev = ts.done;
-            lk.unlock();
-            e = hipEventSynchronize(ev);
-            lk.lock();
-        }
+        const hipError_t e = hipEventQuery(ts.done);
+        if (e == hipErrorNotReady) return false;
         ln.inflight.pop_front();
         ln.seq.pop_front();
         for (int64_t id : ts.finishing) {
@@ -237,6 +237,7 @@ struct spect_server {
         ts.finishing.clear();
         if (e != hipSuccess) fail_resident(ln, SPECT_EHIP, hipGetErrorString(e));
         done.notify_all();
+        return true;
     }
 
     // A launch or runtime error: every resident request of the lane fails
@@ -307,7 +308,7 @@ struct spect_server {
                 msg = "a lane stream could not wait for a submission event";
             }
         if (st == SPECT_OK) {
-            st = spect_internal::tick_launch(T, ts.host, ts.dev, ln.stream);
+            st = spect_internal::tick_launch(T, ts.host, ts.dev, ln.stream, upload, ts.uploaded);
             if (st != SPECT_OK) msg = spect_last_error();
         }
         if (st == SPECT_OK && hipEventRecord(ts.done, ln.stream) != hipSuccess) {
@@ -332,18 +333,20 @@ struct spect_server {
         (void)hipSetDevice(device);
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
-            for (Lane &ln : lanes) finish_oldest(ln, lk, false);
+            for (Lane &ln : lanes)
+                while (finish_oldest(ln)) {
+                }
             if (!stop) admit();
-            bool launched = false;
-            for (Lane &ln : lanes)
+            bool launched = false, busy = false;
+            for (Lane &ln : lanes) {
                 if ((int)ln.inflight.size() < kRing && launch_tick(ln, lk)) launched = true;
+                busy = busy || !ln.inflight.empty();
+            }
             if (launched) continue;
-            // wait for the oldest tick in flight on any lane
-            Lane *oldest = nullptr;
-            for (Lane &ln : lanes)
-                if (!ln.inflight.empty() && (!oldest || ln.seq.front() < oldest->seq.front())) oldest = &ln;
-            if (oldest) {
-                finish_oldest(*oldest, lk, true);
+            if (busy) {
+                // ticks in flight: poll every lane, so that a lane whose
+                // ticks are short is refilled while another's long tick runs
+                wake.wait_for(lk, std::chrono::microseconds(kPollUs));
                 continue;
             }
             if (stop && running() == 0) break;
@@ -374,10 +377,13 @@ int spect_server_create(int32_t n_slots, size_t pool_bytes, spect_server **out)
     s->free_list.push_back(Block{0, s->pool_bytes});
     s->lanes.resize(std::min(n_slots, kMaxLanes));
     bool okay = true;
+    okay = okay && hipStreamCreateWithFlags(&s->upload, hipStreamNonBlocking) == hipSuccess;
     for (Lane &ln : s->lanes) {
         okay = okay && hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) == hipSuccess;
-        for (TickSlot &ts : ln.ring)
+        for (TickSlot &ts : ln.ring) {
             okay = okay && hipEventCreateWithFlags(&ts.done, hipEventDisableTiming) == hipSuccess;
+            okay = okay && hipEventCreateWithFlags(&ts.uploaded, hipEventDisableTiming) == hipSuccess;
+        }
     }
     if (!okay) {
         spect_server_destroy(s);
@@ -408,9 +414,14 @@ int spect_server_destroy(spect_server *s)
         }
         for (TickSlot &ts : ln.ring) {
             if (ts.done) (void)hipEventDestroy(ts.done);
+            if (ts.uploaded) (void)hipEventDestroy(ts.uploaded);
             if (ts.host) (void)hipHostFree(ts.host);
             if (ts.dev) (void)hipFree(ts.dev);
         }
+    }
+    if (s->upload) {
+        (void)hipStreamSynchronize(s->upload);
+        (void)hipStreamDestroy(s->upload);
     }
     for (auto &kv : s->reqs) spect_server::drop_ready(kv.second);
     if (s->pool) (void)hipFree(s->pool);

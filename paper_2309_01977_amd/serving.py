@@ -12,6 +12,7 @@ has arrived and the previous one has finished.
 """
 from __future__ import annotations
 
+import sys
 import time
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence, Tuple
@@ -59,15 +60,30 @@ def poisson_trace(rate_per_s: float, duration_s: float, n_classes: int, rng: np.
         out.append((t, int(rng.choice(n_classes, p=p))))
 
 
+class _Progress:
+    """A line on stderr every `every_s` seconds of a long replay (0: never)."""
+
+    def __init__(self, every_s: float, what: str, total: int):
+        self.every, self.what, self.total = every_s, what, total
+        self.next = every_s
+
+    def __call__(self, now: float, done: int):
+        if self.every > 0 and now >= self.next:
+            print(f"{self.what}: {done}/{self.total} requests done after {now:.0f} s", file=sys.stderr, flush=True)
+            self.next += self.every
+
+
 def replay(server: Server, classes: Sequence[RequestClass], trace: Sequence[Tuple[float, int]],
-           keep_images: bool = False, poll_sleep_s: float = 2e-4) -> List[Served]:
+           keep_images: bool = False, poll_sleep_s: float = 2e-4, log_every_s: float = 0.0) -> List[Served]:
     """Run the trace in real time; returns one record per request."""
     served: List[Served] = []
     pending = {}
     counters = [0] * len(classes)
+    progress = _Progress(log_every_s, "server replay", len(trace))
     t0 = time.perf_counter()
     i = 0
     while i < len(trace) or pending:
+        progress(time.perf_counter() - t0, len(served) - len(pending))
         now = time.perf_counter() - t0
         while i < len(trace) and trace[i][0] <= now:
             arrival, c = trace[i]
@@ -101,13 +117,15 @@ def replay(server: Server, classes: Sequence[RequestClass], trace: Sequence[Tupl
 
 
 def replay_one_at_a_time(classes: Sequence[RequestClass], trace: Sequence[Tuple[float, int]],
-                         keep_images: bool = False) -> List[Served]:
+                         keep_images: bool = False, log_every_s: float = 0.0) -> List[Served]:
     """The baseline: each request is one osem_reconstruct call on the current
     stream, started when it has arrived and the previous one has finished."""
     served: List[Served] = []
     counters = [0] * len(classes)
+    progress = _Progress(log_every_s, "one-at-a-time replay", len(trace))
     t0 = time.perf_counter()
     for arrival, c in trace:
+        progress(time.perf_counter() - t0, len(served))
         wait = arrival - (time.perf_counter() - t0)
         if wait > 0:
             time.sleep(wait)
