@@ -190,15 +190,20 @@ int hip_fail(hipError_t e, const char *what)
 
 struct Tuning {
     int nslab, nchunk;
+    int nchunk_b;  // depth chunks of the rotated-frame pass
 };
 
 enum { T_FWD = 1, T_BACK = 2, T_BOTH = 3 };
 
 // Depth chunking of a launch over n_list angles: pick the chunk count that
 // minimises (waves of resident workgroups) x (depths per workgroup + a fixed
-// per-workgroup cost), summed over the kernels that share the split (both
-// passes of an OSEM step share the attenuation offsets).  Splitting adds an
-// attenuation pre-pass when the kernels sample the attenuation map.
+// per-workgroup cost), summed over the kernels that share the split.  The two
+// passes of an OSEM step share one split when they sample the attenuation
+// map (they share its chunk offsets, and splitting adds a pre-pass that
+// forms them); otherwise each pass takes its own (nchunk for the forward,
+// nchunk_b for the rotated-frame pass).  Only the forward's split changes
+// rounding (its chunks' partial rows are summed); every depth of the
+// rotated-frame pass is written by exactly one chunk.
 bool samples_mu(int att) { return att == ATT_SAMPLE || att == ATT_WRITE; }
 int att_of(bool mu) { return mu ? ATT_SAMPLE : ATT_NONE; }
 
@@ -211,20 +216,29 @@ Tuning tune(const spect_plan *p, int n_list, int att, int which)
     Tuning t;
     t.nslab = (p->Nz + SLAB - 1) / SLAB;
     const long base = (long)std::max(1, n_list) * t.nslab;
-    double best = 1e300;
-    t.nchunk = 1;
-    for (int nc = 1; nc <= p->cap; ++nc) {
-        // the largest chunk, in depths of average work, of each pass
-        const double Df = p->chunk_cost[0][nc], Db = p->chunk_cost[back_set(att)][nc];
-        const long wgs = base * nc;
-        double cost = 0;
-        if (which & T_FWD) cost += (double)((wgs + p->fwd_slots[att] - 1) / p->fwd_slots[att]) * (Df + 6);
-        if (which & T_BACK) cost += (double)((wgs + p->back_slots[att] - 1) / p->back_slots[att]) * (Db + 6);
-        if (samples_mu(att) && nc > 1) cost += 2 + ((p->N + nc - 1) / nc) / 4.0;
-        if (cost < best - 1e-9) {
-            best = cost;
-            t.nchunk = nc;
+    auto best_split = [&](int passes) {
+        double best = 1e300;
+        int bn = 1;
+        for (int nc = 1; nc <= p->cap; ++nc) {
+            // the largest chunk, in depths of average work, of each pass
+            const double Df = p->chunk_cost[0][nc], Db = p->chunk_cost[back_set(att)][nc];
+            const long wgs = base * nc;
+            double cost = 0;
+            if (passes & T_FWD) cost += (double)((wgs + p->fwd_slots[att] - 1) / p->fwd_slots[att]) * (Df + 6);
+            if (passes & T_BACK) cost += (double)((wgs + p->back_slots[att] - 1) / p->back_slots[att]) * (Db + 6);
+            if (samples_mu(att) && nc > 1) cost += 2 + ((p->N + nc - 1) / nc) / 4.0;
+            if (cost < best - 1e-9) {
+                best = cost;
+                bn = nc;
+            }
         }
+        return bn;
+    };
+    if (which == T_BOTH && !samples_mu(att)) {
+        t.nchunk = best_split(T_FWD);
+        t.nchunk_b = best_split(T_BACK);
+    } else {
+        t.nchunk = t.nchunk_b = best_split(which);
     }
     return t;
 }
@@ -693,7 +707,7 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
     b.att = table;
     b.z = z;
     b.nslab = t.nslab;
-    b.nchunk = t.nchunk;
+    b.nchunk = t.nchunk_b;
     b.cbset = back_set(att);
     b.vec = vec;
     if (ones) {
@@ -723,7 +737,7 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
         BackFn bk = back_kernel(att, p->kmc, vec);
         allow_smem(reinterpret_cast<const void *>(bk), back_smem(p));
         ProfScope ps(K_BACK_ROT, st);
-        hipLaunchKernelGGL(bk, dim3(t.nslab, t.nchunk, L.n), dim3(block_threads(p->N)), back_smem(p), st, b);
+        hipLaunchKernelGGL(bk, dim3(t.nslab, t.nchunk_b, L.n), dim3(block_threads(p->N)), back_smem(p), st, b);
     }
     GatherArgs gg{};
     gg.g = p->g;
@@ -1819,7 +1833,7 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
                 bb.att = tab;
                 bb.z = scr;
                 bb.nslab = t.nslab;
-                bb.nchunk = t.nchunk;
+                bb.nchunk = t.nchunk_b;
                 bb.cbset = 1;
                 bb.vec = vec;
                 ba.push_back(bb);
@@ -1851,16 +1865,17 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
                         for (int k = 0; k < sblk; ++k)
                             stk.push_back({(long)p->N * p->N, Task{(int)li, k, sl, al}});
                 const int li_ = (int)li;
-                for (int al = 0; al < L.n; ++al)
+                for (int al = 0; al < L.n; ++al) {
+                    // blur work of the chunk's depths x bins
                     for (int c = 0; c < t.nchunk; ++c) {
-                        // blur work of the chunk's depths x bins
                         const long fc = (long)(chunk_work(p, 0, t.nchunk, L.idx[al], c) * p->N);
-                        const long bc = (long)(chunk_work(p, 1, t.nchunk, L.idx[al], c) * p->N);
-                        for (int sl = 0; sl < t.nslab; ++sl) {
-                            ft.push_back({fc, Task{li_, sl, c, al}});
-                            bt.push_back({bc, Task{li_, sl, c, al}});
-                        }
+                        for (int sl = 0; sl < t.nslab; ++sl) ft.push_back({fc, Task{li_, sl, c, al}});
                     }
+                    for (int c = 0; c < t.nchunk_b; ++c) {
+                        const long bc = (long)(chunk_work(p, 1, t.nchunk_b, L.idx[al], c) * p->N);
+                        for (int sl = 0; sl < t.nslab; ++sl) bt.push_back({bc, Task{li_, sl, c, al}});
+                    }
+                }
                 const int blocks = (p->N * p->Nz + 255) / 256;
                 for (int al = 0; al < L.n; ++al)
                     for (int k = 0; k < blocks; ++k) rt.push_back(Task{li_, k, 0, al});
@@ -2134,7 +2149,7 @@ int spect_batch_create(const spect_plan *const *plans, int32_t n_members, int32_
             const int nl = (int)list.size();
             const Tuning t = tune(p, nl, att, T_BOTH);
             ts.push_back(t);
-            t1.push_back(Tuning{t.nslab, 1});
+            t1.push_back(Tuning{t.nslab, 1, 1});
             tabs.push_back(rel);
             if (b->mu) rel += table_bytes(p, nl);
             scr = std::max(scr, batch_part_bytes(p, t, nl, b->kmc_max));
@@ -2491,7 +2506,7 @@ TickTables *tick_build(const TickItem *items, int n, int *status)
         bb.att = lay.table;
         bb.z = scr;
         bb.nslab = t.nslab;
-        bb.nchunk = t.nchunk;
+        bb.nchunk = t.nchunk_b;
         bb.cbset = back_set(att);
         bb.vec = vec;
         G.ba.push_back(bb);
@@ -2505,15 +2520,16 @@ TickTables *tick_build(const TickItem *items, int n, int *status)
         gg.sens = lay.sens;
         const int gi = (int)ga.size();
         ga.push_back(gg);
-        for (int al = 0; al < L.n; ++al)
+        for (int al = 0; al < L.n; ++al) {
             for (int c = 0; c < t.nchunk; ++c) {
                 const long fc = (long)(chunk_work(p, 0, t.nchunk, L.idx[al], c) * p->N);
-                const long bc = (long)(chunk_work(p, bb.cbset, t.nchunk, L.idx[al], c) * p->N);
-                for (int sl = 0; sl < t.nslab; ++sl) {
-                    G.ft.push_back({fc, Task{fi, sl, c, al}});
-                    G.bt.push_back({bc, Task{fi, sl, c, al}});
-                }
+                for (int sl = 0; sl < t.nslab; ++sl) G.ft.push_back({fc, Task{fi, sl, c, al}});
             }
+            for (int c = 0; c < t.nchunk_b; ++c) {
+                const long bc = (long)(chunk_work(p, bb.cbset, t.nchunk_b, L.idx[al], c) * p->N);
+                for (int sl = 0; sl < t.nslab; ++sl) G.bt.push_back({bc, Task{fi, sl, c, al}});
+            }
+        }
         const int blocks = (p->N * p->Nz + 255) / 256;
         for (int al = 0; al < L.n; ++al)
             for (int k = 0; k < blocks; ++k) rt.push_back(Task{ri, k, 0, al});
