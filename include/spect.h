@@ -380,7 +380,10 @@ int osem_list_step_vjp(const spect_plan *plan, const float *f, const float *mu, 
  * initial image on entry (the paper leaves it open; 1 everywhere is the usual
  * choice) and the reconstruction on return; g, s_add, mu as in
  * osem_subset_step.  The workspace (SPECT_OP_RECON, n_idx = n_subsets) also
- * holds the M sensitivity volumes.  n_iters >= 0.
+ * holds the M sensitivity volumes and, when Nz is a multiple of 128 and mu is
+ * not resampled, a copy of f with columns Nz + 32 floats apart that the
+ * forward reads and every update rewrites (a layout only: the result is the
+ * same).  n_iters >= 0.
  *
  * Graph replay: the launches depend only on the plan and the arguments, so
  * the plan captures them into a HIP graph on the second call with the same
@@ -446,7 +449,7 @@ int bsrem_reconstruct(const spect_plan *plan, float *f, const float *mu, const f
  * launch's own stream.  spect_profile_query waits for the recorded launches of
  * the named kernel ("tau_prepass", "fwd_main", "fwd_reduce", "back_rot",
  * "back_gather", "fill_zero", "rdp_grad", "vol_sum", "fwd_batch", "reduce_batch",
- * "back_batch", "gather_batch", "sens_line") and returns their count and summed duration in
+ * "back_batch", "gather_batch", "sens_line", "pad_columns") and returns their count and summed duration in
  * milliseconds; spect_profile_reset waits for and frees all records.
  * Errors: SPECT_EINVAL (NULL argument, unknown name), SPECT_EHIP. */
 int spect_profile_enable(int enable);

@@ -36,7 +36,7 @@ EXPORTS = ("spect_plan_create", "spect_plan_destroy", "spect_workspace_size", "s
            "spect_server_forget", "spect_server_stats", "spect_profile_enable",
            "spect_profile_reset", "spect_profile_query", "spect_last_error")
 KERNELS = ("tau_prepass", "fwd_main", "fwd_reduce", "back_rot", "back_gather", "fill_zero", "rdp_grad",
-           "vol_sum", "fwd_batch", "reduce_batch", "back_batch", "gather_batch", "sens_line")
+           "vol_sum", "fwd_batch", "reduce_batch", "back_batch", "gather_batch", "sens_line", "pad_columns")
 
 
 class SpectError(RuntimeError):

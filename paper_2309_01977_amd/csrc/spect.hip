@@ -80,12 +80,12 @@ namespace {
 
 enum KernelId {
     K_TAU = 0, K_FWD, K_REDUCE, K_BACK_ROT, K_GATHER, K_FILL, K_RDP, K_SUM,
-    K_FWD_B, K_REDUCE_B, K_BACK_B, K_GATHER_B, K_SENS, K_COUNT
+    K_FWD_B, K_REDUCE_B, K_BACK_B, K_GATHER_B, K_SENS, K_PAD, K_COUNT
 };
 const char *const kKernelNames[K_COUNT] = {"tau_prepass", "fwd_main", "fwd_reduce", "back_rot",
                                            "back_gather", "fill_zero", "rdp_grad", "vol_sum",
                                            "fwd_batch", "reduce_batch", "back_batch", "gather_batch",
-                                           "sens_line"};
+                                           "sens_line", "pad_columns"};
 
 struct ProfRec {
     int kernel;
@@ -207,9 +207,11 @@ enum { T_FWD = 1, T_BACK = 2, T_BOTH = 3 };
 bool samples_mu(int att) { return att == ATT_SAMPLE || att == ATT_WRITE; }
 int att_of(bool mu) { return mu ? ATT_SAMPLE : ATT_NONE; }
 
-// Boundary set of the rotated-frame pass: blur-balanced unless it shares
-// attenuation offsets with the forward (mu sampled).
-int back_set(int att) { return samples_mu(att) ? 0 : 1; }
+// Chunk boundary set of the forward and rotated-frame passes: chunks of
+// equal blur work (the far depths blur widest, so their chunks hold fewer
+// depths), or of equal depth counts when the passes sample mu and share the
+// chunks' attenuation offsets.
+int chunk_set(int att) { return samples_mu(att) ? 0 : 1; }
 
 Tuning tune(const spect_plan *p, int n_list, int att, int which)
 {
@@ -221,7 +223,7 @@ Tuning tune(const spect_plan *p, int n_list, int att, int which)
         int bn = 1;
         for (int nc = 1; nc <= p->cap; ++nc) {
             // the largest chunk, in depths of average work, of each pass
-            const double Df = p->chunk_cost[0][nc], Db = p->chunk_cost[back_set(att)][nc];
+            const double Df = p->chunk_cost[chunk_set(att)][nc], Db = Df;
             const long wgs = base * nc;
             double cost = 0;
             if (passes & T_FWD) cost += (double)((wgs + p->fwd_slots[att] - 1) / p->fwd_slots[att]) * (Df + 6);
@@ -371,6 +373,25 @@ constexpr size_t kMaxTableBytes = size_t(32) << 30;
 
 size_t vol_bytes(const spect_plan *p) { return align256(sizeof(float) * (size_t)p->N * p->N * p->Nz); }
 
+// Column stride (floats) of the reconstruction's padded copy of f, or 0 for
+// none.  With columns a multiple of 512 bytes apart, the forward's
+// workgroups of one slab read a fixed 64-byte slice of every column, and the
+// slabs whose slice falls in the last quarter of each 512 bytes were measured
+// about 10 % slower than the rest (128^3: 84-90 us per 15-angle launch
+// against 73-76 us with 640-byte columns).  Only for the passes that do not
+// sample mu (mu would need the same stride).
+int pad_stride(const spect_plan *p, int att)
+{
+    if (att == ATT_SAMPLE || att == ATT_WRITE) return 0;
+    return (p->Nz % 128 == 0) ? p->Nz + 32 : 0;
+}
+
+size_t pad_bytes(const spect_plan *p, int att)
+{
+    const int zs = pad_stride(p, att);
+    return zs ? align256(sizeof(float) * (size_t)p->N * p->N * zs) : 0;
+}
+
 int subset_size(const spect_plan *p, int M, int m) { return (p->A - m + M - 1) / M; }
 
 size_t table_bytes(const spect_plan *p, int nl)
@@ -399,6 +420,8 @@ size_t recon_ws(const spect_plan *p, int M, bool mu)
 {
     size_t b = (size_t)M * vol_bytes(p);
     for (int m = 0; m < M; ++m) b += recon_tau_bytes(p, M, m, mu);
+    const int att = use_table(p, M, mu) ? ATT_READ : att_of(mu);
+    b += pad_bytes(p, att);
     if (!use_table(p, M, mu)) return b + osem_ws(p, M, mu);
     size_t scratch = 0;
     for (int nl : {p->A / M, (p->A + M - 1) / M}) {
@@ -611,7 +634,7 @@ void launch_tau(const spect_plan *p, const AngleList &L, const Tuning &t, const 
 int run_forward(const spect_plan *p, const float *f, const float *mu, int att, const float *table,
                 const AngleList &L, char *ws, size_t ws_avail, const float *tau_given, int mode, float *proj,
                 const float *g, const float *s_add, float *q, bool vec, int which, hipStream_t st,
-                float *e_rows = nullptr)
+                float *e_rows = nullptr, int zs = 0)
 {
     const Tuning t = tune(p, L.n, att, which);
     if (fwd_need(p, L.n, att, which) > ws_avail)
@@ -639,8 +662,9 @@ int run_forward(const spect_plan *p, const float *f, const float *mu, int att, c
     a.part = part;
     a.nslab = t.nslab;
     a.nchunk = t.nchunk;
-    a.cbset = 0;
+    a.cbset = chunk_set(att);
     a.vec = vec;
+    a.zs = zs;
     KernelFn fk = fwd_kernel(att, p->kmc, vec);
     allow_smem(reinterpret_cast<const void *>(fk), fwd_smem(p));
     {
@@ -670,13 +694,23 @@ int run_forward(const spect_plan *p, const float *f, const float *mu, int att, c
     return SPECT_OK;
 }
 
+// The gather's 16-byte output path: Nz a multiple of 4 and every array it
+// touches 16-byte aligned.
+bool gather_v4(const spect_plan *p, std::initializer_list<const void *> ptrs)
+{
+    if (p->Nz % 4) return false;
+    for (const void *q : ptrs)
+        if (q && reinterpret_cast<uintptr_t>(q) % 16) return false;
+    return true;
+}
+
 // Back projection of one list: rotated-frame pass, then the gather.
 // att: ATT_NONE / ATT_SAMPLE / ATT_WRITE (sample mu and fill table) /
 // ATT_READ (from table).  ws holds [tau][z]; tau_given as in run_forward.
 int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const float *mu, int att,
              float *table, const AngleList &L, char *ws, size_t ws_avail, const float *tau_given, int mode,
              float *out, const float *sens, bool vec, int which, hipStream_t st, const BsremTerms *bt = nullptr,
-             const StepTerms *stt = nullptr)
+             const StepTerms *stt = nullptr, float *fpad = nullptr, int zs = 0)
 {
     const Tuning t = tune(p, L.n, att, which);
     if (back_need(p, L.n, att, which) > ws_avail)
@@ -708,7 +742,7 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
     b.z = z;
     b.nslab = t.nslab;
     b.nchunk = t.nchunk_b;
-    b.cbset = back_set(att);
+    b.cbset = chunk_set(att);
     b.vec = vec;
     if (ones) {
         // constant projection: the blur reduces to in-range tap sums, and the
@@ -747,6 +781,9 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
     gg.mode = mode;
     gg.out = out;
     gg.sens = sens;
+    gg.fpad = fpad;
+    gg.zs = zs;
+    gg.v4 = gather_v4(p, {out, sens, fpad, bt ? bt->sens_all : nullptr, bt ? bt->prior : nullptr});
     gg.bt = bt ? *bt : BsremTerms{nullptr, nullptr, 0.f, 0.f};
     gg.st = stt ? *stt : StepTerms{nullptr, nullptr, nullptr};
     const int tiles = (p->N + GT - 1) / GT;
@@ -790,6 +827,20 @@ int launch_sum(const spect_plan *p, const float *first, size_t stride, int n, fl
     }
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? SPECT_OK : hip_fail(e, "volume sum launch");
+}
+
+// dst = src with columns zs floats apart (the reconstruction's padded f).
+int launch_pad(const spect_plan *p, const float *src, float *dst, int zs, hipStream_t st)
+{
+    const size_t ncol = (size_t)p->N * p->N, n4 = ncol * (p->Nz / 4);
+    {
+        ProfScope ps(K_PAD, st);
+        hipLaunchKernelGGL(pad_columns, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st,
+                           reinterpret_cast<const float4 *>(src), reinterpret_cast<float4 *>(dst), ncol, p->Nz / 4,
+                           zs / 4);
+    }
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SPECT_OK : hip_fail(e, "padded copy launch");
 }
 
 int clear(float *p, size_t n, hipStream_t st)
@@ -1463,8 +1514,12 @@ int reconstruct(const spect_plan *plan, float *f, const float *mu, const float *
         }
         float *q = reinterpret_cast<float *>(w + off);
         const size_t qb = osem_q_bytes(plan, M);
-        char *rest = w + off + qb;
-        const size_t avail = ws_bytes - off - qb;
+        // the forward's padded copy of f, kept current by the updates
+        const int zs = pad_stride(plan, att);
+        const size_t pb = pad_bytes(plan, att);
+        float *fpad = zs ? reinterpret_cast<float *>(w + off + qb) : nullptr;
+        char *rest = w + off + qb + pb;
+        const size_t avail = ws_bytes - off - qb - pb;
         // subset sensitivities H_m^T 1; with a table this pass also fills it
         for (int m = 0; m < M; ++m) {
             if (table)
@@ -1476,6 +1531,7 @@ int reconstruct(const spect_plan *plan, float *f, const float *mu, const float *
             if (st) return st;
         }
         if (bs && (st = launch_sum(plan, sens[0], vb / sizeof(float), M, sens_all, s))) return st;
+        if (zs && n_iters > 0 && (st = launch_pad(plan, f, fpad, zs, s))) return st;
         for (int it = 0; it < n_iters; ++it)
             for (int m = 0; m < M; ++m) {
                 float *tab = table ? per[m] : nullptr;
@@ -1488,11 +1544,11 @@ int reconstruct(const spect_plan *plan, float *f, const float *mu, const float *
                     bt.c_beta = c * bs->beta;
                     if ((st = launch_rdp(plan, f, prior, bs->gamma, s))) return st;
                 }
-                if ((st = run_forward(plan, f, mu, att, tab, lists[m], rest, avail, tau, 1, nullptr, g, s_add, q, vec,
-                                      T_BOTH, s)))
+                if ((st = run_forward(plan, zs ? fpad : f, mu, att, tab, lists[m], rest, avail, tau, 1, nullptr, g, s_add,
+                                      q, vec, T_BOTH, s, nullptr, zs)))
                     return st;
                 if ((st = run_back(plan, q, 1, 0, mu, att, tab, lists[m], rest, avail, tau, bs ? 3 : 2, f, sens[m], vec,
-                                   T_BOTH, s, bs ? &bt : nullptr)))
+                                   T_BOTH, s, bs ? &bt : nullptr, nullptr, fpad, zs)))
                     return st;
             }
         return ok();
@@ -1809,7 +1865,7 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
                 a.part = scr;
                 a.nslab = t.nslab;
                 a.nchunk = t.nchunk;
-                a.cbset = 0;
+                a.cbset = 1;
                 a.vec = vec;
                 fa.push_back(a);
                 ReduceArgs rr{};
@@ -1845,6 +1901,7 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
                 gg.mode = 2;
                 gg.out = P.f[r];
                 gg.sens = sens;
+                gg.v4 = gather_v4(p, {P.f[r], sens});
                 ga.push_back(gg);
                 BackRotArgs sb = bb;  // sensitivity: ones, mu sampled, table written, one depth chunk
                 sb.y = nullptr;
@@ -1858,6 +1915,7 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
                 sgg.mode = 0;
                 sgg.out = sens;
                 sgg.sens = nullptr;
+                sgg.v4 = gather_v4(p, {sens});
                 sg.push_back(sgg);
                 const int sblk = (p->N * (SLAB / 2) + SL_THREADS - 1) / SL_THREADS;
                 for (int al = 0; al < L.n; ++al)
@@ -1868,7 +1926,7 @@ int build_tables(spect_batch *b, const Ptrs &P, bool vec, int sched)
                 for (int al = 0; al < L.n; ++al) {
                     // blur work of the chunk's depths x bins
                     for (int c = 0; c < t.nchunk; ++c) {
-                        const long fc = (long)(chunk_work(p, 0, t.nchunk, L.idx[al], c) * p->N);
+                        const long fc = (long)(chunk_work(p, 1, t.nchunk, L.idx[al], c) * p->N);
                         for (int sl = 0; sl < t.nslab; ++sl) ft.push_back({fc, Task{li_, sl, c, al}});
                     }
                     for (int c = 0; c < t.nchunk_b; ++c) {
@@ -2458,6 +2516,7 @@ TickTables *tick_build(const TickItem *items, int n, int *status)
             gg.nslab = t.nslab;
             gg.mode = 0;
             gg.out = lay.sens;
+            gg.v4 = gather_v4(p, {lay.sens});
             const int gi = (int)ga.size();
             ga.push_back(gg);
             for (int sp = 0; sp < (t.nslab + GS - 1) / GS; ++sp)
@@ -2480,7 +2539,7 @@ TickTables *tick_build(const TickItem *items, int n, int *status)
         a.part = scr;
         a.nslab = t.nslab;
         a.nchunk = t.nchunk;
-        a.cbset = 0;
+        a.cbset = chunk_set(att);
         a.vec = vec;
         const int fi = (int)G.fa.size();
         G.fa.push_back(a);
@@ -2507,7 +2566,7 @@ TickTables *tick_build(const TickItem *items, int n, int *status)
         bb.z = scr;
         bb.nslab = t.nslab;
         bb.nchunk = t.nchunk_b;
-        bb.cbset = back_set(att);
+        bb.cbset = chunk_set(att);
         bb.vec = vec;
         G.ba.push_back(bb);
         GatherArgs gg{};
@@ -2518,11 +2577,12 @@ TickTables *tick_build(const TickItem *items, int n, int *status)
         gg.mode = 2;
         gg.out = it.f;
         gg.sens = lay.sens;
+        gg.v4 = gather_v4(p, {it.f, lay.sens});
         const int gi = (int)ga.size();
         ga.push_back(gg);
         for (int al = 0; al < L.n; ++al) {
             for (int c = 0; c < t.nchunk; ++c) {
-                const long fc = (long)(chunk_work(p, 0, t.nchunk, L.idx[al], c) * p->N);
+                const long fc = (long)(chunk_work(p, a.cbset, t.nchunk, L.idx[al], c) * p->N);
                 for (int sl = 0; sl < t.nslab; ++sl) G.ft.push_back({fc, Task{fi, sl, c, al}});
             }
             for (int c = 0; c < t.nchunk_b; ++c) {

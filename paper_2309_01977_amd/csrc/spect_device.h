@@ -497,6 +497,7 @@ struct FwdArgs {
     float *part;        // [L][nslab][nchunk][N][SLAB + 2 KMC]
     int nslab, nchunk, cbset;
     int vec;
+    int zs;             // column stride of f in floats (0: Nz); mu, when sampled, is never padded
 };
 
 // LDS row buffers of the forward: [buf][row j' + KMC][q] float4, two buffers
@@ -758,7 +759,7 @@ __device__ __forceinline__ void fwd_body(const Args &a, int slab, int chunk, int
     chunk_range(a.g, a.cbset, a.nchunk, ang, chunk, ihi, ilo);
     ConstMem<int> *kd = as_const(a.g.kdep + (size_t)ang * N);
     w.ilo = ilo;
-    w.rowb = 4u * (uint32_t)Nz;
+    w.rowb = 4u * (uint32_t)(a.zs > 0 && !MU ? a.zs : Nz);
     w.colb = w.rowb * (uint32_t)N;
     // row offsets in a z-run (clamped to valid rows; rows past Nz are zeroed)
     w.dk = 4u * (uint32_t)max(min(w.kb, Nz - 4), 0);
@@ -1276,6 +1277,9 @@ struct GatherArgs {
     const float *sens;   // modes 2-4: subset sensitivity H_m^T 1
     BsremTerms bt;       // mode 3
     StepTerms st;        // modes 2, 4
+    float *fpad;         // modes 2, 3: also store the updated image here, columns zs floats apart
+    int zs;
+    int v4;              // Nz % 4 == 0 and every array 16-byte aligned: modes 0, 2, 3 use 16-byte accesses
 };
 
 // Transpose of the bilinear rotation, as a gather.  Workgroup = 8 x 8 object
@@ -1447,6 +1451,42 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
         }
     }
     const size_t base = ((size_t)x * N + y) * Nz;
+    if (a.v4 && (a.mode == 0 || (a.mode == 2 && !a.st.fin) || a.mode == 3)) {
+        // the lane's 4 rows of each slab as one 16-byte access per array
+        // (the same arithmetic per element as the general path below)
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) {
+            const int k = (slab0 + sl) * SLAB + 4 * q;
+            if (k >= Nz) break;
+            float4 *p = reinterpret_cast<float4 *>(a.out + base + k);
+            float4 v;
+            if (a.mode == 0) {
+                v = make_float4(acc[sl][0], acc[sl][1], acc[sl][2], acc[sl][3]);
+            } else if (a.mode == 2) {
+                const float4 sv = *reinterpret_cast<const float4 *>(a.sens + base + k), fv = *p;
+                v.x = sv.x > 0.f ? fv.x * acc[sl][0] / sv.x : fv.x;
+                v.y = sv.y > 0.f ? fv.y * acc[sl][1] / sv.y : fv.y;
+                v.z = sv.z > 0.f ? fv.z * acc[sl][2] / sv.z : fv.z;
+                v.w = sv.w > 0.f ? fv.w * acc[sl][3] / sv.w : fv.w;
+            } else {
+                const float4 sa = *reinterpret_cast<const float4 *>(a.bt.sens_all + base + k), fv = *p;
+                const float4 sm = *reinterpret_cast<const float4 *>(a.sens + base + k);
+                const float4 pr = *reinterpret_cast<const float4 *>(a.bt.prior + base + k);
+                const float sav[4] = {sa.x, sa.y, sa.z, sa.w}, fvv[4] = {fv.x, fv.y, fv.z, fv.w};
+                const float smv[4] = {sm.x, sm.y, sm.z, sm.w}, prv[4] = {pr.x, pr.y, pr.z, pr.w};
+                float o[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float step = acc[sl][r] - smv[r] - a.bt.c_beta * prv[r];
+                    o[r] = sav[r] > 0.f ? fmaxf(0.f, fvv[r] + fvv[r] * a.bt.a_over_c / sav[r] * step) : fvv[r];
+                }
+                v = make_float4(o[0], o[1], o[2], o[3]);
+            }
+            *p = v;
+            if (a.mode != 0 && a.fpad) *reinterpret_cast<float4 *>(a.fpad + ((size_t)x * N + y) * a.zs + k) = v;
+        }
+        return;
+    }
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl) {
 #pragma unroll
@@ -1478,6 +1518,7 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
                     *p = fmaxf(0.f, fv + fv * a.bt.a_over_c / sa * step);
                 }
             }
+            if ((a.mode == 2 || a.mode == 3) && a.fpad) a.fpad[((size_t)x * N + y) * a.zs + k] = *p;
         }
     }
 }
@@ -1505,6 +1546,16 @@ __global__ __launch_bounds__(256) void fill_zero(float *p, size_t n)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.f;
+}
+
+// dst = src with columns zs floats apart instead of Nz (Nz a multiple of 4;
+// the rows past Nz are not written).
+__global__ __launch_bounds__(256) void pad_columns(const float4 *src, float4 *dst, size_t ncol, int nz4, int zs4)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncol * nz4) return;
+    const size_t c = i / nz4, k = i % nz4;
+    dst[c * zs4 + k] = src[i];
 }
 
 // out = sum of n volumes spaced `stride` floats apart from `first`.
