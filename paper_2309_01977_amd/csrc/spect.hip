@@ -531,14 +531,8 @@ int block_threads(int N) { return std::min(512, ((2 * N + 63) / 64) * 64); }
 
 size_t wb_bytes(int N, int kmc) { return sizeof(float4) * 2 * 2 * 2 * (size_t)(N + 2 * kmc); }
 
-// Forward: the two row buffers ([2][N + 2 kmc][FQ] float4), later reused to
-// merge the slab's partial rows ([N][SLAB + 2 kmc] floats).
-size_t fwd_smem(int N, int kmc)
-{
-    const size_t rows = sizeof(float4) * 2 * FQ * (size_t)(N + 2 * kmc);
-    const size_t merge = sizeof(float) * (size_t)N * (SLAB + 2 * kmc);
-    return std::max(rows, merge);
-}
+// Forward: the two row buffers ([2][N + 2 kmc][FQ] float4).
+size_t fwd_smem(int N, int kmc) { return sizeof(float4) * 2 * FQ * (size_t)(N + 2 * kmc); }
 
 // Row buffers plus the projection columns: N columns of SLAB + 2 kmc + 1
 // floats, skewed by 8 floats per group of 8 bins.

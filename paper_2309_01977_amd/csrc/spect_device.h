@@ -504,6 +504,19 @@ struct FwdArgs {
 // of nrows = N + 2 KMC rows (KMC zero rows on each side).
 __device__ __forceinline__ int fwb_index(int buf, int row, int q, int nrows) { return (buf * nrows + row) * FQ + q; }
 
+// Value of lane `src` of this lane's quad (all four lanes active).
+template <int SRC>
+__device__ __forceinline__ int quad_bcast(int v)
+{
+    return __builtin_amdgcn_mov_dpp(v, SRC * 0x55, 0xF, 0xF, false);
+}
+
+template <int SRC>
+__device__ __forceinline__ float quad_bcast(float v)
+{
+    return __int_as_float(quad_bcast<SRC>(__float_as_int(v)));
+}
+
 // Workgroup barrier that orders LDS accesses only: global loads in flight
 // stay in flight across it (__syncthreads() would also wait for them).
 __device__ __forceinline__ void lds_barrier()
@@ -782,24 +795,29 @@ __device__ __forceinline__ void fwd_body(const Args &a, int slab, int chunk, int
     __syncthreads();
     for (int ip = ihi; ip >= ilo; --ip) w.depth(ip, uniform(kd[ip]));
 
-    // merge the four lanes of each bin in LDS ([N][R], lane q's row t is the
-    // slab's partial row 4q + t; lanes added in order q = 0..3), then store
-    // the slab's partial rows with coalesced 16-byte stores
-    float *mb = reinterpret_cast<float *>(smem);
-    __syncthreads();
-    for (int i = threadIdx.x; i < N * R; i += blockDim.x) mb[i] = 0.f;
-    __syncthreads();
+    // merge the four lanes of each bin (lane q's row t is the slab's partial
+    // row 4q + t) in registers: lane 0 of the quad reads the other lanes'
+    // rows through DPP and adds them in the order q = 0..3, then stores the
+    // bin's R partial rows as 16-byte stores.  Every lane takes part in the
+    // DPP moves (the four lanes of a quad are always active here).
+    static_assert(R % 4 == 0, "partial rows in whole 16-byte groups");
+    constexpr int T = FR + 2 * KMC;
+    float *dst = a.part + (((size_t)al * a.nslab + slab) * a.nchunk + chunk) * N * R + (size_t)w.jp * R;
+    const bool store = w.active && w.q == 0;
 #pragma unroll
-    for (int qq = 0; qq < FQ; ++qq) {
-        if (w.active && w.q == qq) {
+    for (int t0 = 0; t0 < R; t0 += 4) {
+        float o[4];
 #pragma unroll
-            for (int t = 0; t < FR + 2 * KMC; ++t) mb[w.jp * R + FR * qq + t] += w.acc[t];
+        for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u;
+            float v = t < T ? w.acc[t] : 0.f;
+            if (t >= 4 && t - 4 < T) v += quad_bcast<1>(w.acc[t - 4]);
+            if (t >= 8 && t - 8 < T) v += quad_bcast<2>(w.acc[t - 8]);
+            if (t >= 12 && t - 12 < T) v += quad_bcast<3>(w.acc[t - 12]);
+            o[u] = v;
         }
-        __syncthreads();
+        if (store) *reinterpret_cast<float4 *>(dst + t0) = make_float4(o[0], o[1], o[2], o[3]);
     }
-    float4 *dst = reinterpret_cast<float4 *>(a.part + (((size_t)al * a.nslab + slab) * a.nchunk + chunk) * N * R);
-    const float4 *src = reinterpret_cast<const float4 *>(mb);
-    for (int i = threadIdx.x; i < N * R / 4; i += blockDim.x) dst[i] = src[i];
 }
 
 // Largest forward workgroup: FQ lanes per bin, N <= 256.
@@ -1304,19 +1322,6 @@ constexpr int GS = 2;  // slabs per gather workgroup
 constexpr int GC = 5;  // candidate load slots per angle
 
 #ifdef SPECT_HOST_TU
-// Value of lane `src` of this lane's quad (all four lanes active).
-template <int SRC>
-__device__ __forceinline__ int quad_bcast(int v)
-{
-    return __builtin_amdgcn_mov_dpp(v, SRC * 0x55, 0xF, 0xF, false);
-}
-
-template <int SRC>
-__device__ __forceinline__ float quad_bcast(float v)
-{
-    return __int_as_float(quad_bcast<SRC>(__float_as_int(v)));
-}
-
 // NS slabs per workgroup: GS, or 1 for launches too small to fill the
 // device (the sums are formed in the same order either way).
 template <int NS, class Args>
