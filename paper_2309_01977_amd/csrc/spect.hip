@@ -209,9 +209,9 @@ int att_of(bool mu) { return mu ? ATT_SAMPLE : ATT_NONE; }
 
 // Chunk boundary set of the forward and rotated-frame passes: chunks of
 // equal blur work (the far depths blur widest, so their chunks hold fewer
-// depths), or of equal depth counts when the passes sample mu and share the
-// chunks' attenuation offsets.
-int chunk_set(int att) { return samples_mu(att) ? 0 : 1; }
+// depths), or of equal depth counts when both passes of a step sample mu and
+// share the chunks' attenuation offsets (which = T_BOTH).
+int chunk_set(int att, int which) { return samples_mu(att) && which == T_BOTH ? 0 : 1; }
 
 Tuning tune(const spect_plan *p, int n_list, int att, int which)
 {
@@ -223,7 +223,7 @@ Tuning tune(const spect_plan *p, int n_list, int att, int which)
         int bn = 1;
         for (int nc = 1; nc <= p->cap; ++nc) {
             // the largest chunk, in depths of average work, of each pass
-            const double Df = p->chunk_cost[chunk_set(att)][nc], Db = Df;
+            const double Df = p->chunk_cost[chunk_set(att, which)][nc], Db = Df;
             const long wgs = base * nc;
             double cost = 0;
             if (passes & T_FWD) cost += (double)((wgs + p->fwd_slots[att] - 1) / p->fwd_slots[att]) * (Df + 6);
@@ -605,7 +605,7 @@ AngleList to_list(const int *a, int n)
 
 // Attenuation offsets for chunked launches.
 void launch_tau(const spect_plan *p, const AngleList &L, const Tuning &t, const float *mu, float *tau,
-                bool vec, hipStream_t st)
+                bool vec, hipStream_t st, int set)
 {
     TauArgs a;
     a.g = p->g;
@@ -613,7 +613,7 @@ void launch_tau(const spect_plan *p, const AngleList &L, const Tuning &t, const 
     a.mu = mu;
     a.tau = tau;
     a.nchunk = t.nchunk;
-    a.cbset = 0;
+    a.cbset = set;
     a.vec = vec;
     const int ngrp = (p->Nz + ROWS - 1) / ROWS;
     dim3 grid((p->N * ngrp + 255) / 256, t.nchunk - 1, L.n);
@@ -641,7 +641,7 @@ int run_forward(const spect_plan *p, const float *f, const float *mu, int att, c
         if (tau_given) {
             tau = tau_given;
         } else {
-            launch_tau(p, L, t, mu, reinterpret_cast<float *>(ws), vec, st);
+            launch_tau(p, L, t, mu, reinterpret_cast<float *>(ws), vec, st, chunk_set(att, which));
             tau = reinterpret_cast<const float *>(ws);
         }
     }
@@ -656,7 +656,7 @@ int run_forward(const spect_plan *p, const float *f, const float *mu, int att, c
     a.part = part;
     a.nslab = t.nslab;
     a.nchunk = t.nchunk;
-    a.cbset = chunk_set(att);
+    a.cbset = chunk_set(att, which);
     a.vec = vec;
     a.zs = zs;
     KernelFn fk = fwd_kernel(att, p->kmc, vec);
@@ -719,7 +719,7 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
         if (tau_given) {
             tau = tau_given;
         } else {
-            launch_tau(p, L, t, mu, reinterpret_cast<float *>(ws), vec, st);
+            launch_tau(p, L, t, mu, reinterpret_cast<float *>(ws), vec, st, chunk_set(att, which));
             tau = reinterpret_cast<const float *>(ws);
         }
     }
@@ -736,7 +736,7 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
     b.z = z;
     b.nslab = t.nslab;
     b.nchunk = t.nchunk_b;
-    b.cbset = chunk_set(att);
+    b.cbset = chunk_set(att, which);
     b.vec = vec;
     if (ones) {
         // constant projection: the blur reduces to in-range tap sums, and the
@@ -1503,7 +1503,9 @@ int reconstruct(const spect_plan *plan, float *f, const float *mu, const float *
             lists[m] = to_list(list.data(), (int)list.size());
             const size_t tb = recon_tau_bytes(plan, M, m, mu != nullptr);
             if (tb) per[m] = reinterpret_cast<float *>(w + off);
-            if (tb && !table) launch_tau(plan, lists[m], tune(plan, lists[m].n, ATT_SAMPLE, T_BOTH), mu, per[m], vec, s);
+            if (tb && !table)
+                launch_tau(plan, lists[m], tune(plan, lists[m].n, ATT_SAMPLE, T_BOTH), mu, per[m], vec, s,
+                           chunk_set(ATT_SAMPLE, T_BOTH));
             off += tb;
         }
         float *q = reinterpret_cast<float *>(w + off);
@@ -2533,7 +2535,7 @@ TickTables *tick_build(const TickItem *items, int n, int *status)
         a.part = scr;
         a.nslab = t.nslab;
         a.nchunk = t.nchunk;
-        a.cbset = chunk_set(att);
+        a.cbset = chunk_set(att, T_BOTH);
         a.vec = vec;
         const int fi = (int)G.fa.size();
         G.fa.push_back(a);
@@ -2560,7 +2562,7 @@ TickTables *tick_build(const TickItem *items, int n, int *status)
         bb.z = scr;
         bb.nslab = t.nslab;
         bb.nchunk = t.nchunk_b;
-        bb.cbset = chunk_set(att);
+        bb.cbset = chunk_set(att, T_BOTH);
         bb.vec = vec;
         G.ba.push_back(bb);
         GatherArgs gg{};
