@@ -196,8 +196,11 @@ struct Tuning {
 enum { T_FWD = 1, T_BACK = 2, T_BOTH = 3 };
 
 // Depth chunking of a launch over n_list angles: pick the chunk count that
-// minimises (waves of resident workgroups) x (depths per workgroup + a fixed
-// per-workgroup cost), summed over the kernels that share the split.  The two
+// minimises (rounds of resident workgroups) x (depths per workgroup + a fixed
+// per-workgroup cost), summed over the kernels that share the split; a last,
+// partly filled round counts in proportion to its fill, up to a whole round
+// at half fill (its workgroups share their CUs with fewer others and run
+// faster).  The two
 // passes of an OSEM step share one split when they sample the attenuation
 // map (they share its chunk offsets, and splitting adds a pre-pass that
 // forms them); otherwise each pass takes its own (nchunk for the forward,
@@ -213,6 +216,12 @@ int att_of(bool mu) { return mu ? ATT_SAMPLE : ATT_NONE; }
 // share the chunks' attenuation offsets (which = T_BOTH).
 int chunk_set(int att, int which) { return samples_mu(att) && which == T_BOTH ? 0 : 1; }
 
+double rounds(long wgs, int slots)
+{
+    const double x = (double)wgs / std::max(1, slots), whole = std::floor(x);
+    return std::max(1.0, whole + std::min(1.0, 2.0 * (x - whole)));
+}
+
 Tuning tune(const spect_plan *p, int n_list, int att, int which)
 {
     Tuning t;
@@ -226,9 +235,12 @@ Tuning tune(const spect_plan *p, int n_list, int att, int which)
             const double Df = p->chunk_cost[chunk_set(att, which)][nc], Db = Df;
             const long wgs = base * nc;
             double cost = 0;
-            if (passes & T_FWD) cost += (double)((wgs + p->fwd_slots[att] - 1) / p->fwd_slots[att]) * (Df + 6);
-            if (passes & T_BACK) cost += (double)((wgs + p->back_slots[att] - 1) / p->back_slots[att]) * (Db + 6);
-            if (samples_mu(att) && nc > 1) cost += 2 + ((p->N + nc - 1) / nc) / 4.0;
+            if (passes & T_FWD) cost += rounds(wgs, p->fwd_slots[att]) * (Df + 6);
+            if (passes & T_BACK) cost += rounds(wgs, p->back_slots[att]) * (Db + 6);
+            // the offsets pre-pass samples mu over (nc - 1) / nc of the
+            // depths, at about 0.3 of a projection's cost per depth
+            if (samples_mu(att) && nc > 1)
+                cost += 2 + 0.3 * (nc - 1) / nc * ((double)base / p->back_slots[att]) * p->N;
             if (cost < best - 1e-9) {
                 best = cost;
                 bn = nc;
@@ -302,11 +314,12 @@ size_t z_bytes(const spect_plan *p, const Tuning &t, int n_list)
 }
 
 // Angles per back-projection group: bounded by the launch list and by a
-// 512 MiB rotated-frame buffer.
+// 4 GiB rotated-frame buffer (a whole 128^3 x 120 adjoint is one group: one
+// rotated-frame launch, which then needs no depth chunks, and one gather).
 int back_group(const spect_plan *p, int n_idx)
 {
     const size_t per = sizeof(float) * (size_t)((p->Nz + SLAB - 1) / SLAB) * SLAB * p->N * p->N;
-    size_t g = (size_t(512) << 20) / std::max<size_t>(per, 1);
+    size_t g = (size_t(4) << 30) / std::max<size_t>(per, 1);
     g = std::max<size_t>(1, std::min<size_t>(g, MAXL));
     return (int)std::min<size_t>(g, std::max(1, n_idx));
 }

@@ -461,8 +461,11 @@ def test_kernel_timer_counts_launches():
 
 
 def test_whole_reconstruction_matches_stepwise_driver():
-    """osem_reconstruct (attenuation offsets computed once per subset) gives
-    the same image as spect_sensitivity + osem_subset_step driven from Python;
+    """osem_reconstruct (attenuation factors read from the subset's table)
+    gives the image of spect_sensitivity + osem_subset_step driven from Python
+    (mu resampled, its depth sums split at other chunk boundaries) to FP32
+    rounding: each ray sums up to 128 depths in a different order, about
+    sqrt(128) x 6e-8 = 7e-7 relative per projection, so the bar is 2e-6;
     uneven subsets (60 angles in 8 subsets) included."""
     w = P.C1
     og, f_true, mu, g = workload_data(P.C2)
@@ -472,7 +475,7 @@ def test_whole_reconstruction_matches_stepwise_driver():
     b = host(S.osem_steps(plan, gd, 1, 8, mud))
     e = rel_l2(a, b)
     say(f"  128^3 one iteration: reconstruct vs stepwise rel L2 {e:.2e}")
-    assert e <= 1e-6
+    assert e <= 2e-6
     r = np.random.default_rng(16)
     og2, plan2 = both(32, 24, 60)
     f2 = P.random_object(og2.object_shape, r) + 0.5
