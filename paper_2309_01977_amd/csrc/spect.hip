@@ -2387,6 +2387,13 @@ namespace spect_internal {
 
 struct TickTables {
     std::vector<char> blob;
+    struct Pad {
+        const spect_plan *p;
+        const float *src;
+        float *dst;
+        int zs;
+    };
+    std::vector<Pad> pads;  // padded copies of f made before the tick's kernels
     struct Launch {
         int kind;  // 0 sensitivity, 1 forward, 2 reduce, 3 rotated-frame, 4 gather
         const void *fn;
@@ -2402,6 +2409,8 @@ namespace {
 
 struct ItemLayout {
     float *sens, *table, *q;
+    float *fpad;  // the forward's padded copy of f (zs floats per column), or nullptr
+    int zs;
     char *rest;
 };
 
@@ -2420,7 +2429,12 @@ ItemLayout item_layout(const TickItem &it)
         off += recon_tau_bytes(p, M, m, mu);
     }
     l.q = reinterpret_cast<float *>(it.region + off);
-    l.rest = it.region + off + osem_q_bytes(p, M);
+    off += osem_q_bytes(p, M);
+    // as in reconstruct: [q][padded f][scratch]
+    const int att = mu ? ATT_READ : ATT_NONE;
+    l.zs = pad_stride(p, att);
+    l.fpad = l.zs ? reinterpret_cast<float *>(it.region + off) : nullptr;
+    l.rest = it.region + off + pad_bytes(p, att);
     return l;
 }
 
@@ -2540,10 +2554,12 @@ TickTables *tick_build(const TickItem *items, int n, int *status)
         Group &G = gr.second;
         G.nmax = std::max(G.nmax, p->N);
         float *scr = reinterpret_cast<float *>(lay.rest);
+        if (it.first_sub && lay.zs) T->pads.push_back(TickTables::Pad{p, it.f, lay.fpad, lay.zs});
         FwdArgs a{};
         a.g = p->g;
         a.L = L;
-        a.f = it.f;
+        a.f = lay.zs ? lay.fpad : it.f;
+        a.zs = lay.zs;
         a.att = lay.table;
         a.part = scr;
         a.nslab = t.nslab;
@@ -2586,7 +2602,9 @@ TickTables *tick_build(const TickItem *items, int n, int *status)
         gg.mode = 2;
         gg.out = it.f;
         gg.sens = lay.sens;
-        gg.v4 = gather_v4(p, {it.f, lay.sens});
+        gg.fpad = lay.fpad;
+        gg.zs = lay.zs;
+        gg.v4 = gather_v4(p, {it.f, lay.sens, lay.fpad});
         const int gi = (int)ga.size();
         ga.push_back(gg);
         for (int al = 0; al < L.n; ++al) {
@@ -2665,6 +2683,8 @@ int tick_launch(TickTables *T, char *host, char *dev, hipStream_t st, hipStream_
         if (e == hipSuccess) e = hipStreamWaitEvent(st, uploaded, 0);
         if (e != hipSuccess) return hip_fail(e, "tick table upload");
     }
+    for (const TickTables::Pad &pd : T->pads)
+        if (const int st2 = launch_pad(pd.p, pd.src, pd.dst, pd.zs, st)) return st2;
     for (const TickTables::Launch &l : T->launches) {
         static const int prof[5] = {K_SENS, K_FWD_B, K_REDUCE_B, K_BACK_B, K_GATHER_B};
         allow_smem(l.fn, l.smem);

@@ -28,6 +28,7 @@ struct TickItem {
     int n_subsets;
     int sens;
     int subset;
+    int first_sub;  // the request's first subiteration: copy f into the forward's padded layout first
 };
 int tick_region_bytes(const spect_plan *p, int n_subsets, bool mu, size_t *bytes);
 // Voxel-angles of one subiteration (N^2 Nz times the larger subset size),

@@ -264,7 +264,7 @@ struct spect_server {
             if (r.issued >= r.steps) continue;
             const int k = r.issued, M = r.subsets;
             spect_internal::TickItem it{r.plan, r.f, r.mu, r.g, r.s, pool + r.off, M, k < M ? 1 : 0,
-                                        k < M ? k : (k - M) % M};
+                                        k < M ? k : (k - M) % M, k == M ? 1 : 0};
             items.push_back(it);
             ids.push_back(id);
             if (k == 0) first.push_back(id);
