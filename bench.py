@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
                     [--recon-only] [--pair-only] [--workload osem|unrolled|bsrem|batched|serving]
-                    [--serve-seconds S]
+                    [--serve-seconds S] [--serve-runs both|continuous|single]
 
 Default workload: the 128^3 voxel, 120-angle acquisition (0.48 cm voxels,
 128 x 128 bins, attenuation map with a water cylinder 0.15/cm, a bone rod
@@ -769,12 +769,16 @@ def bench_serving(args):
         log(f"{name}: {st}")
         return st
 
+    # --serve-runs picks one of the two ways (a 10-minute stream per way is
+    # then one process each; the seeded trace and burst are the same)
+    names = {"both": ("continuous_batching", "one_at_a_time"), "continuous": ("continuous_batching",),
+             "single": ("one_at_a_time",)}[args.serve_runs]
     results = {}
-    for name in ("continuous_batching", "one_at_a_time"):
+    for name in names:
         results[name] = run(name, trace)
-    for name in ("continuous_batching", "one_at_a_time"):
+    for name in names:
         results["burst_" + name] = run(name, burst)
-    cb = results["continuous_batching"]
+    cb = results.get("continuous_batching", results.get("one_at_a_time"))
     out = {
         "metric": "served OSEM reconstructions/s and p50/p99 latency (Poisson 20 req/s, 3 acquisition classes)",
         "value": cb["recon_per_s"],
@@ -786,9 +790,12 @@ def bench_serving(args):
                    "rate_per_s": P.C5_RATE, "seconds": args.serve_seconds, "max_resident": 8, "pool_gib": 64},
         "latency_ms_p50": cb["latency_ms_p50"], "latency_ms_p99": cb["latency_ms_p99"],
         "runs": results,
-        "burst_throughput_ratio": results["burst_continuous_batching"]["recon_per_s"] /
-        results["burst_one_at_a_time"]["recon_per_s"],
+        "burst_throughput_ratio": (results["burst_continuous_batching"]["recon_per_s"] /
+                                   results["burst_one_at_a_time"]["recon_per_s"]
+                                   if len(names) == 2 else None),
     }
+    if len(names) == 1:
+        out["config"]["runs"] = names[0]
     print(json.dumps(out), flush=True)
 
 
@@ -804,6 +811,7 @@ def main():
                     help="time only the whole-angle projector pair of the default workload (for profiling)")
     ap.add_argument("--workload", choices=("osem", "unrolled", "bsrem", "batched", "serving"), default="osem")
     ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-runs", choices=("both", "continuous", "single"), default="both")
     ap.add_argument("--oracle-sample", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.oracle_sample:
