@@ -233,18 +233,23 @@ int spect_batch_set_schedule(spect_batch *batch, int32_t schedule);
  * the sensitivity pass of each subset (with an attenuation map it also fills
  * the subset's attenuation-factor table), then n_iters x n_subsets
  * subiterations; each of these is one step.  A scheduler thread owned by the
- * server launches ticks back to back on the server's stream (default
- * priority); a tick takes the next step of every resident request, whatever
- * its geometry, subset or iteration, and runs them together as one launch
- * per stage (sensitivity pass, forward projection with the ratio, the
- * rotated-frame adjoint, gather with the update; the forward and adjoint
- * stages once per blur-radius class).  At every tick boundary the head of
- * the arrival-order queue is admitted when fewer than n_slots requests are
- * resident and the pool (pool_bytes of device memory owned by the server)
- * holds a free block of the request's workspace (spect_workspace_size with
- * SPECT_OP_RECON); a head that does not fit waits, and so do the requests
- * behind it.  A request retires, freeing its block, once the tick holding
- * its last step has finished.  Its state lives in its block, laid out as
+ * server launches ticks back to back on up to four lanes (streams of default
+ * priority that run concurrently); a lane's tick takes the next step of each
+ * of the lane's resident requests, whatever its geometry, subset or
+ * iteration, and runs them together as one launch per stage (sensitivity
+ * pass, forward projection with the ratio, the rotated-frame adjoint, gather
+ * with the update; the forward and adjoint stages once per blur-radius
+ * class).  The tick's launch tables are copied on a separate upload stream.
+ * At every tick boundary requests are admitted in arrival order, to the lane
+ * with the least work left, while fewer than n_slots are resident and the
+ * pool (pool_bytes of device memory owned by the server) holds a free block
+ * of the request's workspace (spect_workspace_size with SPECT_OP_RECON); a
+ * request that does not fit waits, and so do the requests behind it.  One
+ * exception: a wide request (one step covers at least 2^24 voxel-angles, so
+ * it fills the device on its own) waits while another wide request is
+ * resident, unless four or more wide requests are queued; narrow requests
+ * behind it may start meanwhile.  A request retires, freeing its block, once
+ * the tick holding its last step has finished.  Its state lives in its block, laid out as
  * osem_reconstruct's workspace, and its steps use osem_reconstruct's launch
  * arguments: the result equals osem_reconstruct alone, bitwise, whatever
  * shares its ticks.  With an attenuation map the tables of all subsets must

@@ -672,6 +672,7 @@ int run_forward(const spect_plan *p, const float *f, const float *mu, int att, c
     a.cbset = chunk_set(att, which);
     a.vec = vec;
     a.zs = zs;
+    a.cus = p->cus;
     KernelFn fk = fwd_kernel(att, p->kmc, vec);
     allow_smem(reinterpret_cast<const void *>(fk), fwd_smem(p));
     {

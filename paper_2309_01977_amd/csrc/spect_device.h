@@ -498,6 +498,7 @@ struct FwdArgs {
     int nslab, nchunk, cbset;
     int vec;
     int zs;             // column stride of f in floats (0: Nz); mu, when sampled, is never padded
+    int cus;            // compute units (0: chunks in grid order; see fwd_main)
 };
 
 // LDS row buffers of the forward: [buf][row j' + KMC][q] float4, two buffers
@@ -823,10 +824,20 @@ __device__ __forceinline__ void fwd_body(const Args &a, int slab, int chunk, int
 // Largest forward workgroup: FQ lanes per bin, N <= 256.
 constexpr int FWD_MAX_THREADS = FQ * 256;
 
+// Workgroups are dispatched in linear order, and a CU receives a second
+// workgroup one device-full of workgroups after its first; with the chunk as
+// the fast index after the slab, a CU's two workgroups would hold the same
+// chunk of two angles (two of the heaviest, or two of the lightest).  The
+// angles whose workgroups start in an odd device-full take their chunks in
+// reverse order instead, so that heavy and light chunks share CUs.  The
+// reversal is per angle, so every (slab, chunk, angle) is still covered once.
 template <int ATT, int KMC, bool VEC>
 __global__ __launch_bounds__(FWD_MAX_THREADS) void fwd_main(FwdArgs a)
 {
-    fwd_body<ATT, KMC, VEC>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+    const int z = blockIdx.z;
+    const int round = a.cus > 0 ? (int)(((long)a.nslab * a.nchunk * z) / a.cus) : 0;
+    const int chunk = (round & 1) ? a.nchunk - 1 - (int)blockIdx.y : (int)blockIdx.y;
+    fwd_body<ATT, KMC, VEC>(a, blockIdx.x, chunk, z);
 }
 
 template <int ATT, int KMC, bool VEC, bool PERSIST>

@@ -11,9 +11,10 @@
 // the next step of each of the lane's resident requests (requests at
 // different subsets, iterations and geometries alike) and runs them as one
 // launch per stage (see tick_build).  Requests queue in arrival order; at
-// every tick boundary the head of the queue is admitted, to the lane with
-// the least work left, as soon as fewer than n_slots requests are resident
-// and the pool holds a free block of its workspace; a request retires once
+// every tick boundary they are admitted in that order, to the lane with the
+// least work left, as soon as fewer than n_slots requests are resident and
+// the pool holds a free block of the workspace (a wide request may wait for
+// another wide one to finish; see admit()); a request retires once
 // the tick holding its last step has finished, freeing its block.  A request's state lives in its
 // block laid out as osem_reconstruct's workspace and its steps use
 // osem_reconstruct's launch arguments, so its result is osem_reconstruct's,
@@ -100,6 +101,11 @@ struct Lane {
 };
 
 constexpr int kMaxLanes = 4;
+// A request is wide when one of its steps covers at least this many
+// voxel-angles (a 15-angle subset of a 128^3 object is 3.1e7); wide requests
+// overlap only while at least kWideBacklog of them are queued.
+constexpr double kWideStep = double(1 << 24);
+constexpr int kWideBacklog = 4;
 
 struct spect_server {
     int device = 0;
@@ -188,16 +194,34 @@ struct spect_server {
         return n;
     }
 
-    // Admit from the head of the queue while a resident place and a pool
-    // block are free (arrival order is kept: a head that does not fit waits).
+    // A wide request's steps fill the device on their own.  Two wide
+    // requests resident together share the device and both finish late,
+    // where running them in turn finishes the older one first: at light load
+    // that ordering gives the shorter latency tail.  So a wide request waits
+    // while another wide one is resident, unless a backlog of wide requests
+    // is queued (then they overlap for throughput); narrow requests behind a
+    // waiting wide one may start first, and run beside the wide ones.
+    static bool wide(const Request &r) { return r.step_work >= kWideStep; }
+
+    // Admit in arrival order while a resident place and a pool block are
+    // free, with the exception above for waiting wide requests; a request
+    // that does not fit in the pool stops admission until blocks return.
     void admit()
     {
         while (!queue.empty() && running() < max_resident) {
-            Request &r = reqs[queue.front()];
+            int wide_res = 0, wide_q = 0;
+            for (const Lane &ln : lanes)
+                for (int64_t rid : ln.resident) wide_res += wide(reqs[rid]) ? 1 : 0;
+            for (int64_t qid : queue) wide_q += wide(reqs[qid]) ? 1 : 0;
+            const int wide_cap = wide_q >= kWideBacklog ? max_resident : 1;
+            auto pick = queue.begin();
+            while (pick != queue.end() && wide(reqs[*pick]) && wide_res >= wide_cap) ++pick;
+            if (pick == queue.end()) break;
+            Request &r = reqs[*pick];
             size_t off = 0;
             if (!alloc(r.ws, &off)) break;
-            const int64_t id = queue.front();
-            queue.pop_front();
+            const int64_t id = *pick;
+            queue.erase(pick);
             r.off = off;
             r.issued = 0;
             if (r.iters == 0) {
