@@ -1375,94 +1375,186 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
         w.o = a.g.xy0[(size_t)ang * N + min(max(w.jlo + q, 0), N - 1)];
         return w;
     };
-    Win nxt;
-    if (a.L.n > 0) nxt = window(0);
-    // the quad's candidate table: entry 3 q + di = (weight, byte offset) of
-    // window row di, column q
-    __shared__ float2 ctab[256 / 4][9];
-    float2 *qt = ctab[threadIdx.x >> 2];
-    // loaded candidate bricks, kept across angles (see below)
-    float4 vv[NS][GC];
+    if constexpr (NS == 1) {
+        // One slab per workgroup: small launches, bound by the latency of
+        // each angle's candidate loads.  The loads of angle al + 1 are issued
+        // before the sums of angle al (two register sets, two candidate
+        // tables), every slot unconditionally (an empty slot reads zeros past
+        // the end of the angle's plane), so that no branch makes the compiler
+        // wait for them early.  The sums are formed in the same order as in
+        // the loop below.
+        __shared__ float2 ctab2[2][256 / 4][9];
+        struct Stage {
+            float4 v[GC];
+            float w[GC];
+            int m;  // the quad's candidates beyond the slots
+            __amdgpu_buffer_rsrc_t zr;
+        };
+        // the window (and its ray-origin load) one stage ahead, as below.
+        // Stages run in pairs without branches around their loads: a stage
+        // past the last angle (al == L) has no candidates and adds zeros.
+        const int L = max(a.L.n, 1);  // an empty list runs one stage of zeros
+        Win wn = window(0);
+        auto stage = [&](int al, Stage &S, int buf) {
+            const bool live = al < a.L.n;
+            const Win cur = wn;
+            wn = window(min(al + 1, L - 1));
+            S.zr = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(zs + (size_t)min(al, L - 1) * zstride),
+                                                     (short)0, nsl * planeb, kBufferDword3);
+            float2 *qt = ctab2[buf][threadIdx.x >> 2];
+            const int jp = cur.jlo + q;
+            const bool jin = live && q < 3 && (unsigned)jp < (unsigned)N;
+            const uint32_t jb = (uint32_t)jp * (SLAB * 4);
+            int mq = 0;
 #pragma unroll
-    for (int sl = 0; sl < NS; ++sl)
-#pragma unroll
-        for (int k = 0; k < GC; ++k) vv[sl][k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int al = 0; al < a.L.n; ++al) {
-        const Win cur = nxt;
-        if (al + 1 < a.L.n) nxt = window(al + 1);
-        // raw buffer over the angle's planes of this slab pair: an offset
-        // past its end reads zeros (the second plane of a lone last slab)
-        const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<float *>(zs + (size_t)al * zstride), (short)0, nsl * planeb, kBufferDword3);
-        // this lane's window column jlo + q: weights and brick offsets of its
-        // three rows (lane 3 has none)
-        const int jp = cur.jlo + q;
-        const bool jin = q < 3 && (unsigned)jp < (unsigned)N;
-        const uint32_t jb = (uint32_t)jp * (SLAB * 4);
-        int mq = 0;  // bit di: row di of this window column has a non-zero weight
-#pragma unroll
-        for (int di = 0; di < 3; ++di) {
-            const int ip = cur.ilo + di;
-            const bool inr = jin && (unsigned)ip < (unsigned)N;
-            const float X = fmaf((float)ip, cur.cs.x, cur.o.x), Y = fmaf((float)ip, cur.cs.y, cur.o.y);
-            const float wx = fmaxf(0.f, 1.f - fabsf(X - fxv)), wy = fmaxf(0.f, 1.f - fabsf(Y - fyv));
-            const float wt = inr ? wx * wy : 0.f;
-            if (q < 3) qt[3 * q + di] = make_float2(wt, __int_as_float((int)((uint32_t)ip * rowb + jb)));
-            mq |= (wt > 0.f ? 1 : 0) << di;
-        }
-        // the quad's non-zero candidates, bit 3 q + di
-        int m = quad_bcast<0>(mq) | (quad_bcast<1>(mq) << 3) | (quad_bcast<2>(mq) << 6);
-        // the table entries are written and read by lanes of this wave only
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-        // slot k takes the k-th non-zero candidate.  A quad with fewer
-        // candidates leaves the slot's registers as they are and gives it
-        // weight 0: they hold zero or a value this lane loaded earlier with a
-        // positive weight into the same row sums, so the product is 0 unless
-        // that row's sum is already non-finite.
-        // the slots' table reads are issued together, then their loads
-        bool hk[GC];
-        float2 ek[GC];
-#pragma unroll
-        for (int k = 0; k < GC; ++k) {
-            hk[k] = m != 0;
-            ek[k] = qt[hk[k] ? __builtin_ctz(m) : 0];
-            m &= m - 1;
-        }
-        float wk[GC];
-#pragma unroll
-        for (int k = 0; k < GC; ++k) {
-            wk[k] = hk[k] ? ek[k].x : 0.f;
-            if (hk[k]) {
-                const int off = __float_as_int(ek[k].y) + qoff;
-#pragma unroll
-                for (int sl = 0; sl < NS; ++sl)
-                    vv[sl][k] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(zr, off + sl * planeb, 0, 0));
+            for (int di = 0; di < 3; ++di) {
+                const int ip = cur.ilo + di;
+                const bool inr = jin && (unsigned)ip < (unsigned)N;
+                const float X = fmaf((float)ip, cur.cs.x, cur.o.x), Y = fmaf((float)ip, cur.cs.y, cur.o.y);
+                const float wx = fmaxf(0.f, 1.f - fabsf(X - fxv)), wy = fmaxf(0.f, 1.f - fabsf(Y - fyv));
+                const float wt = inr ? wx * wy : 0.f;
+                if (q < 3) qt[3 * q + di] = make_float2(wt, __int_as_float((int)((uint32_t)ip * rowb + jb)));
+                mq |= (wt > 0.f ? 1 : 0) << di;
             }
-        }
+            int m = quad_bcast<0>(mq) | (quad_bcast<1>(mq) << 3) | (quad_bcast<2>(mq) << 6);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+            bool hk[GC];
+            float2 ek[GC];
 #pragma unroll
-        for (int k = 0; k < GC; ++k) {
-#pragma unroll
-            for (int sl = 0; sl < NS; ++sl) {
-                acc[sl][0] = fmaf(wk[k], vv[sl][k].x, acc[sl][0]);
-                acc[sl][1] = fmaf(wk[k], vv[sl][k].y, acc[sl][1]);
-                acc[sl][2] = fmaf(wk[k], vv[sl][k].z, acc[sl][2]);
-                acc[sl][3] = fmaf(wk[k], vv[sl][k].w, acc[sl][3]);
+            for (int k = 0; k < GC; ++k) {
+                hk[k] = m != 0;
+                ek[k] = qt[hk[k] ? __builtin_ctz(m) : 0];
+                m &= m - 1;
             }
-        }
-        // candidates beyond the slots (not expected; kept for any geometry)
-        while (m != 0) {
-            const float2 e = qt[__builtin_ctz(m)];
-            m &= m - 1;
-            const int off = __float_as_int(e.y) + qoff;
 #pragma unroll
-            for (int sl = 0; sl < NS; ++sl) {
-                const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(zr, off + sl * planeb, 0, 0));
-                acc[sl][0] = fmaf(e.x, v.x, acc[sl][0]);
-                acc[sl][1] = fmaf(e.x, v.y, acc[sl][1]);
-                acc[sl][2] = fmaf(e.x, v.z, acc[sl][2]);
-                acc[sl][3] = fmaf(e.x, v.w, acc[sl][3]);
+            for (int k = 0; k < GC; ++k) {
+                S.w[k] = hk[k] ? ek[k].x : 0.f;
+                const int off = hk[k] ? __float_as_int(ek[k].y) + qoff : kVolPastEnd;
+                S.v[k] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(S.zr, off, 0, 0));
+            }
+            S.m = m;
+        };
+        auto accum = [&](const Stage &S, int buf) {
+#pragma unroll
+            for (int k = 0; k < GC; ++k) {
+                acc[0][0] = fmaf(S.w[k], S.v[k].x, acc[0][0]);
+                acc[0][1] = fmaf(S.w[k], S.v[k].y, acc[0][1]);
+                acc[0][2] = fmaf(S.w[k], S.v[k].z, acc[0][2]);
+                acc[0][3] = fmaf(S.w[k], S.v[k].w, acc[0][3]);
+            }
+            const float2 *qt = ctab2[buf][threadIdx.x >> 2];
+            int m = S.m;
+            while (m != 0) {
+                const float2 e = qt[__builtin_ctz(m)];
+                m &= m - 1;
+                const float4 v = __builtin_bit_cast(
+                    float4, __builtin_amdgcn_raw_buffer_load_b128(S.zr, __float_as_int(e.y) + qoff, 0, 0));
+                acc[0][0] = fmaf(e.x, v.x, acc[0][0]);
+                acc[0][1] = fmaf(e.x, v.y, acc[0][1]);
+                acc[0][2] = fmaf(e.x, v.z, acc[0][2]);
+                acc[0][3] = fmaf(e.x, v.w, acc[0][3]);
+            }
+        };
+        Stage sa, sb;
+        stage(0, sa, 0);
+        for (int al = 0; al < L; al += 2) {
+            stage(al + 1, sb, 1);
+            accum(sa, 0);
+            stage(al + 2, sa, 0);
+            accum(sb, 1);
+        }
+    } else {
+        Win nxt;
+        if (a.L.n > 0) nxt = window(0);
+        // the quad's candidate table: entry 3 q + di = (weight, byte offset) of
+        // window row di, column q
+        __shared__ float2 ctab[256 / 4][9];
+        float2 *qt = ctab[threadIdx.x >> 2];
+        // loaded candidate bricks, kept across angles (see below)
+        float4 vv[NS][GC];
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl)
+#pragma unroll
+            for (int k = 0; k < GC; ++k) vv[sl][k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int al = 0; al < a.L.n; ++al) {
+            const Win cur = nxt;
+            if (al + 1 < a.L.n) nxt = window(al + 1);
+            // raw buffer over the angle's planes of this slab pair: an offset
+            // past its end reads zeros (the second plane of a lone last slab)
+            const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float *>(zs + (size_t)al * zstride), (short)0, nsl * planeb, kBufferDword3);
+            // this lane's window column jlo + q: weights and brick offsets of its
+            // three rows (lane 3 has none)
+            const int jp = cur.jlo + q;
+            const bool jin = q < 3 && (unsigned)jp < (unsigned)N;
+            const uint32_t jb = (uint32_t)jp * (SLAB * 4);
+            int mq = 0;  // bit di: row di of this window column has a non-zero weight
+#pragma unroll
+            for (int di = 0; di < 3; ++di) {
+                const int ip = cur.ilo + di;
+                const bool inr = jin && (unsigned)ip < (unsigned)N;
+                const float X = fmaf((float)ip, cur.cs.x, cur.o.x), Y = fmaf((float)ip, cur.cs.y, cur.o.y);
+                const float wx = fmaxf(0.f, 1.f - fabsf(X - fxv)), wy = fmaxf(0.f, 1.f - fabsf(Y - fyv));
+                const float wt = inr ? wx * wy : 0.f;
+                if (q < 3) qt[3 * q + di] = make_float2(wt, __int_as_float((int)((uint32_t)ip * rowb + jb)));
+                mq |= (wt > 0.f ? 1 : 0) << di;
+            }
+            // the quad's non-zero candidates, bit 3 q + di
+            int m = quad_bcast<0>(mq) | (quad_bcast<1>(mq) << 3) | (quad_bcast<2>(mq) << 6);
+            // the table entries are written and read by lanes of this wave only
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+            // slot k takes the k-th non-zero candidate.  A quad with fewer
+            // candidates leaves the slot's registers as they are and gives it
+            // weight 0: they hold zero or a value this lane loaded earlier with a
+            // positive weight into the same row sums, so the product is 0 unless
+            // that row's sum is already non-finite.
+            // the slots' table reads are issued together, then their loads
+            bool hk[GC];
+            float2 ek[GC];
+#pragma unroll
+            for (int k = 0; k < GC; ++k) {
+                hk[k] = m != 0;
+                ek[k] = qt[hk[k] ? __builtin_ctz(m) : 0];
+                m &= m - 1;
+            }
+            float wk[GC];
+#pragma unroll
+            for (int k = 0; k < GC; ++k) {
+                wk[k] = hk[k] ? ek[k].x : 0.f;
+                if (hk[k]) {
+                    const int off = __float_as_int(ek[k].y) + qoff;
+#pragma unroll
+                    for (int sl = 0; sl < NS; ++sl)
+                        vv[sl][k] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(zr, off + sl * planeb, 0, 0));
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < GC; ++k) {
+#pragma unroll
+                for (int sl = 0; sl < NS; ++sl) {
+                    acc[sl][0] = fmaf(wk[k], vv[sl][k].x, acc[sl][0]);
+                    acc[sl][1] = fmaf(wk[k], vv[sl][k].y, acc[sl][1]);
+                    acc[sl][2] = fmaf(wk[k], vv[sl][k].z, acc[sl][2]);
+                    acc[sl][3] = fmaf(wk[k], vv[sl][k].w, acc[sl][3]);
+                }
+            }
+            // candidates beyond the slots (not expected; kept for any geometry)
+            while (m != 0) {
+                const float2 e = qt[__builtin_ctz(m)];
+                m &= m - 1;
+                const int off = __float_as_int(e.y) + qoff;
+#pragma unroll
+                for (int sl = 0; sl < NS; ++sl) {
+                    const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(zr, off + sl * planeb, 0, 0));
+                    acc[sl][0] = fmaf(e.x, v.x, acc[sl][0]);
+                    acc[sl][1] = fmaf(e.x, v.y, acc[sl][1]);
+                    acc[sl][2] = fmaf(e.x, v.z, acc[sl][2]);
+                    acc[sl][3] = fmaf(e.x, v.w, acc[sl][3]);
+                }
             }
         }
     }
