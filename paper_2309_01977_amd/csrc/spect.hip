@@ -230,7 +230,11 @@ Tuning tune(const spect_plan *p, int n_list, int att, int which)
     auto best_split = [&](int passes) {
         double best = 1e300;
         int bn = 1;
-        for (int nc = 1; nc <= p->cap; ++nc) {
+        // the forward's chunks keep at least 8 depths on average (its
+        // partial rows grow with the chunk count); the rotated-frame pass
+        // writes each depth once and may take chunks of 4
+        const int ncmax = (passes & T_FWD) ? std::max(1, std::min(p->cap, p->N / 8)) : p->cap;
+        for (int nc = 1; nc <= ncmax; ++nc) {
             // the largest chunk, in depths of average work, of each pass
             const double Df = p->chunk_cost[chunk_set(att, which)][nc], Db = Df;
             const long wgs = base * nc;
@@ -1019,8 +1023,8 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
         }
     }
     // depth chunking: per-depth work 10 + K, boundaries per chunk count and
-    // angle (at least 8 depths per chunk on average)
-    p->cap = std::max(1, N / 8);
+    // angle (at least 4 depths per chunk on average; the forward keeps 8)
+    p->cap = std::max(1, N / 4);
     const int cap = p->cap;
     std::vector<int> cb((size_t)2 * cap * A * (cap + 1), 0);
     for (int set = 0; set < 2; ++set) {
