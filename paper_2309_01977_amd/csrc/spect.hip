@@ -433,13 +433,23 @@ size_t recon_tau_bytes(const spect_plan *p, int M, int m, bool mu)
 
 size_t osem_ws(const spect_plan *p, int M, bool mu);
 
+// Without attenuation the reconstruction runs the sensitivity passes of all
+// subsets as one launch over every angle (subset after subset), then one
+// gather per subset: the per-subset passes of a small object are too short
+// to fill the device.
+bool combined_sens(const spect_plan *p, int M, bool mu) { return !mu && M > 1 && p->A <= MAXL; }
+
 size_t recon_ws(const spect_plan *p, int M, bool mu)
 {
     size_t b = (size_t)M * vol_bytes(p);
     for (int m = 0; m < M; ++m) b += recon_tau_bytes(p, M, m, mu);
     const int att = use_table(p, M, mu) ? ATT_READ : att_of(mu);
     b += pad_bytes(p, att);
-    if (!use_table(p, M, mu)) return b + osem_ws(p, M, mu);
+    if (!use_table(p, M, mu)) {
+        size_t rest = osem_ws(p, M, mu);
+        if (combined_sens(p, M, mu)) rest = std::max(rest, osem_q_bytes(p, M) + back_need(p, p->A, ATT_NONE, T_BACK));
+        return b + rest;
+    }
     size_t scratch = 0;
     for (int nl : {p->A / M, (p->A + M - 1) / M}) {
         if (nl < 1) continue;
@@ -716,13 +726,47 @@ bool gather_v4(const spect_plan *p, std::initializer_list<const void *> ptrs)
     return true;
 }
 
+// The gather of a back projection: the object-space sums over the list's
+// angles of the rotated-frame bricks z ([L][nslab][N][N][16]), combined into
+// out by `mode` (see GatherArgs).
+int launch_gather(const spect_plan *p, const AngleList &L, const float *z, int nslab, int mode, float *out,
+                  const float *sens, float *fpad, int zs, const BsremTerms *bt, const StepTerms *stt, hipStream_t st)
+{
+    GatherArgs gg{};
+    gg.g = p->g;
+    gg.L = L;
+    gg.z = z;
+    gg.nslab = nslab;
+    gg.mode = mode;
+    gg.out = out;
+    gg.sens = sens;
+    gg.fpad = fpad;
+    gg.zs = zs;
+    gg.v4 = gather_v4(p, {out, sens, fpad, bt ? bt->sens_all : nullptr, bt ? bt->prior : nullptr});
+    gg.bt = bt ? *bt : BsremTerms{nullptr, nullptr, 0.f, 0.f};
+    gg.st = stt ? *stt : StepTerms{nullptr, nullptr, nullptr};
+    const int tiles = (p->N + GT - 1) / GT;
+    {
+        // one slab per workgroup when two would leave the device under-filled
+        const bool one = (long)tiles * tiles * ((nslab + GS - 1) / GS) < 2L * p->cus;
+        ProfScope ps(K_GATHER, st);
+        if (one)
+            hipLaunchKernelGGL(back_gather<1>, dim3(tiles * tiles, nslab), dim3(256), 0, st, gg);
+        else
+            hipLaunchKernelGGL(back_gather<GS>, dim3(tiles * tiles, (nslab + GS - 1) / GS), dim3(256), 0, st, gg);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "back projection launch");
+    return SPECT_OK;
+}
+
 // Back projection of one list: rotated-frame pass, then the gather.
 // att: ATT_NONE / ATT_SAMPLE / ATT_WRITE (sample mu and fill table) /
 // ATT_READ (from table).  ws holds [tau][z]; tau_given as in run_forward.
 int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const float *mu, int att,
              float *table, const AngleList &L, char *ws, size_t ws_avail, const float *tau_given, int mode,
              float *out, const float *sens, bool vec, int which, hipStream_t st, const BsremTerms *bt = nullptr,
-             const StepTerms *stt = nullptr, float *fpad = nullptr, int zs = 0)
+             const StepTerms *stt = nullptr, float *fpad = nullptr, int zs = 0, bool do_gather = true)
 {
     const Tuning t = tune(p, L.n, att, which);
     if (back_need(p, L.n, att, which) > ws_avail)
@@ -785,32 +829,11 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
         ProfScope ps(K_BACK_ROT, st);
         hipLaunchKernelGGL(bk, dim3(t.nslab, t.nchunk_b, L.n), dim3(block_threads(p->N)), back_smem(p), st, b);
     }
-    GatherArgs gg{};
-    gg.g = p->g;
-    gg.L = L;
-    gg.z = z;
-    gg.nslab = t.nslab;
-    gg.mode = mode;
-    gg.out = out;
-    gg.sens = sens;
-    gg.fpad = fpad;
-    gg.zs = zs;
-    gg.v4 = gather_v4(p, {out, sens, fpad, bt ? bt->sens_all : nullptr, bt ? bt->prior : nullptr});
-    gg.bt = bt ? *bt : BsremTerms{nullptr, nullptr, 0.f, 0.f};
-    gg.st = stt ? *stt : StepTerms{nullptr, nullptr, nullptr};
-    const int tiles = (p->N + GT - 1) / GT;
-    {
-        // one slab per workgroup when two would leave the device under-filled
-        const bool one = (long)tiles * tiles * ((t.nslab + GS - 1) / GS) < 2L * p->cus;
-        ProfScope ps(K_GATHER, st);
-        if (one)
-            hipLaunchKernelGGL(back_gather<1>, dim3(tiles * tiles, t.nslab), dim3(256), 0, st, gg);
-        else
-            hipLaunchKernelGGL(back_gather<GS>, dim3(tiles * tiles, (t.nslab + GS - 1) / GS), dim3(256), 0, st, gg);
+    if (!do_gather) {
+        const hipError_t e = hipGetLastError();
+        return e == hipSuccess ? SPECT_OK : hip_fail(e, "back projection launch");
     }
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "back projection launch");
-    return SPECT_OK;
+    return launch_gather(p, L, z, t.nslab, mode, out, sens, fpad, zs, bt, stt, st);
 }
 
 // grad = gradient of the relative difference prior at f (weight gamma).
@@ -1535,7 +1558,27 @@ int reconstruct(const spect_plan *plan, float *f, const float *mu, const float *
         char *rest = w + off + qb + pb;
         const size_t avail = ws_bytes - off - qb - pb;
         // subset sensitivities H_m^T 1; with a table this pass also fills it
-        for (int m = 0; m < M; ++m) {
+        if (combined_sens(plan, M, mu != nullptr)) {
+            std::vector<int> all, first(M);
+            for (int m = 0; m < M; ++m) {
+                first[m] = (int)all.size();
+                all.insert(all.end(), lists[m].idx, lists[m].idx + lists[m].n);
+            }
+            const AngleList La = to_list(all.data(), (int)all.size());
+            if ((st = run_back(plan, nullptr, 0, 1, nullptr, ATT_NONE, nullptr, La, rest, avail, nullptr, 0, nullptr,
+                               nullptr, vec, T_BACK, s, nullptr, nullptr, nullptr, 0, false)))
+                return st;
+            // the pass wrote one brick volume per listed angle at the start of
+            // the scratch; subset m's are contiguous from its first angle
+            const int nslab = tune(plan, La.n, ATT_NONE, T_BACK).nslab;
+            const float *z = reinterpret_cast<const float *>(rest);
+            const size_t per = (size_t)nslab * plan->N * plan->N * SLAB;
+            for (int m = 0; m < M; ++m)
+                if ((st = launch_gather(plan, lists[m], z + (size_t)first[m] * per, nslab, 0, sens[m], nullptr,
+                                        nullptr, 0, nullptr, nullptr, s)))
+                    return st;
+        }
+        for (int m = 0; m < M && !combined_sens(plan, M, mu != nullptr); ++m) {
             if (table)
                 st = run_back(plan, nullptr, 0, 1, mu, ATT_WRITE, per[m], lists[m], rest, avail, nullptr, 0, sens[m],
                               nullptr, vec, T_BACK, s);
