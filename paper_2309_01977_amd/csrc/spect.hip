@@ -760,6 +760,35 @@ int launch_gather(const spect_plan *p, const AngleList &L, const float *z, int n
     return SPECT_OK;
 }
 
+// Sensitivity gathers of the M interleaved subsets of La (every angle,
+// subset after subset) in one launch: subset m's sum into
+// sens0 + m * out_stride (see back_gather_subsets).
+int launch_gather_subsets(const spect_plan *p, const AngleList &La, const float *z, int nslab, int M, float *sens0,
+                          size_t out_stride, hipStream_t st)
+{
+    GatherArgs gg{};
+    gg.g = p->g;
+    gg.L = La;
+    gg.z = z;
+    gg.nslab = nslab;
+    gg.mode = 0;
+    gg.out = sens0;
+    gg.v4 = gather_v4(p, {sens0}) && (out_stride % 4 == 0);
+    const int tiles = (p->N + GT - 1) / GT;
+    {
+        const bool one = (long)tiles * tiles * ((nslab + GS - 1) / GS) * M < 2L * p->cus;
+        ProfScope ps(K_GATHER, st);
+        if (one)
+            hipLaunchKernelGGL(back_gather_subsets<1>, dim3(tiles * tiles, nslab, M), dim3(256), 0, st, gg, M,
+                               out_stride);
+        else
+            hipLaunchKernelGGL(back_gather_subsets<GS>, dim3(tiles * tiles, (nslab + GS - 1) / GS, M), dim3(256), 0,
+                               st, gg, M, out_stride);
+    }
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SPECT_OK : hip_fail(e, "sensitivity gather launch");
+}
+
 // Back projection of one list: rotated-frame pass, then the gather.
 // att: ATT_NONE / ATT_SAMPLE / ATT_WRITE (sample mu and fill table) /
 // ATT_READ (from table).  ws holds [tau][z]; tau_given as in run_forward.
@@ -1559,24 +1588,19 @@ int reconstruct(const spect_plan *plan, float *f, const float *mu, const float *
         const size_t avail = ws_bytes - off - qb - pb;
         // subset sensitivities H_m^T 1; with a table this pass also fills it
         if (combined_sens(plan, M, mu != nullptr)) {
-            std::vector<int> all, first(M);
-            for (int m = 0; m < M; ++m) {
-                first[m] = (int)all.size();
-                all.insert(all.end(), lists[m].idx, lists[m].idx + lists[m].n);
-            }
+            std::vector<int> all;
+            for (int m = 0; m < M; ++m) all.insert(all.end(), lists[m].idx, lists[m].idx + lists[m].n);
             const AngleList La = to_list(all.data(), (int)all.size());
             if ((st = run_back(plan, nullptr, 0, 1, nullptr, ATT_NONE, nullptr, La, rest, avail, nullptr, 0, nullptr,
                                nullptr, vec, T_BACK, s, nullptr, nullptr, nullptr, 0, false)))
                 return st;
             // the pass wrote one brick volume per listed angle at the start of
-            // the scratch; subset m's are contiguous from its first angle
+            // the scratch; subset m's are contiguous from its first angle,
+            // and the sensitivity volumes are vb bytes apart
             const int nslab = tune(plan, La.n, ATT_NONE, T_BACK).nslab;
-            const float *z = reinterpret_cast<const float *>(rest);
-            const size_t per = (size_t)nslab * plan->N * plan->N * SLAB;
-            for (int m = 0; m < M; ++m)
-                if ((st = launch_gather(plan, lists[m], z + (size_t)first[m] * per, nslab, 0, sens[m], nullptr,
-                                        nullptr, 0, nullptr, nullptr, s)))
-                    return st;
+            if ((st = launch_gather_subsets(plan, La, reinterpret_cast<const float *>(rest), nslab, M, sens[0],
+                                            vb / sizeof(float), s)))
+                return st;
         }
         for (int m = 0; m < M && !combined_sens(plan, M, mu != nullptr); ++m) {
             if (table)

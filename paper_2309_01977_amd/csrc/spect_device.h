@@ -1336,8 +1336,15 @@ constexpr int GC = 5;  // candidate load slots per angle
 // NS slabs per workgroup: GS, or 1 for launches too small to fill the
 // device (the sums are formed in the same order either way).
 template <int NS, class Args>
-__device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
+__device__ __forceinline__ void gather_body(const Args &a, int tile, int pair, int ao = 0, int na = -1,
+                                            const float *zb = nullptr, float *outp = nullptr)
 {
+    // angles ao .. ao + na - 1 of the list, their bricks from zb and the
+    // result into outp (by default the whole list, the bricks and the output
+    // of the arguments)
+    if (na < 0) na = a.L.n;
+    if (!zb) zb = a.z;
+    if (!outp) outp = a.out;
     const int N = a.g.N, Nz = a.g.Nz;
     const int tiles = (N + GT - 1) / GT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1352,7 +1359,7 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
     const float fxv = (float)x, fyv = (float)y;
     float acc[NS][4] = {};
     const size_t zstride = (size_t)a.nslab * N * N * SLAB;
-    const float *zs = a.z + (size_t)slab0 * N * N * SLAB;
+    const float *zs = zb + (size_t)slab0 * N * N * SLAB;
     const int qoff = 16 * q;
     const uint32_t rowb = (uint32_t)N * SLAB * 4;  // bytes per rotated row i' (N <= 256: < 2^22)
     const int planeb = (int)(N * rowb);             // bytes per slab plane (<= 4 MiB)
@@ -1365,7 +1372,7 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
     };
     auto window = [&](int al) {
         Win w;
-        const int ang = uniform(a.L.idx[al]);
+        const int ang = uniform(a.L.idx[ao + al]);
         w.cs = a.g.cs[ang];
         const float wdw = fabsf(w.cs.x) + fabsf(w.cs.y) + 1e-3f;
         const float ic = c + w.cs.x * xx + w.cs.y * yy;
@@ -1393,10 +1400,10 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
         // the window (and its ray-origin load) one stage ahead, as below.
         // Stages run in pairs without branches around their loads: a stage
         // past the last angle (al == L) has no candidates and adds zeros.
-        const int L = max(a.L.n, 1);  // an empty list runs one stage of zeros
+        const int L = max(na, 1);  // an empty list runs one stage of zeros
         Win wn = window(0);
         auto stage = [&](int al, Stage &S, int buf) {
-            const bool live = al < a.L.n;
+            const bool live = al < na;
             const Win cur = wn;
             wn = window(min(al + 1, L - 1));
             S.zr = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(zs + (size_t)min(al, L - 1) * zstride),
@@ -1467,7 +1474,7 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
         }
     } else {
         Win nxt;
-        if (a.L.n > 0) nxt = window(0);
+        if (na > 0) nxt = window(0);
         // the quad's candidate table: entry 3 q + di = (weight, byte offset) of
         // window row di, column q
         __shared__ float2 ctab[256 / 4][9];
@@ -1478,9 +1485,9 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
         for (int sl = 0; sl < NS; ++sl)
 #pragma unroll
             for (int k = 0; k < GC; ++k) vv[sl][k] = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int al = 0; al < a.L.n; ++al) {
+        for (int al = 0; al < na; ++al) {
             const Win cur = nxt;
-            if (al + 1 < a.L.n) nxt = window(al + 1);
+            if (al + 1 < na) nxt = window(al + 1);
             // raw buffer over the angle's planes of this slab pair: an offset
             // past its end reads zeros (the second plane of a lone last slab)
             const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
@@ -1566,7 +1573,7 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
         for (int sl = 0; sl < NS; ++sl) {
             const int k = (slab0 + sl) * SLAB + 4 * q;
             if (k >= Nz) break;
-            float4 *p = reinterpret_cast<float4 *>(a.out + base + k);
+            float4 *p = reinterpret_cast<float4 *>(outp + base + k);
             float4 v;
             if (a.mode == 0) {
                 v = make_float4(acc[sl][0], acc[sl][1], acc[sl][2], acc[sl][3]);
@@ -1601,7 +1608,7 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair)
         for (int r = 0; r < 4; ++r) {
             const int k = (slab0 + sl) * SLAB + 4 * q + r;
             if (k >= Nz) break;
-            float *p = a.out + base + k;
+            float *p = outp + base + k;
             if (a.mode == 0) {
                 *p = acc[sl][r];
             } else if (a.mode == 1) {
@@ -1638,6 +1645,21 @@ template <int NS>
 __global__ __launch_bounds__(256) void back_gather(GatherArgs a)
 {
     gather_body<NS>(a, blockIdx.x, blockIdx.y);
+}
+
+// The gathers of M interleaved subsets in one launch (blockIdx.z = subset):
+// a.L lists every angle, subset after subset (subset m holds the angles
+// m, m + M, ..., so its count is ceil((A - m) / M)); subset m's bricks follow
+// those of the subsets before it in a.z, and its result goes to
+// a.out + m * out_stride.
+template <int NS>
+__global__ __launch_bounds__(256) void back_gather_subsets(GatherArgs a, int M, size_t out_stride)
+{
+    const int m = blockIdx.z, A = a.L.n;
+    const int first = m * (A / M) + min(m, A % M), count = A / M + (m < A % M ? 1 : 0);
+    const size_t per = (size_t)a.nslab * a.g.N * a.g.N * SLAB;
+    gather_body<NS>(a, blockIdx.x, blockIdx.y, first, count, a.z + (size_t)first * per,
+                    a.out + (size_t)m * out_stride);
 }
 
 __global__ __launch_bounds__(256) void gather_batch(BatchList<GatherArgs> b)
