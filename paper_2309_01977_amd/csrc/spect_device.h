@@ -900,7 +900,24 @@ __device__ __forceinline__ void reduce_body(const Args &a, int blk, int al)
         off[i] = ok[i] ? (size_t)s * a.nchunk * cstride + (size_t)(k - s * SLAB + a.kmc) : 0;
     }
     float sum = 0.f;
-    for (int c = 0; c < a.nchunk; ++c) {
+    // four chunks' loads in flight together (the sum keeps chunk order)
+    const int nch = a.nchunk;
+    int c = 0;
+    for (; c + 4 <= nch; c += 4) {
+        float v[4][RED_SLABS];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float *p = pc + (size_t)(c + u) * cstride;
+#pragma unroll
+            for (int i = 0; i < RED_SLABS; ++i) v[u][i] = p[off[i]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int i = 0; i < RED_SLABS; ++i)
+                if (ok[i]) sum += v[u][i];
+    }
+    for (; c < nch; ++c) {
         const float *p = pc + (size_t)c * cstride;
         float v[RED_SLABS];
 #pragma unroll
