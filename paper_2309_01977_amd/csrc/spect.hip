@@ -433,11 +433,16 @@ size_t recon_tau_bytes(const spect_plan *p, int M, int m, bool mu)
 
 size_t osem_ws(const spect_plan *p, int M, bool mu);
 
-// Without attenuation the reconstruction runs the sensitivity passes of all
-// subsets as one launch over every angle (subset after subset), then one
-// gather per subset: the per-subset passes of a small object are too short
-// to fill the device.
-bool combined_sens(const spect_plan *p, int M, bool mu) { return !mu && M > 1 && p->A <= MAXL; }
+// Without attenuation the reconstruction of a small object runs the
+// sensitivity passes of all subsets as one launch over every angle (subset
+// after subset), then the subsets' gathers as one launch: the per-subset
+// passes of a small object are too short to fill the device.  Small: the
+// bricks of every angle fit in 512 MiB of workspace (larger objects fill the
+// device subset by subset).
+bool combined_sens(const spect_plan *p, int M, bool mu)
+{
+    return !mu && M > 1 && p->A <= MAXL && (size_t)p->A * vol_bytes(p) <= (size_t(512) << 20);
+}
 
 size_t recon_ws(const spect_plan *p, int M, bool mu)
 {
