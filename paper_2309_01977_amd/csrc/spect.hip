@@ -33,6 +33,7 @@ struct spect_plan {
     double voxel_cm;
     int kmax;   // largest blur radius
     int kmc;    // compile-time radius class (multiple of 4, <= 32)
+    bool one_psf;  // every angle at one detector distance: the same taps per depth
     int TS;     // tap row stride
     int device;
     int cus;            // compute units of the device
@@ -230,10 +231,8 @@ Tuning tune(const spect_plan *p, int n_list, int att, int which)
     auto best_split = [&](int passes) {
         double best = 1e300;
         int bn = 1;
-        // the forward's chunks keep at least 8 depths on average (its
-        // partial rows grow with the chunk count); the rotated-frame pass
-        // writes each depth once and may take chunks of 4
-        const int ncmax = (passes & T_FWD) ? std::max(1, std::min(p->cap, p->N / 8)) : p->cap;
+        // chunks of 4 depths at the least, on average
+        const int ncmax = p->cap;
         for (int nc = 1; nc <= ncmax; ++nc) {
             // the largest chunk, in depths of average work, of each pass
             const double Df = p->chunk_cost[chunk_set(att, which)][nc], Db = Df;
@@ -433,16 +432,23 @@ size_t recon_tau_bytes(const spect_plan *p, int M, int m, bool mu)
 
 size_t osem_ws(const spect_plan *p, int M, bool mu);
 
-// Without attenuation the reconstruction of a small object runs the
-// sensitivity passes of all subsets as one launch over every angle (subset
-// after subset), then the subsets' gathers as one launch: the per-subset
-// passes of a small object are too short to fill the device.  Small: the
-// bricks of every angle fit in 512 MiB of workspace (larger objects fill the
-// device subset by subset).
+// Without attenuation the reconstruction runs the sensitivity passes of all
+// subsets as one launch over every angle (subset after subset), then the
+// subsets' gathers as one launch: the per-subset passes of a small object
+// are too short to fill the device.  A brick of the constant projection then
+// holds in-range tap sums of its depth only, so when every angle has the
+// same taps the pass forms one angle's brick and the gathers read it for
+// every angle; otherwise it forms a brick per angle, and only for small
+// objects (the bricks of every angle within 512 MiB of workspace; larger ones
+// fill the device subset by subset).
 bool combined_sens(const spect_plan *p, int M, bool mu)
 {
-    return !mu && M > 1 && p->A <= MAXL && (size_t)p->A * vol_bytes(p) <= (size_t(512) << 20);
+    return !mu && M > 1 && p->A <= MAXL &&
+           (p->one_psf || (size_t)p->A * vol_bytes(p) <= (size_t(512) << 20));
 }
+
+// Brick volumes the combined sensitivity pass forms.
+int sens_bricks(const spect_plan *p) { return p->one_psf ? 1 : p->A; }
 
 size_t recon_ws(const spect_plan *p, int M, bool mu)
 {
@@ -452,7 +458,8 @@ size_t recon_ws(const spect_plan *p, int M, bool mu)
     b += pad_bytes(p, att);
     if (!use_table(p, M, mu)) {
         size_t rest = osem_ws(p, M, mu);
-        if (combined_sens(p, M, mu)) rest = std::max(rest, osem_q_bytes(p, M) + back_need(p, p->A, ATT_NONE, T_BACK));
+        if (combined_sens(p, M, mu))
+            rest = std::max(rest, osem_q_bytes(p, M) + back_need(p, sens_bricks(p), ATT_NONE, T_BACK));
         return b + rest;
     }
     size_t scratch = 0;
@@ -714,7 +721,12 @@ int run_forward(const spect_plan *p, const float *f, const float *mu, int att, c
     r.e = e_rows;
     {
         ProfScope ps(K_REDUCE, st);
-        hipLaunchKernelGGL(fwd_reduce, dim3((p->N * p->Nz + 255) / 256, L.n), dim3(256), 0, st, r);
+        // slabs whose partial rows overlap one output row: at most
+        // ceil((16 + 2 kmc) / 16)
+        const dim3 grid((p->N * p->Nz + 255) / 256, L.n);
+        if (p->kmc <= 16) hipLaunchKernelGGL(fwd_reduce<3>, grid, dim3(256), 0, st, r);
+        else if (p->kmc <= 24) hipLaunchKernelGGL(fwd_reduce<4>, grid, dim3(256), 0, st, r);
+        else hipLaunchKernelGGL(fwd_reduce<RED_SLABS>, grid, dim3(256), 0, st, r);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "forward launch");
@@ -767,9 +779,10 @@ int launch_gather(const spect_plan *p, const AngleList &L, const float *z, int n
 
 // Sensitivity gathers of the M interleaved subsets of La (every angle,
 // subset after subset) in one launch: subset m's sum into
-// sens0 + m * out_stride (see back_gather_subsets).
+// sens0 + m * out_stride (see back_gather_subsets); zshare: one brick volume
+// at z serves every angle.
 int launch_gather_subsets(const spect_plan *p, const AngleList &La, const float *z, int nslab, int M, float *sens0,
-                          size_t out_stride, hipStream_t st)
+                          size_t out_stride, bool zshare, hipStream_t st)
 {
     GatherArgs gg{};
     gg.g = p->g;
@@ -778,6 +791,7 @@ int launch_gather_subsets(const spect_plan *p, const AngleList &La, const float 
     gg.nslab = nslab;
     gg.mode = 0;
     gg.out = sens0;
+    gg.zshare = zshare ? 1 : 0;
     gg.v4 = gather_v4(p, {sens0}) && (out_stride % 4 == 0);
     const int tiles = (p->N + GT - 1) / GT;
     {
@@ -849,7 +863,7 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
         b.nchunk = 1;
         if (att == ATT_NONE) {
             const long blocks = (long)nblk * t.nslab * L.n;
-            b.nchunk = (int)std::min<long>(std::max(1, p->N / 8), (2L * p->cus + blocks - 1) / blocks);
+            b.nchunk = (int)std::min<long>(std::max(1, p->N / 2), (2L * p->cus + blocks - 1) / blocks);
             b.nchunk = std::max(1, b.nchunk);
         }
         b.cbset = 0;
@@ -1045,6 +1059,7 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
     p->N = g.n;
     p->Nz = g.nz;
     p->A = g.n_angles;
+    p->one_psf = std::all_of(rad.begin(), rad.end(), [&](double r) { return r == rad[0]; });
     p->voxel_cm = g.voxel_cm;
     p->kmax = kmax;
     p->kmc = ((kmax + 3) / 4) * 4;
@@ -1080,7 +1095,7 @@ int spect_plan_create(const spect_geometry *geom, spect_plan **out)
         }
     }
     // depth chunking: per-depth work 10 + K, boundaries per chunk count and
-    // angle (at least 4 depths per chunk on average; the forward keeps 8)
+    // angle (at least 4 depths per chunk on average)
     p->cap = std::max(1, N / 4);
     const int cap = p->cap;
     std::vector<int> cb((size_t)2 * cap * A * (cap + 1), 0);
@@ -1596,7 +1611,8 @@ int reconstruct(const spect_plan *plan, float *f, const float *mu, const float *
             std::vector<int> all;
             for (int m = 0; m < M; ++m) all.insert(all.end(), lists[m].idx, lists[m].idx + lists[m].n);
             const AngleList La = to_list(all.data(), (int)all.size());
-            if ((st = run_back(plan, nullptr, 0, 1, nullptr, ATT_NONE, nullptr, La, rest, avail, nullptr, 0, nullptr,
+            const AngleList Lr = to_list(all.data(), sens_bricks(plan));
+            if ((st = run_back(plan, nullptr, 0, 1, nullptr, ATT_NONE, nullptr, Lr, rest, avail, nullptr, 0, nullptr,
                                nullptr, vec, T_BACK, s, nullptr, nullptr, nullptr, 0, false)))
                 return st;
             // the pass wrote one brick volume per listed angle at the start of
@@ -1604,7 +1620,7 @@ int reconstruct(const spect_plan *plan, float *f, const float *mu, const float *
             // and the sensitivity volumes are vb bytes apart
             const int nslab = tune(plan, La.n, ATT_NONE, T_BACK).nslab;
             if ((st = launch_gather_subsets(plan, La, reinterpret_cast<const float *>(rest), nslab, M, sens[0],
-                                            vb / sizeof(float), s)))
+                                            vb / sizeof(float), plan->one_psf, s)))
                 return st;
         }
         for (int m = 0; m < M && !combined_sens(plan, M, mu != nullptr); ++m) {

@@ -873,12 +873,35 @@ struct ReduceArgs {
 #ifdef SPECT_HOST_TU
 // Sum the partial rows of all chunks and overlapping slabs for one output
 // element (angle, bin, row), chunks outer and slabs ascending.  The slabs
-// whose partial rows hold row k are s with k + kmc - R < 16 s <= k + kmc: at
-// most five for kmc <= 32, so their offsets are fixed before the chunk loop
-// and each chunk's loads are issued together.
+// whose partial rows hold row k are s with k + kmc - R < 16 s <= k + kmc, a
+// half-open range of R = 16 + 2 kmc rows: at most ceil(R / 16) slabs (NSL;
+// five for kmc <= 32), so their offsets are fixed before the chunk loop.
+// The measured row (and the additive term) is loaded first and up to eight
+// chunks' loads are issued together: the kernel is one short dependency
+// chain per thread, so every load it can start at once is a round trip saved.
 constexpr int RED_SLABS = 5;
 
-template <class Args>
+// G chunks' partial rows, loaded together and added in chunk order.
+template <int G, int NSL>
+__device__ __forceinline__ float reduce_group(const float *pc, size_t cstride, int c, const size_t (&off)[NSL],
+                                              const bool (&ok)[NSL], float sum)
+{
+    float v[G][NSL];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+        const float *p = pc + (size_t)(c + u) * cstride;
+#pragma unroll
+        for (int i = 0; i < NSL; ++i) v[u][i] = p[off[i]];
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+#pragma unroll
+        for (int i = 0; i < NSL; ++i)
+            if (ok[i]) sum += v[u][i];
+    return sum;
+}
+
+template <int NSL, class Args>
 __device__ __forceinline__ void reduce_body(const Args &a, int blk, int al)
 {
     const int N = a.N, Nz = a.Nz;
@@ -886,66 +909,55 @@ __device__ __forceinline__ void reduce_body(const Args &a, int blk, int al)
     if (t >= N * Nz) return;
     const int ang = uniform(a.L.idx[al]);
     const int r = t / Nz, k = t % Nz;
+    const size_t o = ((size_t)ang * N + r) * Nz + k;
+    const size_t oc = ((size_t)al * N + r) * Nz + k;
+    const int mode = a.mode;
+    const float *const gd = a.g, *const sa = a.s_add;
+    float *const ev = a.e;
+    float gv = 0.f, sv = 0.f, ev3 = 0.f;
+    if (mode != 0) {
+        gv = gd[o];
+        if (mode == 3) ev3 = ev[oc];
+        else if (sa) sv = sa[o];
+    }
     const int R = SLAB + 2 * a.kmc;
     const int slo = max(0, (k + a.kmc - R + 4 * SLAB) / SLAB - 3);  // floor((k + kmc - R) / 16) + 1
     const int shi = min(a.nslab - 1, (k + a.kmc) / SLAB);
     const size_t cstride = (size_t)N * R;  // one chunk
     const float *pc = a.part + (size_t)al * a.nslab * a.nchunk * cstride + (size_t)r * R;
-    size_t off[RED_SLABS];
-    bool ok[RED_SLABS];
+    size_t off[NSL];
+    bool ok[NSL];
 #pragma unroll
-    for (int i = 0; i < RED_SLABS; ++i) {
+    for (int i = 0; i < NSL; ++i) {
         const int s = slo + i;
         ok[i] = s <= shi;
         off[i] = ok[i] ? (size_t)s * a.nchunk * cstride + (size_t)(k - s * SLAB + a.kmc) : 0;
     }
     float sum = 0.f;
-    // four chunks' loads in flight together (the sum keeps chunk order)
     const int nch = a.nchunk;
     int c = 0;
-    for (; c + 4 <= nch; c += 4) {
-        float v[4][RED_SLABS];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const float *p = pc + (size_t)(c + u) * cstride;
-#pragma unroll
-            for (int i = 0; i < RED_SLABS; ++i) v[u][i] = p[off[i]];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int i = 0; i < RED_SLABS; ++i)
-                if (ok[i]) sum += v[u][i];
+    for (; c + 8 <= nch; c += 8) sum = reduce_group<8, NSL>(pc, cstride, c, off, ok, sum);
+    if (c + 4 <= nch) {
+        sum = reduce_group<4, NSL>(pc, cstride, c, off, ok, sum);
+        c += 4;
     }
-    for (; c < nch; ++c) {
-        const float *p = pc + (size_t)c * cstride;
-        float v[RED_SLABS];
-#pragma unroll
-        for (int i = 0; i < RED_SLABS; ++i) v[i] = p[off[i]];
-#pragma unroll
-        for (int i = 0; i < RED_SLABS; ++i)
-            if (ok[i]) sum += v[i];
-    }
-    const size_t o = ((size_t)ang * N + r) * Nz + k;
-    const size_t oc = ((size_t)al * N + r) * Nz + k;
-    const int mode = a.mode;
-    float *const q = a.q, *const ev = a.e;
-    const float *const gd = a.g, *const sa = a.s_add;
+    for (; c < nch; ++c) sum = reduce_group<1, NSL>(pc, cstride, c, off, ok, sum);
+    float *const q = a.q;
     if (mode == 0) {
         a.proj[o] = sum;
     } else if (mode != 3) {
-        const float e = sa ? sum + sa[o] : sum;
-        q[oc] = e > 0.f ? gd[o] / e : 0.f;
+        const float e = sa ? sum + sv : sum;
+        q[oc] = e > 0.f ? gv / e : 0.f;
         if (mode == 2) ev[oc] = e;
     } else {
         // sum = (H v)_o for the gradient v of the ratio q = g / e; its
         // derivative in e is -g / e^2 where e > 0 and 0 elsewhere
-        const float e = ev[oc];
-        q[oc] = e > 0.f ? -sum * gd[o] / (e * e) : 0.f;
+        q[oc] = ev3 > 0.f ? -sum * gv / (ev3 * ev3) : 0.f;
     }
 }
 
-__global__ __launch_bounds__(256) void fwd_reduce(ReduceArgs a) { reduce_body(a, blockIdx.x, blockIdx.y); }
+template <int NSL>
+__global__ __launch_bounds__(256) void fwd_reduce(ReduceArgs a) { reduce_body<NSL>(a, blockIdx.x, blockIdx.y); }
 
 __global__ __launch_bounds__(256) void reduce_batch(BatchList<ReduceArgs> b)
 {
@@ -953,7 +965,7 @@ __global__ __launch_bounds__(256) void reduce_batch(BatchList<ReduceArgs> b)
     ConstMem<Task> *tasks = as_const(b.tasks);
     for (int t = blockIdx.x; t < b.ntasks; t += gridDim.x) {
         const int r = tasks[t].r, x = tasks[t].x, z = tasks[t].z;
-        reduce_body(args[r], x, z);
+        reduce_body<RED_SLABS>(args[r], x, z);
     }
 }
 
@@ -1326,6 +1338,7 @@ struct GatherArgs {
     float *fpad;         // modes 2, 3: also store the updated image here, columns zs floats apart
     int zs;
     int v4;              // Nz % 4 == 0 and every array 16-byte aligned: modes 0, 2, 3 use 16-byte accesses
+    int zshare;          // 1: every angle reads the one brick volume at z
 };
 
 // Transpose of the bilinear rotation, as a gather.  Workgroup = 8 x 8 object
@@ -1375,7 +1388,7 @@ __device__ __forceinline__ void gather_body(const Args &a, int tile, int pair, i
     const float xx = (float)x - c, yy = (float)y - c;
     const float fxv = (float)x, fyv = (float)y;
     float acc[NS][4] = {};
-    const size_t zstride = (size_t)a.nslab * N * N * SLAB;
+    const size_t zstride = a.zshare ? 0 : (size_t)a.nslab * N * N * SLAB;
     const float *zs = zb + (size_t)slab0 * N * N * SLAB;
     const int qoff = 16 * q;
     const uint32_t rowb = (uint32_t)N * SLAB * 4;  // bytes per rotated row i' (N <= 256: < 2^22)
@@ -1668,13 +1681,14 @@ __global__ __launch_bounds__(256) void back_gather(GatherArgs a)
 // a.L lists every angle, subset after subset (subset m holds the angles
 // m, m + M, ..., so its count is ceil((A - m) / M)); subset m's bricks follow
 // those of the subsets before it in a.z, and its result goes to
-// a.out + m * out_stride.
+// a.out + m * out_stride (with a.zshare, every angle's brick is the one at
+// a.z).
 template <int NS>
 __global__ __launch_bounds__(256) void back_gather_subsets(GatherArgs a, int M, size_t out_stride)
 {
     const int m = blockIdx.z, A = a.L.n;
     const int first = m * (A / M) + min(m, A % M), count = A / M + (m < A % M ? 1 : 0);
-    const size_t per = (size_t)a.nslab * a.g.N * a.g.N * SLAB;
+    const size_t per = a.zshare ? 0 : (size_t)a.nslab * a.g.N * a.g.N * SLAB;
     gather_body<NS>(a, blockIdx.x, blockIdx.y, first, count, a.z + (size_t)first * per,
                     a.out + (size_t)m * out_stride);
 }

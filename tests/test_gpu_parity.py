@@ -523,17 +523,22 @@ def test_attenuation_table_calls_match_the_oracle(n, nz, A, idx):
         plan.workspace_size(S.OP_OSEM, 2, 2)
 
 
-@pytest.mark.parametrize("n,nz,A,M", [(32, 24, 30, 4), (40, 20, 13, 13), (24, 16, 12, 1)])
-def test_reconstruction_without_attenuation_matches_per_subset_passes(n, nz, A, M):
+@pytest.mark.parametrize("n,nz,A,M,orbit", [(32, 24, 30, 4, False), (40, 20, 13, 13, False),
+                                             (24, 16, 12, 1, False), (32, 24, 30, 4, True)])
+def test_reconstruction_without_attenuation_matches_per_subset_passes(n, nz, A, M, orbit):
     """Without an attenuation map osem_reconstruct runs the sensitivity pass
     of every subset as one launch over all angles (subset after subset) and
-    the subsets' gathers as one launch; the sensitivities are the same values
-    as the per-subset passes of spect_sensitivity, formed in the same order,
-    so the reconstruction equals the stepwise driver's bitwise (uneven and
-    one-angle subsets, and a single subset, which takes the per-subset path).
-    Both meet the oracle's OSEM (Eq. 5)."""
+    the subsets' gathers as one launch; with one detector distance for every
+    angle (the same blur taps) the pass forms one angle's brick, which the
+    gathers read for every angle.  The sensitivities are the same values as
+    the per-subset passes of spect_sensitivity, formed in the same order, so
+    the reconstruction equals the stepwise driver's bitwise (uneven and
+    one-angle subsets, a single subset, which takes the per-subset path, and a
+    per-angle detector distance, which keeps a brick per angle).  Both meet
+    the oracle's OSEM (Eq. 5)."""
     r = np.random.default_rng(1977 + n + A)
-    og, plan = both(n, nz, A)
+    rad = list(0.5 * n * 0.48 + 2.0 + 1.5 * np.cos(np.arange(A) * 2 * np.pi / A) ** 2) if orbit else None
+    og, plan = both(n, nz, A, radius=rad)
     f = P.random_object(og.object_shape, r) + 0.5
     g = P.poisson_counts(O.forward(og, f.astype(np.float64), None), 1e5, r)
     gd = dev(g)
