@@ -747,7 +747,8 @@ bool gather_v4(const spect_plan *p, std::initializer_list<const void *> ptrs)
 // angles of the rotated-frame bricks z ([L][nslab][N][N][16]), combined into
 // out by `mode` (see GatherArgs).
 int launch_gather(const spect_plan *p, const AngleList &L, const float *z, int nslab, int mode, float *out,
-                  const float *sens, float *fpad, int zs, const BsremTerms *bt, const StepTerms *stt, hipStream_t st)
+                  const float *sens, float *fpad, int zs, const BsremTerms *bt, const StepTerms *stt, hipStream_t st,
+                  bool zshare = false)
 {
     GatherArgs gg{};
     gg.g = p->g;
@@ -762,6 +763,7 @@ int launch_gather(const spect_plan *p, const AngleList &L, const float *z, int n
     gg.v4 = gather_v4(p, {out, sens, fpad, bt ? bt->sens_all : nullptr, bt ? bt->prior : nullptr});
     gg.bt = bt ? *bt : BsremTerms{nullptr, nullptr, 0.f, 0.f};
     gg.st = stt ? *stt : StepTerms{nullptr, nullptr, nullptr};
+    gg.zshare = zshare ? 1 : 0;
     const int tiles = (p->N + GT - 1) / GT;
     {
         // one slab per workgroup when two would leave the device under-filled
@@ -1310,6 +1312,23 @@ int do_sens(const spect_plan *plan, const float *mu, float *sens, float *table, 
     if ((st = check_ws(ws, ws_bytes, back_ws(plan, (int)list.size(), att)))) return st;
     const bool vec = want_vec(plan, {mu});
     const int G = back_group(plan, (int)list.size());
+    if (att == ATT_NONE && plan->one_psf) {
+        // no attenuation and the same taps for every angle: one angle's brick
+        // of the constant projection serves every angle's gather
+        char *w = static_cast<char *>(ws);
+        const AngleList L1 = to_list(list.data(), 1);
+        if ((st = run_back(plan, nullptr, 0, 1, nullptr, ATT_NONE, nullptr, L1, w, ws_bytes, nullptr, 0, nullptr,
+                           nullptr, vec, T_BACK, s, nullptr, nullptr, nullptr, 0, false)))
+            return st;
+        const int nslab = tune(plan, 1, ATT_NONE, T_BACK).nslab;
+        for (size_t b = 0; b < list.size(); b += G) {
+            const int n = (int)std::min<size_t>(G, list.size() - b);
+            if ((st = launch_gather(plan, to_list(list.data() + b, n), reinterpret_cast<const float *>(w), nslab,
+                                    b == 0 ? 0 : 1, sens, nullptr, nullptr, 0, nullptr, nullptr, s, true)))
+                return st;
+        }
+        return ok();
+    }
     for (size_t b = 0; b < list.size(); b += G) {
         const int n = (int)std::min<size_t>(G, list.size() - b);
         const AngleList L = to_list(list.data() + b, n);
