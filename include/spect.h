@@ -404,6 +404,16 @@ int osem_reconstruct(const spect_plan *plan, float *f, const float *mu, const fl
                      const float *s_add, int32_t n_iters, int32_t n_subsets, void *ws,
                      size_t ws_bytes, void *stream);
 
+/* osem_reconstruct from the start image 1 everywhere (the usual choice for
+ * Eq. 5's iteration, Section 2.1.3): f is written, never read, so it may hold
+ * anything on entry.  The first sensitivity launch also sets f to 1 (no
+ * separate fill launch); the result equals osem_reconstruct's from an f of
+ * ones bitwise.  Arguments, workspace, errors and graph replay as
+ * osem_reconstruct (the two calls keep separate graphs). */
+int osem_reconstruct_ones(const spect_plan *plan, float *f, const float *mu, const float *g,
+                          const float *s_add, int32_t n_iters, int32_t n_subsets, void *ws,
+                          size_t ws_bytes, void *stream);
+
 /* BSREM with the relative difference prior (Section 2.1.3: Eq. 4 with the
  * Table 1 BSREM preconditioner C = f alpha^(n) / (c^(n) H^T 1), prior
  * weight beta^(n) = c^(n) beta, and the Table 1 RelativeDifferencePrior

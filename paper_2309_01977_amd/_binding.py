@@ -28,7 +28,7 @@ ATT_TABLE = 2   # with_mu code of the attenuation-table calls
 EXPORTS = ("spect_plan_create", "spect_plan_destroy", "spect_workspace_size", "spect_fwd", "spect_fwd_static",
            "spect_back", "spect_sensitivity", "spect_table_size", "spect_sensitivity_table",
            "spect_fwd_table", "spect_back_table", "osem_subset_step", "osem_list_step", "osem_list_step_vjp",
-           "osem_reconstruct",
+           "osem_reconstruct", "osem_reconstruct_ones",
            "spect_rdp_gradient", "bsrem_subset_step", "bsrem_reconstruct", "spect_batch_create",
            "spect_batch_destroy", "spect_batch_workspace_size", "osem_batch_reconstruct", "osem_batch_autotune",
            "spect_batch_schedule", "spect_batch_set_schedule", "spect_server_create", "spect_server_destroy",
@@ -81,6 +81,7 @@ def load_library(path: Optional[str] = None):
     lib.spect_back_table.argtypes = [vp, vp, vp, vp, i32p, i32, ctypes.c_int, vp, sz, vp]
     lib.osem_subset_step.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, vp, sz, vp]
     lib.osem_reconstruct.argtypes = [vp, vp, vp, vp, vp, i32, i32, vp, sz, vp]
+    lib.osem_reconstruct_ones.argtypes = [vp, vp, vp, vp, vp, i32, i32, vp, sz, vp]
     lib.osem_list_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i32p, i32, vp, sz, vp]
     lib.osem_list_step_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32p, i32, vp, vp, vp, sz, vp]
     f32 = ctypes.c_float
@@ -418,13 +419,17 @@ class KernelTimer:
 
 def _recon_method(self, g: torch.Tensor, n_iters: int, n_subsets: int,
                   mu: Optional[torch.Tensor] = None, s_add: Optional[torch.Tensor] = None,
-                  f: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """Whole OSEM reconstruction (osem_reconstruct); f holds the initial image
-    (1 everywhere if None) and receives the result."""
+                  f: Optional[torch.Tensor] = None, from_ones: bool = False) -> torch.Tensor:
+    """Whole OSEM reconstruction: f holds the initial image and receives the
+    result (osem_reconstruct); with from_ones, or when f is None, the start
+    image is 1 everywhere and f is only written (osem_reconstruct_ones)."""
     if f is None:
-        f = torch.ones(self.object_shape, dtype=torch.float32, device=g.device)
+        f = torch.empty(self.object_shape, dtype=torch.float32, device=g.device)
+        from_ones = True
     ws = self.workspace(OP_RECON, n_subsets, mu is not None)
-    _check(load_library().osem_reconstruct(
+    lib = load_library()
+    fn = lib.osem_reconstruct_ones if from_ones else lib.osem_reconstruct
+    _check(fn(
         self._h, _ptr(f, self.object_shape, "f"), _ptr(mu, self.object_shape, "mu"),
         _ptr(g, self.proj_shape, "g"), _ptr(s_add, self.proj_shape, "s_add"), int(n_iters),
         int(n_subsets), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))

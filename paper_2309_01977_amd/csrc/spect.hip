@@ -56,11 +56,12 @@ struct spect_plan {
         int iters, subsets, bsrem;
         float beta, gamma;
         std::vector<float> relax;
+        bool ones;  // the start image is written (1 everywhere), not read
         bool operator==(const GraphKey &o) const
         {
             return f == o.f && mu == o.mu && g == o.g && s_add == o.s_add && ws == o.ws && ws_bytes == o.ws_bytes &&
                    iters == o.iters && subsets == o.subsets && bsrem == o.bsrem && beta == o.beta &&
-                   gamma == o.gamma && relax == o.relax;
+                   gamma == o.gamma && relax == o.relax && ones == o.ones;
         }
     };
     struct CachedGraph {
@@ -816,7 +817,8 @@ int launch_gather_subsets(const spect_plan *p, const AngleList &La, const float 
 int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const float *mu, int att,
              float *table, const AngleList &L, char *ws, size_t ws_avail, const float *tau_given, int mode,
              float *out, const float *sens, bool vec, int which, hipStream_t st, const BsremTerms *bt = nullptr,
-             const StepTerms *stt = nullptr, float *fpad = nullptr, int zs = 0, bool do_gather = true)
+             const StepTerms *stt = nullptr, float *fpad = nullptr, int zs = 0, bool do_gather = true,
+             float *fill = nullptr)
 {
     const Tuning t = tune(p, L.n, att, which);
     if (back_need(p, L.n, att, which) > ws_avail)
@@ -836,7 +838,7 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
         }
     }
     float *z = reinterpret_cast<float *>(ws + off);
-    BackRotArgs b;
+    BackRotArgs b{};
     b.g = p->g;
     b.L = L;
     b.y = y;
@@ -854,6 +856,9 @@ int run_back(const spect_plan *p, const float *y, int y_compact, int ones, const
         // constant projection: the blur reduces to in-range tap sums, and the
         // pass walks every depth in one thread (no chunk offsets)
         const bool v2 = p->Nz % 2 == 0 && (mu == nullptr || aligned8(mu));
+        // the sensitivity launch may also write a start image of ones
+        b.fill = fill;
+        b.fill_n = fill ? (size_t)p->N * p->N * p->Nz : 0;
         BackFn sk = nullptr;
         if (att == ATT_WRITE) sk = v2 ? sens_line<ATT_WRITE, true> : sens_line<ATT_WRITE, false>;
         else if (att == ATT_SAMPLE) sk = v2 ? sens_line<ATT_SAMPLE, true> : sens_line<ATT_SAMPLE, false>;
@@ -1569,7 +1574,8 @@ bool finite_nonneg(float x) { return std::isfinite(x) && x >= 0.f; }
 // two volumes (all-angle sensitivity, prior gradient) for BSREM right after
 // the M sensitivities.
 int reconstruct(const spect_plan *plan, float *f, const float *mu, const float *g, const float *s_add,
-                int32_t n_iters, int32_t n_subsets, void *ws, size_t ws_bytes, void *stream, const BsremSpec *bs)
+                int32_t n_iters, int32_t n_subsets, void *ws, size_t ws_bytes, void *stream, const BsremSpec *bs,
+                bool from_ones = false)
 {
     int st;
     if ((st = check_plan(plan))) return st;
@@ -1593,7 +1599,10 @@ int reconstruct(const spect_plan *plan, float *f, const float *mu, const float *
     const size_t extra = bs ? 2 * vb : 0;
     if ((st = check_ws(ws, ws_bytes, recon_ws(plan, M, mu != nullptr) + extra))) return st;
     spect_plan::GraphKey key{f, mu, g, s_add, ws, ws_bytes, n_iters, n_subsets, bs ? (bs->relax ? 2 : 1) : 0,
-                             bs ? bs->beta : 0.f, bs ? bs->gamma : 0.f, {}};
+                             bs ? bs->beta : 0.f, bs ? bs->gamma : 0.f, {}, from_ones};
+    // from_ones: the first sensitivity launch also writes f = 1 (no launch
+    // reads f before it)
+    float *const fill = from_ones ? f : nullptr;
     if (bs && bs->relax) key.relax.assign(bs->relax, bs->relax + n_iters);
     auto launch_all = [&](hipStream_t s) -> int {
         const bool vec = want_vec(plan, {f, mu});
@@ -1632,7 +1641,7 @@ int reconstruct(const spect_plan *plan, float *f, const float *mu, const float *
             const AngleList La = to_list(all.data(), (int)all.size());
             const AngleList Lr = to_list(all.data(), sens_bricks(plan));
             if ((st = run_back(plan, nullptr, 0, 1, nullptr, ATT_NONE, nullptr, Lr, rest, avail, nullptr, 0, nullptr,
-                               nullptr, vec, T_BACK, s, nullptr, nullptr, nullptr, 0, false)))
+                               nullptr, vec, T_BACK, s, nullptr, nullptr, nullptr, 0, false, fill)))
                 return st;
             // the pass wrote one brick volume per listed angle at the start of
             // the scratch; subset m's are contiguous from its first angle,
@@ -1643,12 +1652,13 @@ int reconstruct(const spect_plan *plan, float *f, const float *mu, const float *
                 return st;
         }
         for (int m = 0; m < M && !combined_sens(plan, M, mu != nullptr); ++m) {
+            float *fl = m == 0 ? fill : nullptr;
             if (table)
                 st = run_back(plan, nullptr, 0, 1, mu, ATT_WRITE, per[m], lists[m], rest, avail, nullptr, 0, sens[m],
-                              nullptr, vec, T_BACK, s);
+                              nullptr, vec, T_BACK, s, nullptr, nullptr, nullptr, 0, true, fl);
             else
                 st = run_back(plan, nullptr, 0, 1, mu, att, nullptr, lists[m], rest, avail, per[m], 0, sens[m], nullptr,
-                              vec, T_BOTH, s);
+                              vec, T_BOTH, s, nullptr, nullptr, nullptr, 0, true, fl);
             if (st) return st;
         }
         if (bs && (st = launch_sum(plan, sens[0], vb / sizeof(float), M, sens_all, s))) return st;
@@ -1763,6 +1773,12 @@ int osem_reconstruct(const spect_plan *plan, float *f, const float *mu, const fl
                      int32_t n_iters, int32_t n_subsets, void *ws, size_t ws_bytes, void *stream)
 {
     return reconstruct(plan, f, mu, g, s_add, n_iters, n_subsets, ws, ws_bytes, stream, nullptr);
+}
+
+int osem_reconstruct_ones(const spect_plan *plan, float *f, const float *mu, const float *g, const float *s_add,
+                          int32_t n_iters, int32_t n_subsets, void *ws, size_t ws_bytes, void *stream)
+{
+    return reconstruct(plan, f, mu, g, s_add, n_iters, n_subsets, ws, ws_bytes, stream, nullptr, true);
 }
 
 int bsrem_reconstruct(const spect_plan *plan, float *f, const float *mu, const float *g, const float *s_add,

@@ -985,6 +985,8 @@ struct BackRotArgs {
     float *z;           // [L][nslab][N][N][SLAB] rotated-frame values
     int nslab, nchunk, cbset;
     int vec;
+    float *fill;        // sensitivity pass: also set fill[0 .. fill_n) to 1 (or nullptr)
+    size_t fill_n;
 };
 
 template <int ATT, int KMC, bool VEC, class Args>
@@ -1288,6 +1290,14 @@ __device__ __forceinline__ void sensl_walk(const Args &a, int jp, int rp, int sl
 template <int ATT, bool V2>
 __global__ __launch_bounds__(SL_THREADS) void sens_line(BackRotArgs a)
 {
+    if (a.fill) {
+        // a reconstruction's start image, 1 everywhere, written by the
+        // launch that precedes its first read
+        const size_t nt = (size_t)gridDim.x * gridDim.y * gridDim.z * SL_THREADS;
+        const size_t t0 = (((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * SL_THREADS +
+                          threadIdx.x;
+        for (size_t i = t0; i < a.fill_n; i += nt) a.fill[i] = 1.f;
+    }
     sensl_body<ATT, V2>(a, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 

@@ -24,13 +24,13 @@ def osem(plan: Plan, g: torch.Tensor, n_iters: int, n_subsets: int,
          mu: Optional[torch.Tensor] = None, s_add: Optional[torch.Tensor] = None,
          f0: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """OSEM from f0 (default: 1 everywhere) for n_iters x n_subsets
-    subiterations, as one library call (osem_reconstruct)."""
+    subiterations, as one library call (osem_reconstruct, or
+    osem_reconstruct_ones without f0: the library writes the start image)."""
     if out is None:
         out = torch.empty(plan.object_shape, dtype=torch.float32, device=g.device)
     if f0 is None:
-        out.fill_(1.0)
-    else:
-        out.copy_(f0)
+        return plan.reconstruct(g, n_iters, n_subsets, mu, s_add, f=out, from_ones=True)
+    out.copy_(f0)
     return plan.reconstruct(g, n_iters, n_subsets, mu, s_add, f=out)
 
 

@@ -144,3 +144,28 @@ def test_bsrem_replays_equal_eager_calls():
     for call in range(3):
         np.testing.assert_array_equal(host(run(relax2)), ref2, err_msg=f"relaxation 2, call {call}")
     plan.close()
+
+
+@pytest.mark.parametrize("shape,with_mu", [((40, 20, 24), False), ((40, 20, 24), True), ((24, 128, 12), True)])
+def test_reconstruct_from_ones_writes_its_start_image(shape, with_mu):
+    """osem_reconstruct_ones (the first sensitivity launch also writes f = 1)
+    equals osem_reconstruct from an image of ones bitwise, whatever f held on
+    entry (NaN here), eager and graph-replayed; with Nz = 128 the forward's
+    padded copy is made from the written image; zero iterations leave f = 1."""
+    n, nz, A = shape
+    og, mu, g = problem(500 + nz + with_mu, n, nz, A, 0.15 if with_mu else 0.0, 2e5)
+    plan = S.Plan(n, nz, A, 0.48, 0.03, 0.1)
+    gd = dev(g)
+    mud = dev(mu) if with_mu else None
+    f = torch.empty(og.object_shape, device="cuda")
+    ones = torch.ones(og.object_shape, device="cuda")
+    ref = host(S.osem(plan, gd, 2, 4, mud, f0=ones))
+    for call in range(4):
+        f.fill_(float("nan"))
+        got = host(plan.reconstruct(gd, 2, 4, mud, None, f=f, from_ones=True))
+        np.testing.assert_array_equal(got, ref, err_msg=f"call {call}")
+    say(f"  {shape} mu {with_mu}: 4 calls bitwise equal to the explicit start image")
+    f.fill_(float("nan"))
+    np.testing.assert_array_equal(host(plan.reconstruct(gd, 0, 4, mud, None, f=f, from_ones=True)),
+                                  np.ones(og.object_shape))
+    plan.close()
